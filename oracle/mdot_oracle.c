@@ -1,0 +1,680 @@
+/*
+ * mdot_oracle.c -- plain, slow, FP64 CPU reference of MDOT-PNCG.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library. The product (the HIP library under
+ * paper_2307_08507_amd/) never links, loads or calls it, and shares no code with it.
+ *
+ * What it computes follows "Efficient and Accurate Optimal Transport with Mirror
+ * Descent and Conjugate Gradients" (Kemertas, Jepson, Farahmand):
+ *   - entropy H and H_min ............................ Sec. 2 (Notation), Prop. 1.3
+ *   - Gibbs plan P_ij = exp(u_i + v_j - gamma C_ij) .. Sec. 2.1, eq. (lagrangian-closed-form)
+ *   - dual objective g(u,v) and its gradient ........ Sec. 2.1, eq. (sinkhorn-dual), eq. (hessian)
+ *   - two-sided LogSumExp (log r(P), log c(P)) ...... Alg. 2 (PNCG), initial LSE lines
+ *   - PNCG with the Sinkhorn direction, preconditioned
+ *     Hestenes-Stiefel beta and descent reset ........ Alg. 2, eq. (sinkhorn-direction), eq. (beta_PPR_OT)
+ *   - hybrid bisection/secant line search on the
+ *     approximate Wolfe conditions .................. App. B, eq. (approximate-wolfe), eq. (phiprime)
+ *   - log-domain Sinkhorn projector ................. Alg. 4
+ *   - MDOT annealing loop, entropy-aware tolerance,
+ *     variable smoothing, Taylor warm start ......... Alg. 1, Sec. 4.2, eq. (approx-znext)
+ *   - Round onto U(r,c) ............................. Alg. 3 (Altschuler et al.)
+ *   - gap certificate (not in the paper; the paper measures error against an exact
+ *     solver): the double c-transform of cost-unit potentials is dual-feasible, so by
+ *     weak LP duality it lower-bounds OT(r,c,C) for ANY potentials. Two potential sets
+ *     are tried and the larger bound kept: f = u/gamma, and the finite difference
+ *     f = (u^t - u^{t-1}) / (gamma^t - gamma^{t-1}) along the annealing path, which
+ *     removes the O(1/gamma) entropic offset of u/gamma (u ~ gamma f* + a).
+ *
+ * Conventions: gamma is the inverse temperature (the paper's convention), u, v are
+ * in nats, C is dense row-major n x n with entries in [0,1]. All arithmetic is FP64
+ * with libm exp/log; LSEs are two-pass (max, then sum of exp(x - max)) in ascending
+ * index order. Independent rows (or columns) may run on different OpenMP threads;
+ * that does not change any value.
+ *
+ * Readings where the paper is silent (also listed in the design doc):
+ *   - PNCG is called with tolerance eps_d/2 on the smoothed marginals (Alg. 1 L6).
+ *   - ||grad g||_1 = ||r(P) - r~||_1 + ||c(P) - c~||_1.
+ *   - smoothing weight eps_d/4 is clamped at 1/2.
+ *   - line search constants c1 = 0.1, c2 = 0.9 (Hager-Zhang defaults), first trial
+ *     alpha = previous accepted alpha in the stage (1 at stage start), expansion by
+ *     doubling until bracketed, secant guarded to the open bracket (midpoint
+ *     otherwise), trial cap; at the cap alpha_lo is accepted when positive.
+ *   - beta = 0 when its denominator is 0; no clipping.
+ *   - warm start from stage 1 to 2 uses z^0 = (log r~, log c~) at gamma^0 = 0, so
+ *     Delta gamma^0 = gamma_i; later steps use the actual (clipped) Delta gamma.
+ *   - Round: r(P)_i = 0 gives x_i = 1, c(F)_j = 0 gives y_j = 1, ||err_r||_1 = 0
+ *     gives G = F'.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_W_NOT_CONVERGED 1
+#define ORC_E_ARG (-1)
+#define ORC_E_NOMEM (-4)
+
+typedef struct {
+    double p;            /* tolerance exponent: eps_d = H_min / gamma^p        (Alg. 1) */
+    double q;            /* gamma growth factor per stage                       (Alg. 1) */
+    double gamma_i;      /* initial gamma                                       (Alg. 1) */
+    double gamma_f;      /* > 0: final gamma (the paper's input); 0: adaptive   (Alg. 1) */
+    double target_gap;   /* adaptive mode: stop when certified gap <= target */
+    double gamma_cap;    /* adaptive mode: largest gamma; 0 => 5 H_min / (2 target) (Remark 1) */
+    double ls_c1, ls_c2; /* approximate Wolfe constants                         (App. B) */
+    int32_t max_ls_trials;
+    int32_t max_pncg_iters;   /* per stage */
+    int64_t max_sweeps;       /* whole solve; 0 = unlimited */
+    int32_t projector;        /* 0 = PNCG (Alg. 2), 1 = Sinkhorn (Alg. 4) */
+    int32_t warm_start;       /* 1 = Taylor extrapolation eq. (approx-znext), 0 = copy */
+} orc_params;
+
+typedef struct {
+    double primal_cost;   /* <G, C> of the rounded plan (best over checked stages) */
+    double dual_bound;    /* best lower bound on OT */
+    double gap;           /* primal_cost - dual_bound */
+    double gamma_final;   /* gamma of the stage whose plan is reported */
+    double marg_err_l1;   /* ||r(G) - r||_1 + ||c(G) - c||_1 */
+    double grad_norm;     /* ||grad g||_1 on the smoothed marginals at the end */
+    int32_t stages;
+    int32_t status;
+    int64_t pncg_iters, ls_trials, sweeps, cg_resets, ls_failures;
+} orc_result;
+
+typedef struct {
+    double gamma, eps_d, smooth_w, grad_norm, ub, lb;
+    int64_t pncg_iters, ls_trials, sweeps, cg_resets;
+} orc_stage_log;
+
+void orc_default_params(orc_params* prm)
+{
+    prm->p = 1.5;
+    prm->q = pow(2.0, 1.0 / 3.0);
+    prm->gamma_i = 16.0;
+    prm->gamma_f = 0.0;
+    prm->target_gap = 1e-6;
+    prm->gamma_cap = 0.0;
+    prm->ls_c1 = 0.1;
+    prm->ls_c2 = 0.9;
+    prm->max_ls_trials = 50;
+    prm->max_pncg_iters = 100000;
+    prm->max_sweeps = 0;
+    prm->projector = 0;
+    prm->warm_start = 1;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Shannon entropy H(r) = -<r, log r> with 0 log 0 = 0 (Sec. 2, Notation). */
+double orc_entropy(int n, const double* r)
+{
+    double h = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (r[i] > 0.0) h -= r[i] * log(r[i]);
+    return h;
+}
+
+/* Two-sided LogSumExp of X_ij = u_i + v_j - gamma C_ij:
+ *   lr_i = log sum_j exp(X_ij) = log r(P)_i,   lc_j = log sum_i exp(X_ij) = log c(P)_j
+ * (Alg. 2, the lines that form log r(P) and log c(P); LSE_r, LSE_c as defined in Sec. 2). */
+void orc_lse2(int n, const double* C, const double* u, const double* v, double gamma,
+              double* lr, double* lc)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        const double* Ci = C + (size_t)i * n;
+        double m = -INFINITY;
+        for (int j = 0; j < n; ++j) {
+            double x = u[i] + v[j] - gamma * Ci[j];
+            if (x > m) m = x;
+        }
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += exp(u[i] + v[j] - gamma * Ci[j] - m);
+        lr[i] = m + log(s);
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        double m = -INFINITY;
+        for (int i = 0; i < n; ++i) {
+            double x = u[i] + v[j] - gamma * C[(size_t)i * n + j];
+            if (x > m) m = x;
+        }
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += exp(u[i] + v[j] - gamma * C[(size_t)i * n + j] - m);
+        lc[j] = m + log(s);
+    }
+}
+
+/* Row LSE only: lr_i = log sum_j exp(u_i + v_j - gamma C_ij) (Alg. 4). */
+static void lse_rows(int n, const double* C, const double* u, const double* v, double gamma, double* lr)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        const double* Ci = C + (size_t)i * n;
+        double m = -INFINITY;
+        for (int j = 0; j < n; ++j) {
+            double x = u[i] + v[j] - gamma * Ci[j];
+            if (x > m) m = x;
+        }
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += exp(u[i] + v[j] - gamma * Ci[j] - m);
+        lr[i] = m + log(s);
+    }
+}
+
+/* Column LSE only: lc_j = log sum_i exp(u_i + v_j - gamma C_ij) (Alg. 4). */
+static void lse_cols(int n, const double* C, const double* u, const double* v, double gamma, double* lc)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        double m = -INFINITY;
+        for (int i = 0; i < n; ++i) {
+            double x = u[i] + v[j] - gamma * C[(size_t)i * n + j];
+            if (x > m) m = x;
+        }
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += exp(u[i] + v[j] - gamma * C[(size_t)i * n + j] - m);
+        lc[j] = m + log(s);
+    }
+}
+
+/* Dual objective g(u,v; gamma, r, c) = sum_ij P_ij - <u,r> - <v,c> (Sec. 2.1, eq. (sinkhorn-dual)). */
+double orc_dual_objective(int n, const double* C, const double* u, const double* v, double gamma,
+                          const double* r, const double* c)
+{
+    double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) s += exp(u[i] + v[j] - gamma * C[(size_t)i * n + j]);
+    double ur = 0.0, vc = 0.0;
+    for (int i = 0; i < n; ++i) {
+        ur += u[i] * r[i];
+        vc += v[i] * c[i];
+    }
+    return s - ur - vc;
+}
+
+/* Gradient of g: (r(P) - r, c(P) - c) (Sec. 4.3, eq. (hessian)); written into g[0..2n). */
+static void gradient(int n, const double* lr, const double* lc, const double* rt, const double* ct, double* g)
+{
+    for (int i = 0; i < n; ++i) g[i] = exp(lr[i]) - rt[i];
+    for (int j = 0; j < n; ++j) g[n + j] = exp(lc[j]) - ct[j];
+}
+
+static double dot(int m, const double* a, const double* b)
+{
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) s += a[k] * b[k];
+    return s;
+}
+
+static double norm1(int m, const double* a)
+{
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) s += fabs(a[k]);
+    return s;
+}
+
+typedef struct {
+    int64_t pncg_iters, ls_trials, sweeps, cg_resets, ls_failures;
+} counters;
+
+static int budget_left(const orc_params* prm, const counters* cn)
+{
+    return prm->max_sweeps <= 0 || cn->sweeps < prm->max_sweeps;
+}
+
+/* phi'(alpha) = <p_u, r(P_alpha) - r~> + <p_v, c(P_alpha) - c~> (App. B, eq. (phiprime)). */
+static double phi_prime(int n, const double* lr, const double* lc, const double* rt, const double* ct,
+                        const double* p)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += p[i] * (exp(lr[i]) - rt[i]);
+    for (int j = 0; j < n; ++j) s += p[n + j] * (exp(lc[j]) - ct[j]);
+    return s;
+}
+
+/* Hybrid bisection/secant line search for the approximate Wolfe conditions
+ * (2 c1 - 1) phi'(0) >= phi'(alpha) >= c2 phi'(0)   (App. B, eq. (approximate-wolfe)).
+ * On return zt = z + alpha p and lr, lc hold the LSEs at the accepted alpha, so the
+ * next Sinkhorn direction needs no extra sweep (App. B).
+ * Returns 0 on acceptance, 1 when the trial cap hit and alpha_lo > 0 was taken,
+ * -1 when no step was found. */
+static int line_search(int n, const double* C, double gamma, const double* rt, const double* ct,
+                       const double* z, const double* p, double dphi0, double alpha0,
+                       const orc_params* prm, double* zt, double* lr, double* lc, double* alpha_out,
+                       counters* cn)
+{
+    const double c1 = prm->ls_c1, c2 = prm->ls_c2;
+    double alo = 0.0, dlo = dphi0, ahi = INFINITY, dhi = 0.0;
+    double a = alpha0;
+    for (int t = 0; t < prm->max_ls_trials && budget_left(prm, cn); ++t) {
+        for (int k = 0; k < 2 * n; ++k) zt[k] = z[k] + a * p[k];
+        orc_lse2(n, C, zt, zt + n, gamma, lr, lc);
+        cn->sweeps++;
+        cn->ls_trials++;
+        double d = phi_prime(n, lr, lc, rt, ct, p);
+        if ((2.0 * c1 - 1.0) * dphi0 >= d && d >= c2 * dphi0) {
+            *alpha_out = a;
+            return 0;
+        }
+        if (d < 0.0) { /* still descending steeply: the minimiser lies beyond a */
+            alo = a;
+            dlo = d;
+        } else { /* past the minimiser (NaN/inf also lands here) */
+            ahi = a;
+            dhi = d;
+        }
+        if (isinf(ahi)) {
+            a = 2.0 * a;
+        } else {
+            /* secant: zero of the linear interpolant of phi' between the bracket ends */
+            double asec = (alo * dhi - ahi * dlo) / (dhi - dlo);
+            double amid = 0.5 * (alo + ahi);
+            if (!(asec > alo && asec < ahi)) asec = amid;
+            a = 0.5 * asec + 0.5 * amid;
+        }
+    }
+    cn->ls_failures++;
+    if (alo > 0.0) {
+        for (int k = 0; k < 2 * n; ++k) zt[k] = z[k] + alo * p[k];
+        orc_lse2(n, C, zt, zt + n, gamma, lr, lc);
+        cn->sweeps++;
+        *alpha_out = alo;
+        return 1;
+    }
+    *alpha_out = 0.0;
+    return -1;
+}
+
+/* PNCG (Alg. 2): minimise g(., .; gamma, r~, c~) from z = (u, v) until ||grad g||_1 <= tol.
+ * z is updated in place. Returns ORC_OK or ORC_W_NOT_CONVERGED. */
+static int pncg(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
+                double* z, const orc_params* prm, counters* cn, double* gnorm_out)
+{
+    const int m = 2 * n;
+    double* lr = (double*)malloc(sizeof(double) * m); /* lr = log r(P), lr + n = log c(P) */
+    double* g = (double*)malloc(sizeof(double) * m);
+    double* gprev = (double*)malloc(sizeof(double) * m);
+    double* s = (double*)malloc(sizeof(double) * m);
+    double* p = (double*)malloc(sizeof(double) * m);
+    double* zt = (double*)malloc(sizeof(double) * m);
+    double* lrt = (double*)malloc(sizeof(double) * m);
+    double* logt = (double*)malloc(sizeof(double) * m);
+    int status = ORC_OK;
+    if (!lr || !g || !gprev || !s || !p || !zt || !lrt || !logt) {
+        status = ORC_E_NOMEM;
+        goto out;
+    }
+    for (int i = 0; i < n; ++i) {
+        logt[i] = log(rt[i]);
+        logt[n + i] = log(ct[i]);
+    }
+    /* initial log r(P), log c(P) and gradient */
+    orc_lse2(n, C, z, z + n, gamma, lr, lr + n);
+    cn->sweeps++;
+    gradient(n, lr, lr + n, rt, ct, g);
+    memset(p, 0, sizeof(double) * m);
+    double gnorm = norm1(m, g);
+    double beta = 0.0, alpha_prev = 1.0;
+    int64_t k = 1;
+    while (gnorm > tol) {
+        if (k > prm->max_pncg_iters || !budget_left(prm, cn)) {
+            status = ORC_W_NOT_CONVERGED;
+            break;
+        }
+        /* Sinkhorn direction s = (log r~ - log r(P), log c~ - log c(P)) (eq. (sinkhorn-direction)) */
+        for (int t = 0; t < m; ++t) s[t] = logt[t] - lr[t];
+        /* preconditioned Hestenes-Stiefel beta (eq. (beta_PPR_OT)); beta^(1) = 0, p^(0) = 0 */
+        if (k == 1) {
+            beta = 0.0;
+        } else {
+            double num = 0.0, den = 0.0;
+            for (int t = 0; t < m; ++t) {
+                double y = g[t] - gprev[t];
+                num += y * (-s[t]);
+                den += y * p[t];
+            }
+            beta = (den != 0.0) ? num / den : 0.0;
+        }
+        for (int t = 0; t < m; ++t) p[t] = s[t] + beta * p[t];
+        double dphi0 = dot(m, p, g);
+        if (dphi0 >= 0.0) { /* reset CG when p is not a descent direction (Alg. 2) */
+            memcpy(p, s, sizeof(double) * m);
+            dphi0 = dot(m, p, g);
+            if (k > 1) cn->cg_resets++;
+        }
+        if (!(dphi0 < 0.0)) { /* even s is not a descent direction: numerical floor */
+            status = ORC_W_NOT_CONVERGED;
+            break;
+        }
+        double alpha;
+        int ls = line_search(n, C, gamma, rt, ct, z, p, dphi0, alpha_prev, prm, zt, lrt, lrt + n,
+                             &alpha, cn);
+        if (ls < 0) {
+            status = ORC_W_NOT_CONVERGED;
+            break;
+        }
+        /* step: z <- z + alpha p; the accepted trial's LSEs become the new log r(P), log c(P) */
+        memcpy(gprev, g, sizeof(double) * m);
+        memcpy(z, zt, sizeof(double) * m);
+        memcpy(lr, lrt, sizeof(double) * m);
+        gradient(n, lr, lr + n, rt, ct, g);
+        gnorm = norm1(m, g);
+        alpha_prev = alpha;
+        cn->pncg_iters++;
+        ++k;
+    }
+    *gnorm_out = gnorm;
+out:
+    free(lr); free(g); free(gprev); free(s); free(p); free(zt); free(lrt); free(logt);
+    return status;
+}
+
+/* Log-domain Sinkhorn projector (Alg. 4): row scaling then column scaling until the row
+ * residual ||r~ - r(P)||_1 (the whole gradient, since c(P) = c~ after each column update)
+ * is at most tol. */
+static int sinkhorn(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
+                    double* z, const orc_params* prm, counters* cn, double* gnorm_out)
+{
+    double* u = z;
+    double* v = z + n;
+    double* lr = (double*)malloc(sizeof(double) * n);
+    double* lc = (double*)malloc(sizeof(double) * n);
+    if (!lr || !lc) {
+        free(lr); free(lc);
+        return ORC_E_NOMEM;
+    }
+    int status = ORC_OK;
+    lse_rows(n, C, u, v, gamma, lr);
+    cn->sweeps++;
+    double res = 0.0;
+    for (int i = 0; i < n; ++i) res += fabs(rt[i] - exp(lr[i]));
+    int64_t it = 0;
+    while (res > tol) {
+        if (it >= prm->max_pncg_iters || !budget_left(prm, cn)) {
+            status = ORC_W_NOT_CONVERGED;
+            break;
+        }
+        for (int i = 0; i < n; ++i) u[i] = u[i] + log(rt[i]) - lr[i];
+        /* v <- log c~ - LSE_c(u 1^T - gamma C): evaluate with the current v, then shift */
+        lse_cols(n, C, u, v, gamma, lc);
+        for (int j = 0; j < n; ++j) v[j] = v[j] + log(ct[j]) - lc[j];
+        lse_rows(n, C, u, v, gamma, lr);
+        cn->sweeps += 2;
+        res = 0.0;
+        for (int i = 0; i < n; ++i) res += fabs(rt[i] - exp(lr[i]));
+        cn->pncg_iters++;
+        ++it;
+    }
+    *gnorm_out = res;
+    free(lr); free(lc);
+    return status;
+}
+
+/* Round (Alg. 3, Altschuler et al.): project P onto U(r, c). G must hold n*n doubles. */
+void orc_round(int n, const double* P, const double* r, const double* c, double* G)
+{
+    double* x = (double*)malloc(sizeof(double) * n);
+    double* y = (double*)malloc(sizeof(double) * n);
+    double* cF = (double*)malloc(sizeof(double) * n);
+    double* er = (double*)malloc(sizeof(double) * n);
+    double* ec = (double*)malloc(sizeof(double) * n);
+    for (int i = 0; i < n; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < n; ++j) rs += P[(size_t)i * n + j];
+        x[i] = (rs > 0.0) ? fmin(r[i] / rs, 1.0) : 1.0; /* x = r / r(P) ^ 1 */
+    }
+    /* F = D(x) P; y = c / c(F) ^ 1 */
+    for (int j = 0; j < n; ++j) cF[j] = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) cF[j] += x[i] * P[(size_t)i * n + j];
+    for (int j = 0; j < n; ++j) y[j] = (cF[j] > 0.0) ? fmin(c[j] / cF[j], 1.0) : 1.0;
+    /* F' = F D(y) */
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) G[(size_t)i * n + j] = x[i] * P[(size_t)i * n + j] * y[j];
+    /* err_r = r - r(F'), err_c = c - c(F') */
+    for (int i = 0; i < n; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < n; ++j) rs += G[(size_t)i * n + j];
+        er[i] = r[i] - rs;
+    }
+    for (int j = 0; j < n; ++j) ec[j] = c[j];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) ec[j] -= G[(size_t)i * n + j];
+    double l1 = norm1(n, er);
+    /* G = F' + err_r err_c^T / ||err_r||_1 */
+    if (l1 > 0.0)
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) G[(size_t)i * n + j] += er[i] * ec[j] / l1;
+    free(x); free(y); free(cF); free(er); free(ec);
+}
+
+/* Lower bound on OT(r, c, C) from any cost-unit potentials (f, g): the double c-transform
+ *   g'_j = min_i (C_ij - f_i),  f'_i = min_j (C_ij - g'_j)
+ * is dual-feasible (f'_i + g'_j <= C_ij), so <f', r> + <g', c> <= OT by weak LP duality.
+ * Both orders (starting from f, and starting from g) are evaluated and the larger bound
+ * is returned. Not part of the paper; it certifies the gap the paper measures against an
+ * exact solver. */
+double orc_ctransform_bound(int n, const double* C, const double* f, const double* g, const double* r,
+                            const double* c)
+{
+    double* a = (double*)malloc(sizeof(double) * n);
+    double* b = (double*)malloc(sizeof(double) * n);
+    /* start from f */
+    for (int j = 0; j < n; ++j) {
+        double m = INFINITY;
+        for (int i = 0; i < n; ++i) m = fmin(m, C[(size_t)i * n + j] - f[i]);
+        b[j] = m;
+    }
+    for (int i = 0; i < n; ++i) {
+        double m = INFINITY;
+        for (int j = 0; j < n; ++j) m = fmin(m, C[(size_t)i * n + j] - b[j]);
+        a[i] = m;
+    }
+    double lb1 = dot(n, a, r) + dot(n, b, c);
+    /* start from g */
+    for (int i = 0; i < n; ++i) {
+        double m = INFINITY;
+        for (int j = 0; j < n; ++j) m = fmin(m, C[(size_t)i * n + j] - g[j]);
+        a[i] = m;
+    }
+    for (int j = 0; j < n; ++j) {
+        double m = INFINITY;
+        for (int i = 0; i < n; ++i) m = fmin(m, C[(size_t)i * n + j] - a[i]);
+        b[j] = m;
+    }
+    double lb2 = dot(n, a, r) + dot(n, b, c);
+    free(a); free(b);
+    return fmax(lb1, lb2);
+}
+
+/* Form P(u, v; gamma) (eq. (lagrangian-closed-form)), round it (Alg. 3), and evaluate
+ * UB = <G, C> and the marginal error of G. The lower bound is the larger double
+ * c-transform bound of f = u/gamma (g = v/gamma) and, when u_prev is given, of the
+ * finite difference f = (u - u_prev)/(gamma - gamma_prev), g likewise.
+ * G_out (n*n) may be NULL. Returns ORC_OK or ORC_E_NOMEM. */
+int orc_round_certify(int n, const double* C, const double* u, const double* v, double gamma,
+                      const double* u_prev, const double* v_prev, double gamma_prev,
+                      const double* r, const double* c, double* ub, double* lb, double* marg_err,
+                      double* G_out)
+{
+    size_t nn = (size_t)n * n;
+    double* P = (double*)malloc(sizeof(double) * nn);
+    double* G = G_out ? G_out : (double*)malloc(sizeof(double) * nn);
+    double* f = (double*)malloc(sizeof(double) * n);
+    double* g = (double*)malloc(sizeof(double) * n);
+    if (!P || !G || !f || !g) {
+        free(P); if (!G_out) free(G); free(f); free(g);
+        return ORC_E_NOMEM;
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) P[(size_t)i * n + j] = exp(u[i] + v[j] - gamma * C[(size_t)i * n + j]);
+    orc_round(n, P, r, c, G);
+    double s = 0.0;
+    for (size_t k = 0; k < nn; ++k) s += G[k] * C[k];
+    *ub = s;
+    double e = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < n; ++j) rs += G[(size_t)i * n + j];
+        e += fabs(rs - r[i]);
+    }
+    for (int j = 0; j < n; ++j) {
+        double cs = 0.0;
+        for (int i = 0; i < n; ++i) cs += G[(size_t)i * n + j];
+        e += fabs(cs - c[j]);
+    }
+    *marg_err = e;
+    for (int i = 0; i < n; ++i) {
+        f[i] = u[i] / gamma;
+        g[i] = v[i] / gamma;
+    }
+    double b = orc_ctransform_bound(n, C, f, g, r, c);
+    if (u_prev && v_prev && gamma > gamma_prev) {
+        for (int i = 0; i < n; ++i) {
+            f[i] = (u[i] - u_prev[i]) / (gamma - gamma_prev);
+            g[i] = (v[i] - v_prev[i]) / (gamma - gamma_prev);
+        }
+        b = fmax(b, orc_ctransform_bound(n, C, f, g, r, c));
+    }
+    *lb = b;
+    free(P); if (!G_out) free(G); free(f); free(g);
+    return ORC_OK;
+}
+
+/* KL projection at fixed gamma from z (PNCG or Sinkhorn), as called by Alg. 1 L6. */
+int orc_project(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
+                double* z, const orc_params* prm, int64_t* counts /* [5] or NULL */, double* gnorm)
+{
+    counters cn = {0, 0, 0, 0, 0};
+    int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm)
+                                 : pncg(n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm);
+    if (counts) {
+        counts[0] = cn.pncg_iters; counts[1] = cn.ls_trials; counts[2] = cn.sweeps;
+        counts[3] = cn.cg_resets; counts[4] = cn.ls_failures;
+    }
+    return st;
+}
+
+/* MDOT (Alg. 1). r, c on the simplex; C in [0,1]. u_out, v_out receive the potentials
+ * (nats) of the reported stage. With prm->gamma_f > 0 the paper's schedule is run to
+ * gamma_f and the final plan is rounded and certified once; with gamma_f == 0 the loop
+ * rounds and certifies after every stage and stops when the certified gap is at most
+ * target_gap, or at gamma_cap. log (capacity log_cap) receives one entry per stage. */
+int orc_mdot(int n, const double* C, const double* r, const double* c, const orc_params* prm,
+             double* u_out, double* v_out, orc_result* res, orc_stage_log* log_, int log_cap)
+{
+    if (n < 1 || !C || !r || !c || !prm || !res) return ORC_E_ARG;
+    memset(res, 0, sizeof(*res));
+    const int m = 2 * n;
+    const int adaptive = !(prm->gamma_f > 0.0);
+    const double hmin = fmin(orc_entropy(n, r), orc_entropy(n, c)); /* H_min (Prop. 1.3) */
+    double gf;
+    if (!adaptive) gf = prm->gamma_f;
+    else gf = prm->gamma_cap > 0.0 ? prm->gamma_cap : 5.0 * hmin / (2.0 * prm->target_gap); /* Remark 1 */
+
+    double* z = (double*)malloc(sizeof(double) * m);      /* current (u, v) */
+    double* zprev = (double*)malloc(sizeof(double) * m);  /* solution at the previous gamma */
+    double* zbest = (double*)malloc(sizeof(double) * m);
+    double* rt = (double*)malloc(sizeof(double) * n);
+    double* ct = (double*)malloc(sizeof(double) * n);
+    if (!z || !zprev || !zbest || !rt || !ct) {
+        free(z); free(zprev); free(zbest); free(rt); free(ct);
+        return ORC_E_NOMEM;
+    }
+    counters tot = {0, 0, 0, 0, 0};
+    double gamma = fmin(prm->gamma_i, gf); /* Alg. 1: gamma <- min(gamma_i, gamma_f) */
+    double gamma_prev = 0.0;               /* gamma^0 = 0 (Prop. 1) */
+    double best_ub = INFINITY, best_lb = -INFINITY, best_gamma = gamma, best_me = 0.0, gnorm = 0.0;
+    int status = ORC_OK, t = 1;
+    for (;;) {
+        double eps_d = hmin / pow(gamma, prm->p); /* entropy-aware tolerance (Alg. 1) */
+        double w = fmin(eps_d / 4.0, 0.5);        /* variable smoothing weight (Alg. 1) */
+        for (int i = 0; i < n; ++i) {
+            rt[i] = (1.0 - w) * r[i] + w / n;
+            ct[i] = (1.0 - w) * c[i] + w / n;
+        }
+        if (t == 1) { /* rank-1 initial guess (Alg. 1); also z^0 for the first warm start */
+            for (int i = 0; i < n; ++i) {
+                z[i] = log(rt[i]);
+                z[n + i] = log(ct[i]);
+            }
+            memcpy(zprev, z, sizeof(double) * m);
+        }
+        counters cn = {0, 0, 0, 0, 0};
+        int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, eps_d / 2.0, z, prm, &cn, &gnorm)
+                                     : pncg(n, C, gamma, rt, ct, eps_d / 2.0, z, prm, &cn, &gnorm);
+        if (st < 0) { status = st; break; }
+        if (st == ORC_W_NOT_CONVERGED) status = ORC_W_NOT_CONVERGED;
+        tot.pncg_iters += cn.pncg_iters; tot.ls_trials += cn.ls_trials; tot.sweeps += cn.sweeps;
+        tot.cg_resets += cn.cg_resets; tot.ls_failures += cn.ls_failures;
+        double ub = NAN, lb = NAN;
+        int last = (gamma >= gf);
+        if (adaptive || last) {
+            double me;
+            int rc = orc_round_certify(n, C, z, z + n, gamma, zprev, zprev + n, gamma_prev, r, c, &ub,
+                                       &lb, &me, NULL);
+            if (rc != ORC_OK) { status = rc; break; }
+            if (ub < best_ub) {
+                best_ub = ub; best_gamma = gamma; best_me = me;
+                memcpy(zbest, z, sizeof(double) * m);
+            }
+            if (lb > best_lb) best_lb = lb;
+        }
+        if (log_ && t - 1 < log_cap) {
+            orc_stage_log* L = &log_[t - 1];
+            L->gamma = gamma; L->eps_d = eps_d; L->smooth_w = w; L->grad_norm = gnorm; L->ub = ub; L->lb = lb;
+            L->pncg_iters = cn.pncg_iters; L->ls_trials = cn.ls_trials; L->sweeps = cn.sweeps;
+            L->cg_resets = cn.cg_resets;
+        }
+        res->stages = t;
+        if (adaptive && best_ub - best_lb <= prm->target_gap) break;
+        if (last) {
+            if (adaptive) status = ORC_W_NOT_CONVERGED; /* gamma cap reached above target */
+            break;
+        }
+        if (!budget_left(prm, &tot)) { status = ORC_W_NOT_CONVERGED; break; }
+        /* Alg. 1: Delta gamma <- (q-1) gamma, gamma <- min(gamma + Delta gamma, gamma_f) */
+        double gnew = fmin(gamma + (prm->q - 1.0) * gamma, gf);
+        double dg = gnew - gamma, dg_prev = gamma - gamma_prev;
+        /* warm start, eq. (approx-znext): z' = z^t + (dg^t / dg^{t-1}) (z^t - z^{t-1}) */
+        double ratio = prm->warm_start ? dg / dg_prev : 0.0;
+        for (int k = 0; k < m; ++k) {
+            double zt = z[k];
+            z[k] = zt + ratio * (zt - zprev[k]);
+            zprev[k] = zt;
+        }
+        gamma_prev = gamma;
+        gamma = gnew;
+        ++t;
+    }
+    res->primal_cost = best_ub;
+    res->dual_bound = best_lb;
+    res->gap = best_ub - best_lb;
+    res->gamma_final = best_gamma;
+    res->marg_err_l1 = best_me;
+    res->grad_norm = gnorm;
+    res->status = status;
+    res->pncg_iters = tot.pncg_iters; res->ls_trials = tot.ls_trials; res->sweeps = tot.sweeps;
+    res->cg_resets = tot.cg_resets; res->ls_failures = tot.ls_failures;
+    if (u_out && v_out && isfinite(best_ub)) {
+        memcpy(u_out, zbest, sizeof(double) * n);
+        memcpy(v_out, zbest + n, sizeof(double) * n);
+    }
+    free(z); free(zprev); free(zbest); free(rt); free(ct);
+    return status;
+}
