@@ -1,0 +1,169 @@
+/*
+ * mdot.h -- C ABI of the MI355X MDOT-PNCG optimal-transport library (libmdot.so).
+ *
+ * The library solves the discrete optimal transport problem
+ *     OT(r, c, C) = min { <P, C> : P >= 0, P 1 = r, P^T 1 = c }
+ * for a square cost C in [0,1]^{n x n} and marginals r, c on the simplex (paper Sec. 2.1),
+ * with MDOT (Alg. 1: gamma annealing read as mirror descent, entropy-aware tolerance,
+ * variable marginal smoothing, Taylor warm start eq. (approx-znext)), the PNCG projector
+ * (Alg. 2 with the Sinkhorn direction eq. (sinkhorn-direction), the preconditioned
+ * Hestenes-Stiefel beta eq. (beta_PPR_OT) and the App. B hybrid line search on the
+ * approximate Wolfe conditions eq. (approximate-wolfe)), and the Round step (Alg. 3).
+ *
+ * Notation: gamma is the inverse temperature, P_ij = exp(u_i + v_j - gamma C_ij)
+ * (eq. (lagrangian-closed-form)); u, v are potentials in nats. Cost-unit potentials are
+ * f = u / gamma, g = v / gamma.
+ *
+ * Certified gap: every solve reports UB = <G, C> for the rounded plan G in U(r, c) and a
+ * lower bound LB <= OT(r, c, C) obtained from the double c-transform of cost-unit
+ * potentials (dual feasible, so weak LP duality applies). The potentials tried are u/gamma
+ * and the finite difference (u^t - u^{t-1}) / (gamma^t - gamma^{t-1}) along the annealing
+ * path. gap = UB - LB >= UB - OT. The lower bound is not part of the paper, which measures
+ * error against an exact CPU solver.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked "device" are HIP device pointers on the context's device; the caller
+ *     owns them. The library keeps no pointer after a synchronous call returns.
+ *   - Calls are issued on the context's HIP stream. Synchronous calls return after the
+ *     stream work they queued has completed.
+ *   - Return value: 0 (MDOT_OK) on success; < 0 on error, in which case outputs are left
+ *     untouched and mdot_last_error() describes the failure; > 0 is a warning with valid
+ *     outputs (MDOT_W_NOT_CONVERGED: the budget or gamma cap was hit with gap > target;
+ *     MDOT_W_RANGE: a sweep input put some row or column outside the exponent range the
+ *     kernel can represent, see mdot_lse2).
+ *   - One host thread per context.
+ */
+#ifndef MDOT_H
+#define MDOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MDOT_OK = 0,
+    MDOT_W_NOT_CONVERGED = 1,
+    MDOT_W_RANGE = 2,
+    MDOT_E_ARG = -1,      /* bad size, NULL pointer, bad enum or parameter */
+    MDOT_E_MARGINAL = -2, /* r or c negative, non-finite, or |sum - 1| > 1e-9 n */
+    MDOT_E_COST = -3,     /* scaled cost outside [0, 1] or non-finite */
+    MDOT_E_NOMEM = -4,    /* device allocation failed, or the request exceeds the HBM budget */
+    MDOT_E_DEVICE = -5,   /* a HIP call failed */
+    MDOT_E_BUSY = -6      /* no free serving slot */
+};
+
+/* How C is given. DENSE: data is an n*n row-major array of dtype. POINTS_*: data holds
+ * X (n*d FP32, row-major) followed by Y (n*d FP32); C_ij = scale * dist(x_i, y_j), computed
+ * on the fly in FP64 inside the sweep (paper Sec. 3: O(n) memory when entries of C can be
+ * computed in O(1)). */
+typedef enum { MDOT_COST_DENSE = 0, MDOT_COST_POINTS_SQEUCLID = 1, MDOT_COST_POINTS_L1 = 2 } mdot_cost_kind;
+typedef enum { MDOT_DT_F64 = 0, MDOT_DT_F32 = 1, MDOT_DT_F16 = 2, MDOT_DT_BF16 = 3 } mdot_dtype;
+
+/* Arithmetic of the O(n^2) sweeps. F64: FP64 exponent arguments, FP64 exp and sums.
+ * F32: FP64 exponent arguments, hardware FP32 exp2, FP32 partial sums of <= 4 terms,
+ * FP64 everything else (dual objective, marginals, dot products, line search, gap
+ * certificate); rows or columns whose shifted sums fall outside the FP32 range are
+ * re-evaluated in F64. Round and certificate sweeps always accumulate in FP64. */
+typedef enum { MDOT_PREC_F64 = 0, MDOT_PREC_F32 = 1 } mdot_precision;
+
+typedef struct {
+    int32_t n;            /* problem size, >= 1 */
+    int32_t d;            /* point dimension for POINTS_* (1..3), ignored for DENSE */
+    mdot_cost_kind kind;
+    mdot_dtype dtype;     /* DENSE only: element type of data (POINTS_* use FP32 coordinates) */
+    const void* data;     /* device */
+    double scale;         /* C = scale * raw; > 0. For POINTS_*, 0 means 1 / max_ij raw. */
+} mdot_cost_desc;
+
+typedef struct {
+    double p;             /* eps_d = H_min / gamma^p (Alg. 1); paper: 1.5 */
+    double q;             /* gamma_{t+1} = q gamma_t (Alg. 1); paper: 2^(1/3) */
+    double gamma_i;       /* first gamma (Alg. 1); paper: 2^4 */
+    double gamma_f;       /* > 0: run the paper's schedule to gamma_f, round and certify once.
+                             0: adaptive, certify after every stage, stop at gap <= target */
+    double gamma_cap;     /* adaptive cap; 0 => 5 H_min / (2 target) (Remark 1) */
+    double ls_c1, ls_c2;  /* approximate Wolfe constants; the paper leaves them open,
+                             defaults 0.1 and 0.9 (Hager-Zhang) */
+    int32_t max_ls_trials;    /* per line search (default 50) */
+    int32_t max_pncg_iters;   /* per stage (default 100000) */
+    int64_t max_sweeps;       /* LSE sweeps per solve, 0 = unlimited */
+    mdot_precision precision; /* default MDOT_PREC_F32 */
+    int32_t warm_start;       /* 1: Taylor warm start eq. (approx-znext); 0: reuse z^t */
+} mdot_params;
+
+typedef struct {
+    double primal_cost;   /* UB = <G, C>, G = Round(P) in U(r, c) (Alg. 3), best over checked stages */
+    double dual_bound;    /* LB <= OT(r, c, C), best over checked stages */
+    double gap;           /* UB - LB */
+    double gamma_final;   /* gamma of the stage whose plan gave UB (potentials returned for it) */
+    double marg_err_l1;   /* rounding-error estimate of ||r(G) - r||_1 + ||c(G) - c||_1 */
+    double grad_norm;     /* ||grad g||_1 on the smoothed marginals when the solve stopped */
+    double seconds;       /* device time of the solve (HIP events) */
+    int32_t stages;
+    int32_t status;       /* same value the call returns */
+    int64_t pncg_iters, ls_trials, sweeps, cg_resets, ls_failures;
+    int64_t fp64_retries; /* F32 sweeps re-run in F64 because of range */
+    int64_t cert_sweeps;  /* Round/certificate sweeps */
+} mdot_result;
+
+typedef struct mdot_ctx mdot_ctx;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream` (a hipStream_t,
+ * NULL = the default stream). hbm_budget_bytes bounds the workspace the context may hold
+ * (0 = no bound). Returns MDOT_OK, MDOT_E_ARG or MDOT_E_DEVICE. */
+int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_ctx** out);
+
+/* Free the context and its workspace. NULL is accepted. */
+int mdot_ctx_destroy(mdot_ctx* ctx);
+
+/* Fill *out with the defaults (paper Sec. 5.2: p = 1.5, q = 2^(1/3), gamma_i = 2^4;
+ * adaptive mode, F32 sweeps). */
+void mdot_default_params(mdot_params* out);
+
+/* Solve OT(r, c, C) to a certified gap <= target_gap (adaptive mode), or run the paper's
+ * schedule to params->gamma_f (schedule mode).
+ *   cost       : cost descriptor (device data)
+ *   r, c       : device FP64[n], on the simplex: non-negative, finite, |sum - 1| <= 1e-9 n
+ *   target_gap : > 0 in adaptive mode (ignored in schedule mode)
+ *   params     : NULL = mdot_default_params()
+ *   u_out,v_out: device FP64[n] or NULL: potentials (nats) of the reported stage, gauge
+ *                fixed so that sum(u) = sum(v)
+ *   res        : host, required
+ * Synchronous. Returns MDOT_OK, MDOT_W_NOT_CONVERGED or an error. */
+int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c,
+               double target_gap, const mdot_params* params, double* u_out, double* v_out,
+               mdot_result* res);
+
+/* One fused two-sided LogSumExp sweep (Alg. 2, the lines forming log r(P) and log c(P)):
+ *   lr_i = log sum_j exp(u_i + v_j - gamma C_ij),   lc_j = log sum_i exp(u_i + v_j - gamma C_ij)
+ * in one pass over C. u, v: device FP64[n]; lr_out, lc_out: device FP64[n].
+ * shift: device FP64[n] prediction of lr used as the per-row exponent shift, or NULL, in
+ * which case the library first runs a row-max pass. Columns are exact to FP32/FP64 range
+ * when their log-sum lies within ~60 (F32) / ~700 (F64) nats of the largest row shift of
+ * each 64-row tile; otherwise MDOT_W_RANGE is returned (values then may be -inf).
+ * precision: MDOT_PREC_F32 or MDOT_PREC_F64. Synchronous. */
+int mdot_lse2(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
+              const double* shift, mdot_precision precision, double* lr_out, double* lc_out);
+
+/* Round (Alg. 3) and certify the plan P(u, v; gamma) without materialising it: two sweeps
+ * give UB = <G, C> with G = Round(P, r, c), and LB = the larger double c-transform bound of
+ * (u/gamma, v/gamma) and, when u_prev/v_prev are non-NULL, of
+ * ((u - u_prev)/(gamma - gamma_prev), (v - v_prev)/(gamma - gamma_prev)).
+ * u, v, u_prev, v_prev, r, c: device FP64[n]. ub, lb, marg_err: host. Synchronous. */
+int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v,
+                       double gamma, const double* u_prev, const double* v_prev, double gamma_prev,
+                       const double* r, const double* c, double* ub, double* lb, double* marg_err);
+
+/* Text of the last error on this context (never NULL). */
+const char* mdot_last_error(const mdot_ctx* ctx);
+
+/* Library version string. */
+const char* mdot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDOT_H */

@@ -1,0 +1,558 @@
+// C ABI of libmdot (include/mdot.h): context, workspace, intake validation and the host
+// side of the solve loop. All solver decisions are taken on the device (mdot_kernels.hip);
+// the host replays a captured graph of solver steps and polls a done flag once per chunk,
+// keeping two chunks in flight so the GPU never waits for the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mdot_internal.h"
+
+using namespace mdot;
+
+namespace {
+
+constexpr int kChunk = 32;          // solver steps per graph launch (even: the state slot alternates)
+constexpr int kMaxN = 65536;        // column finalizer keeps n / 64 tile shifts in LDS
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct mdot_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    std::string err;
+    // workspace for the current capacity
+    int cap_n = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    Work host_work{};
+    Work* d_work = nullptr;
+    State* h_state = nullptr;     // pinned
+    int* h_done = nullptr;        // pinned, two slots
+    double* h_scratch = nullptr;  // pinned, intake results
+    double* d_scratch = nullptr;  // device, intake results / cost range partials
+    size_t scratch_doubles = 0;
+    DevParams* d_prm = nullptr;
+    DevParams* h_prm = nullptr;   // pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    // captured chunk of solver steps for the current n
+    hipGraphExec_t graph = nullptr;
+    int graph_n = 0;
+};
+
+static int fail(mdot_ctx* ctx, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, MDOT_E_DEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                      \
+    } while (0)
+
+static inline int tiles_r(int n) { return (n + kBR - 1) / kBR; }
+static inline int tiles_c(int n) { return (n + kBC - 1) / kBC; }
+
+// Bytes of workspace for size n (see Work in mdot_internal.h).
+static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
+{
+    const size_t nrt = tiles_r(n), nct = tiles_c(n), N = n;
+    const size_t counts[] = {
+        2 * N, 2 * N, 2 * N, 2 * N, 2 * N, 2 * N, 2 * N, 2 * N, 2 * N,  // rt logt z zprev zbest p g lz lzt
+        N, N, N,                                                      // xr yc errc
+        2 * N, 2 * N,                                                 // gp fpp
+        nct * N, nrt * N, nct * N, nct * N,                           // rowpart colpart rowpart2 rowpart3
+        2 * nct * N, 2 * nrt * N,                                     // rowmin colmin
+        nrt, (nrt + nct) * kNDot,                                     // tshift bdots
+    };
+    size_t off = 0;
+    const int k = sizeof(counts) / sizeof(counts[0]);
+    for (int i = 0; i < k; ++i) {
+        if (out_offsets) out_offsets[i] = off;
+        off += ((counts[i] * sizeof(double) + 255) / 256) * 256;
+    }
+    if (out_offsets) out_offsets[k] = off;  // counters
+    off += ((nrt + nct + 1) * sizeof(uint32_t) + 255) / 256 * 256;
+    return off;
+}
+
+static int ensure_workspace(mdot_ctx* ctx, int n)
+{
+    if (n <= ctx->cap_n && ctx->ws) return MDOT_OK;
+    size_t need = workspace_bytes(n);
+    if (ctx->budget && need > ctx->budget)
+        return fail(ctx, MDOT_E_NOMEM, "workspace for n=%d needs %zu bytes > budget %zu", n, need, ctx->budget);
+    if (ctx->ws) {
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+    }
+    if (ctx->graph) {
+        (void)hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+        ctx->graph_n = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->ws, need);
+    if (e != hipSuccess) {
+        ctx->ws = nullptr;
+        ctx->cap_n = 0;
+        return fail(ctx, MDOT_E_NOMEM, "hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
+    }
+    ctx->ws_bytes = need;
+    ctx->cap_n = n;
+    HIPCHK(ctx, hipMemsetAsync(ctx->ws, 0, need, ctx->stream));
+    const size_t scr = std::max<size_t>(64, 2 * (size_t)tiles_r(n) * tiles_c(n));
+    if (scr > ctx->scratch_doubles) {
+        if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+        if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
+        ctx->d_scratch = nullptr;
+        ctx->h_scratch = nullptr;
+        HIPCHK(ctx, hipMalloc(&ctx->d_scratch, scr * sizeof(double)));
+        HIPCHK(ctx, hipHostMalloc(&ctx->h_scratch, scr * sizeof(double), hipHostMallocDefault));
+        ctx->scratch_doubles = scr;
+    }
+    return MDOT_OK;
+}
+
+// Lay the Work struct out over the workspace for size n (n <= cap_n) and upload it.
+static int bind_work(mdot_ctx* ctx, int n, const mdot_cost_desc* cost, double scale, const double* r,
+                     const double* c)
+{
+    size_t off[32];
+    workspace_bytes(n, off);
+    char* b = (char*)ctx->ws;
+    Work& w = ctx->host_work;
+    memset(&w, 0, sizeof w);
+    w.n = n;
+    w.nrt = tiles_r(n);
+    w.nct = tiles_c(n);
+    w.cost_kind = cost ? cost->kind : MDOT_COST_DENSE;
+    w.dtype = cost ? cost->dtype : MDOT_DT_F32;
+    w.d = cost ? cost->d : 0;
+    w.cost = cost ? cost->data : nullptr;
+    w.scale = scale;
+    w.r = r;
+    w.c = c;
+    double** vec[] = {&w.rt, &w.logt, &w.z, &w.zprev, &w.zbest, &w.p, &w.g, &w.lz, &w.lzt, &w.xr, &w.yc,
+                      &w.errc, &w.gp, &w.fpp, &w.rowpart, &w.colpart, &w.rowpart2, &w.rowpart3, &w.rowmin,
+                      &w.colmin, &w.tshift, &w.bdots};
+    const int k = sizeof(vec) / sizeof(vec[0]);
+    for (int i = 0; i < k; ++i) *vec[i] = (double*)(b + off[i]);
+    w.cnt = (uint32_t*)(b + off[k]);
+    w.st = (State*)((char*)ctx->d_work + sizeof(Work));
+    w.prm = ctx->d_prm;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_work, &w, sizeof w, hipMemcpyHostToDevice, ctx->stream));
+    return MDOT_OK;
+}
+
+static void fill_defaults(mdot_params* p)
+{
+    p->p = 1.5;
+    p->q = std::pow(2.0, 1.0 / 3.0);
+    p->gamma_i = 16.0;
+    p->gamma_f = 0.0;
+    p->gamma_cap = 0.0;
+    p->ls_c1 = 0.1;
+    p->ls_c2 = 0.9;
+    p->max_ls_trials = 50;
+    p->max_pncg_iters = 100000;
+    p->max_sweeps = 0;
+    p->precision = MDOT_PREC_F32;
+    p->warm_start = 1;
+}
+
+static int check_cost_desc(mdot_ctx* ctx, const mdot_cost_desc* cost)
+{
+    if (!cost || !cost->data) return fail(ctx, MDOT_E_ARG, "cost descriptor or its data is NULL");
+    if (cost->n < 1 || cost->n > kMaxN) return fail(ctx, MDOT_E_ARG, "n=%d outside [1, %d]", cost->n, kMaxN);
+    if (cost->kind != MDOT_COST_DENSE && cost->kind != MDOT_COST_POINTS_SQEUCLID && cost->kind != MDOT_COST_POINTS_L1)
+        return fail(ctx, MDOT_E_ARG, "unknown cost kind %d", (int)cost->kind);
+    if (cost->kind == MDOT_COST_DENSE && (cost->dtype < MDOT_DT_F64 || cost->dtype > MDOT_DT_BF16))
+        return fail(ctx, MDOT_E_ARG, "unknown dtype %d", (int)cost->dtype);
+    if (cost->kind != MDOT_COST_DENSE && (cost->d < 1 || cost->d > 3))
+        return fail(ctx, MDOT_E_ARG, "point dimension d=%d outside [1, 3]", cost->d);
+    if (!(cost->scale >= 0.0) || !std::isfinite(cost->scale) || (cost->kind == MDOT_COST_DENSE && cost->scale == 0.0))
+        return fail(ctx, MDOT_E_ARG, "bad cost scale %g", cost->scale);
+    return MDOT_OK;
+}
+
+// Range of the raw cost (one pass) -> resolved scale; MDOT_E_COST if scale*raw leaves [0,1].
+static int resolve_scale(mdot_ctx* ctx, const mdot_cost_desc* cost, double* scale_out)
+{
+    const int n = cost->n;
+    const int tiles = tiles_r(n) * tiles_c(n);
+    if (launch_cost_range(ctx->d_work, tiles, ctx->d_scratch, ctx->stream))
+        return fail(ctx, MDOT_E_DEVICE, "cost range kernel launch failed");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 2 * tiles * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double lo = INFINITY, hi = -INFINITY;
+    bool nonfinite = false;
+    for (int t = 0; t < tiles; ++t) {
+        lo = std::min(lo, ctx->h_scratch[2 * t]);
+        double h = ctx->h_scratch[2 * t + 1];
+        if (std::isnan(h)) nonfinite = true;
+        else hi = std::max(hi, h);
+    }
+    if (nonfinite || !std::isfinite(lo)) return fail(ctx, MDOT_E_COST, "cost has non-finite entries");
+    double scale = cost->scale;
+    if (cost->kind != MDOT_COST_DENSE && scale == 0.0) scale = hi > 0.0 ? 1.0 / hi : 1.0;
+    const double slack = 1e-12;
+    if (scale * lo < -slack || scale * hi > 1.0 + slack)
+        return fail(ctx, MDOT_E_COST, "scaled cost range [%g, %g] is outside [0, 1]", scale * lo, scale * hi);
+    *scale_out = scale;
+    return MDOT_OK;
+}
+
+static int intake_marginals(mdot_ctx* ctx, int n, double* hmin)
+{
+    if (launch_intake(ctx->d_work, ctx->d_scratch, ctx->stream))
+        return fail(ctx, MDOT_E_DEVICE, "intake kernel launch failed");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const double* s = ctx->h_scratch;
+    const double tol = 1e-9 * n;
+    if (s[6] > 0) return fail(ctx, MDOT_E_MARGINAL, "marginals contain non-finite values");
+    if (s[2] < 0 || s[3] < 0) return fail(ctx, MDOT_E_MARGINAL, "marginals contain negative values");
+    if (std::fabs(s[0] - 1.0) > tol || std::fabs(s[1] - 1.0) > tol)
+        return fail(ctx, MDOT_E_MARGINAL, "marginals must sum to 1 (sum r = %.17g, sum c = %.17g)", s[0], s[1]);
+    *hmin = std::min(s[4], s[5]);
+    return MDOT_OK;
+}
+
+static int ensure_graph(mdot_ctx* ctx, int n)
+{
+    if (ctx->graph && ctx->graph_n == n) return MDOT_OK;
+    if (ctx->graph) {
+        (void)hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    const int tiles = tiles_r(n) * tiles_c(n);
+    hipStream_t cap;
+    HIPCHK(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < kChunk; ++k) launch_step(ctx->d_work, n, tiles, k & 1, cap);
+        e = hipStreamEndCapture(cap, &g);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        ctx->graph = nullptr;
+        return fail(ctx, MDOT_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    ctx->graph_n = n;
+    return MDOT_OK;
+}
+
+// Run solver steps until the device sets done (or max_chunks chunks have run).
+static int run_steps(mdot_ctx* ctx, int n, int max_chunks)
+{
+    int rc = ensure_graph(ctx, n);
+    if (rc) return rc;
+    State* st_dev = ctx->host_work.st;  // slot 0 holds the newest state after an even chunk
+    int launched = 0, checked = 0;
+    ctx->h_done[0] = ctx->h_done[1] = 0;
+    for (;;) {
+        while (launched < checked + 2 && launched < max_chunks) {
+            HIPCHK(ctx, hipGraphLaunch(ctx->graph, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(&ctx->h_done[launched & 1], &st_dev->done, sizeof(int), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            HIPCHK(ctx, hipEventRecord(ctx->ev[launched & 1], ctx->stream));
+            ++launched;
+        }
+        if (checked == launched) break;
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev[checked & 1]));
+        const int done = ctx->h_done[checked & 1];
+        ++checked;
+        if (done) break;
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MDOT_OK;
+}
+
+static int read_state(mdot_ctx* ctx)
+{
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_state, ctx->host_work.st, sizeof(State), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MDOT_OK;
+}
+
+extern "C" {
+
+const char* mdot_version(void) { return "mdot-mi355x 0.1 (gfx950)"; }
+
+void mdot_default_params(mdot_params* out)
+{
+    if (out) fill_defaults(out);
+}
+
+const char* mdot_last_error(const mdot_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_ctx** out)
+{
+    if (!out) return MDOT_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MDOT_E_DEVICE;
+    if (device < 0 || device >= ndev) return MDOT_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return MDOT_E_DEVICE;
+    mdot_ctx* ctx = new mdot_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->budget = hbm_budget_bytes;
+    bool ok = hipMalloc(&ctx->d_work, sizeof(Work) + 2 * sizeof(State)) == hipSuccess &&
+              hipMalloc(&ctx->d_prm, sizeof(DevParams)) == hipSuccess &&
+              hipHostMalloc(&ctx->h_state, sizeof(State), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_prm, sizeof(DevParams), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_done, 2 * sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreate(&ctx->t0) == hipSuccess && hipEventCreate(&ctx->t1) == hipSuccess;
+    if (!ok) {
+        mdot_ctx_destroy(ctx);
+        return MDOT_E_DEVICE;
+    }
+    *out = ctx;
+    return MDOT_OK;
+}
+
+int mdot_ctx_destroy(mdot_ctx* ctx)
+{
+    if (!ctx) return MDOT_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->d_work) (void)hipFree(ctx->d_work);
+    if (ctx->d_prm) (void)hipFree(ctx->d_prm);
+    if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+    if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
+    if (ctx->h_state) (void)hipHostFree(ctx->h_state);
+    if (ctx->h_prm) (void)hipHostFree(ctx->h_prm);
+    if (ctx->h_done) (void)hipHostFree(ctx->h_done);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->t0) (void)hipEventDestroy(ctx->t0);
+    if (ctx->t1) (void)hipEventDestroy(ctx->t1);
+    delete ctx;
+    return MDOT_OK;
+}
+
+int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c, double target_gap,
+               const mdot_params* params, double* u_out, double* v_out, mdot_result* res)
+{
+    if (!ctx) return MDOT_E_ARG;
+    if (!res) return fail(ctx, MDOT_E_ARG, "result pointer is NULL");
+    int rc = check_cost_desc(ctx, cost);
+    if (rc) return rc;
+    if (!r || !c) return fail(ctx, MDOT_E_ARG, "marginal pointer is NULL");
+    mdot_params prm;
+    if (params) prm = *params;
+    else fill_defaults(&prm);
+    const bool adaptive = !(prm.gamma_f > 0.0);
+    if (adaptive && !(target_gap > 0.0 && std::isfinite(target_gap)))
+        return fail(ctx, MDOT_E_ARG, "target_gap must be > 0 in adaptive mode");
+    if (!(prm.p >= 1.0) || !(prm.q > 1.0) || !(prm.gamma_i > 0.0) || !(prm.ls_c1 > 0.0 && prm.ls_c1 < prm.ls_c2 &&
+                                                                       prm.ls_c2 < 1.0) ||
+        prm.max_ls_trials < 1 || prm.max_pncg_iters < 1 || prm.max_sweeps < 0 ||
+        (prm.precision != MDOT_PREC_F32 && prm.precision != MDOT_PREC_F64))
+        return fail(ctx, MDOT_E_ARG, "invalid parameters");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int n = cost->n;
+    rc = ensure_workspace(ctx, n);
+    if (rc) return rc;
+    rc = bind_work(ctx, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c);
+    if (rc) return rc;
+    double scale;
+    rc = resolve_scale(ctx, cost, &scale);
+    if (rc) return rc;
+    if (scale != ctx->host_work.scale) {
+        rc = bind_work(ctx, n, cost, scale, r, c);
+        if (rc) return rc;
+    }
+    double hmin;
+    rc = intake_marginals(ctx, n, &hmin);
+    if (rc) return rc;
+
+    DevParams& P = *ctx->h_prm;
+    memset(&P, 0, sizeof P);
+    P.p = prm.p;
+    P.q = prm.q;
+    P.gamma_i = prm.gamma_i;
+    P.adaptive = adaptive;
+    P.target = adaptive ? target_gap : 0.0;
+    P.gamma_f = adaptive ? (prm.gamma_cap > 0.0 ? prm.gamma_cap : 5.0 * hmin / (2.0 * target_gap)) : prm.gamma_f;
+    if (!(P.gamma_f > 0.0)) P.gamma_f = prm.gamma_i;  // H_min = 0: a single stage at gamma_i
+    P.c1 = prm.ls_c1;
+    P.c2 = prm.ls_c2;
+    P.hmin = hmin;
+    P.tol_floor = 1e-14;
+    P.f32_min_tol = 0.0;
+    P.max_sweeps = prm.max_sweeps;
+    P.max_ls_trials = prm.max_ls_trials;
+    P.max_pncg_iters = prm.max_pncg_iters;
+    P.exp64_default = prm.precision == MDOT_PREC_F64;
+    P.warm_start = prm.warm_start;
+    P.n = n;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_prm, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->t0, ctx->stream));
+    if (launch_init(ctx->d_work, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "init launch failed");
+    // hard cap on steps: every LSE sweep is one step, each stage adds at most a few more
+    const int64_t max_steps = prm.max_sweeps > 0 ? 4 * prm.max_sweeps + 4096 : (int64_t)1 << 22;
+    rc = run_steps(ctx, n, (int)std::min<int64_t>(max_steps / kChunk + 1, 1 << 30));
+    if (rc) return rc;
+    if (launch_finish(ctx->d_work, u_out, v_out, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
+    HIPCHK(ctx, hipEventRecord(ctx->t1, ctx->stream));
+    rc = read_state(ctx);
+    if (rc) return rc;
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
+    const State& S = *ctx->h_state;
+    if (!S.done) return fail(ctx, MDOT_E_DEVICE, "solve did not finish within the step cap");
+    memset(res, 0, sizeof *res);
+    res->primal_cost = S.best_ub;
+    res->dual_bound = S.best_lb;
+    res->gap = S.best_ub - S.best_lb;
+    res->gamma_final = S.best_gamma;
+    res->marg_err_l1 = S.best_me;
+    res->grad_norm = S.gnorm;
+    res->seconds = ms * 1e-3;
+    res->stages = S.stage;
+    res->status = S.status;
+    res->pncg_iters = S.pncg_iters;
+    res->ls_trials = S.ls_trials;
+    res->sweeps = S.sweeps;
+    res->cg_resets = S.cg_resets;
+    res->ls_failures = S.ls_failures;
+    res->fp64_retries = S.fallbacks;
+    res->cert_sweeps = S.cert_sweeps;
+    return S.status;
+}
+
+// Set up the state for a standalone sweep sequence (one LSE, or Round + certificate).
+static int standalone_setup(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
+                            const double* shift, int exp64, int kind, const double* u_prev, const double* v_prev,
+                            double gamma_prev, const double* r, const double* c)
+{
+    const int n = cost->n;
+    int rc = ensure_workspace(ctx, n);
+    if (rc) return rc;
+    rc = bind_work(ctx, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c);
+    if (rc) return rc;
+    double scale;
+    rc = resolve_scale(ctx, cost, &scale);
+    if (rc) return rc;
+    if (scale != ctx->host_work.scale) {
+        rc = bind_work(ctx, n, cost, scale, r, c);
+        if (rc) return rc;
+    }
+    const Work& w = ctx->host_work;
+    HIPCHK(ctx, hipMemcpyAsync(w.z, u, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(w.z + n, v, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(w.p, 0, 2 * n * sizeof(double), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(w.g, 0, 2 * n * sizeof(double), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(w.rt, 0, 2 * n * sizeof(double), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(w.logt, 0, 2 * n * sizeof(double), ctx->stream));
+    if (shift) HIPCHK(ctx, hipMemcpyAsync(w.lz, shift, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    const bool ext = u_prev && v_prev && gamma > gamma_prev;
+    if (ext) {
+        HIPCHK(ctx, hipMemcpyAsync(w.zprev, u_prev, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(w.zprev + n, v_prev, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    DevParams& P = *ctx->h_prm;
+    memset(&P, 0, sizeof P);
+    P.exp64_default = exp64;
+    P.n = n;
+    P.gamma_f = gamma;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_prm, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
+    State& S = *ctx->h_state;
+    memset(&S, 0, sizeof S);
+    S.standalone = kind;
+    S.sweep_mode = shift ? SM_LSE : SM_MAX;
+    S.ls_phase = LS_STANDALONE;
+    S.exp64 = exp64;
+    S.exp64_stage = exp64;
+    S.gamma = gamma;
+    S.gamma_prev = ext ? gamma_prev : gamma;
+    S.best_ub = INFINITY;
+    S.best_lb = -INFINITY;
+    HIPCHK(ctx, hipMemcpyAsync(w.st, &S, sizeof S, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, (w.nrt + w.nct) * sizeof(uint32_t), ctx->stream));
+    return MDOT_OK;
+}
+
+int mdot_lse2(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
+              const double* shift, mdot_precision precision, double* lr_out, double* lc_out)
+{
+    if (!ctx) return MDOT_E_ARG;
+    int rc = check_cost_desc(ctx, cost);
+    if (rc) return rc;
+    if (!u || !v || !lr_out || !lc_out) return fail(ctx, MDOT_E_ARG, "NULL vector pointer");
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(ctx, MDOT_E_ARG, "bad gamma %g", gamma);
+    if (precision != MDOT_PREC_F32 && precision != MDOT_PREC_F64) return fail(ctx, MDOT_E_ARG, "bad precision");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    rc = standalone_setup(ctx, cost, u, v, gamma, shift, precision == MDOT_PREC_F64, 1, nullptr, nullptr, 0.0, nullptr,
+                          nullptr);
+    if (rc) return rc;
+    rc = run_steps(ctx, cost->n, 1);
+    if (rc) return rc;
+    rc = read_state(ctx);
+    if (rc) return rc;
+    if (!ctx->h_state->done) return fail(ctx, MDOT_E_DEVICE, "standalone sweep did not finish");
+    const Work& w = ctx->host_work;
+    const int n = cost->n;
+    HIPCHK(ctx, hipMemcpyAsync(lr_out, w.lzt, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(lc_out, w.lzt + n, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return ctx->h_state->status;
+}
+
+int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
+                       const double* u_prev, const double* v_prev, double gamma_prev, const double* r,
+                       const double* c, double* ub, double* lb, double* marg_err)
+{
+    if (!ctx) return MDOT_E_ARG;
+    int rc = check_cost_desc(ctx, cost);
+    if (rc) return rc;
+    if (!u || !v || !r || !c || !ub || !lb || !marg_err) return fail(ctx, MDOT_E_ARG, "NULL pointer argument");
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(ctx, MDOT_E_ARG, "bad gamma %g", gamma);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    rc = standalone_setup(ctx, cost, u, v, gamma, nullptr, 1, 2, u_prev, v_prev, gamma_prev, r, c);
+    if (rc) return rc;
+    rc = run_steps(ctx, cost->n, 1);
+    if (rc) return rc;
+    rc = read_state(ctx);
+    if (rc) return rc;
+    if (!ctx->h_state->done) return fail(ctx, MDOT_E_DEVICE, "round/certify sweeps did not finish");
+    *ub = ctx->h_state->best_ub;
+    *lb = ctx->h_state->best_lb;
+    *marg_err = ctx->h_state->best_me;
+    return ctx->h_state->status;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal layout shared by the host orchestration (mdot_api.cpp) and the kernels
+// (mdot_kernels.hip). Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/mdot.h"
+
+namespace mdot {
+
+// Tile geometry of the fused sweep: a workgroup of 4 wave64s covers BR rows x BC columns;
+// each lane owns 4 consecutive columns, each wave RPW consecutive rows.
+constexpr int kWG = 256;
+constexpr int kBC = 256;
+constexpr int kRPW = 16;
+constexpr int kBR = 4 * kRPW;
+constexpr int kVecWG = 256;
+
+// What the next sweep does.
+enum SweepMode : int32_t { SM_NONE = 0, SM_LSE = 1, SM_R1 = 2, SM_R2 = 3, SM_MAX = 4 };
+// Phase of an LSE sweep.
+enum LsPhase : int32_t { LS_INIT = 0, LS_TRIAL = 1, LS_FORCE = 2, LS_STANDALONE = 3 };
+// O(n) work the vector kernel applies before the next sweep (bit mask, applied in this order).
+enum VecAction : int32_t { VA_ACCEPT = 1, VA_SAVE_BEST = 2, VA_STAGE_INIT = 4, VA_ROUND_PREP = 8 };
+
+// Per-block partial reductions written by the row / column finalizers.
+enum Dot : int {
+    // LSE sweep (trial values at alpha; y = g_new - g_cur)
+    D_PHI = 0,   // <p, g_new>            = phi'(alpha)            (App. B, eq. (phiprime))
+    D_NUM = 1,   // <y, -s_new>           numerator of beta        (eq. (beta_PPR_OT))
+    D_DEN = 2,   // <y, p>                denominator of beta
+    D_SG = 3,    // <s_new, g_new>
+    D_GN = 4,    // ||g_new||_1
+    D_BAD = 5,   // number of rows/columns outside the exponent range
+    // R1 sweep
+    D_CG1 = 0,   // sum_j c_j g'_j   (from f = u/gamma)
+    D_CG2 = 1,   // sum_j c_j g'_j   (from the finite-difference potentials)
+    D_RF1 = 2,   // sum_i r_i f''_i  (from g = v/gamma)
+    D_RF2 = 3,   // sum_i r_i f''_i  (finite difference)
+    D_ERRC = 4,  // sum_j err_c_j
+    // R2 sweep
+    D_A = 0,     // sum_ij F'_ij C_ij
+    D_ERRR = 1,  // sum_i err_r_i  (= ||err_r||_1, err_r >= 0)
+    D_EC = 2,    // sum_i err_r_i (C err_c)_i
+    D_RFP1 = 3,  // sum_i r_i f'_i
+    D_RFP2 = 4,
+    D_CGP1 = 5,  // sum_j c_j g''_j
+    D_CGP2 = 6,
+    // max pass
+    kNDot = 8
+};
+
+struct DevParams {
+    double p, q, gamma_i, gamma_f, target, c1, c2, hmin;
+    double tol_floor;     // lower limit of the PNCG tolerance eps_d / 2
+    double f32_min_tol;   // F32 sweeps while eps_d / 2 >= this, FP64 exp below it
+    int64_t max_sweeps;
+    int32_t max_ls_trials, max_pncg_iters;
+    int32_t adaptive, exp64_default, warm_start, n;
+};
+
+// Scalar solver state in device memory. Written only by the last workgroup of a sweep
+// (one thread), read by every thread of the next kernels.
+struct State {
+    int32_t done, status, sweep_mode, vec_action;
+    int32_t exp64, ls_phase, stage, reset;
+    int32_t save_best, inner_warn, ls_trials_cur, standalone;  // standalone: 0 solve, 1 LSE only, 2 round+certify
+    int32_t budget_stop, exp64_stage, pending, pad2;  // pending: a sweep ran with this state
+    double gamma, gamma_prev, eps_d, w, ws_ratio, tol;
+    double alpha, alpha_acc, alpha_prev, beta;
+    double dphi0, alo, dlo, ahi, dhi, gnorm;
+    double r1[4];   // R1 sums: c.g'(2), r.f''(2)
+    double errc_sum;
+    double best_ub, best_lb, best_gamma, best_me, last_ub, last_lb;
+    int64_t k, sweeps, pncg_iters, ls_trials, cg_resets, ls_failures, fallbacks, cert_sweeps;
+};
+
+// Device buffers of one problem (all FP64 unless noted). 2n-vectors hold rows then columns.
+struct Work {
+    int32_t n, nrt, nct;     // size, row tiles, column tiles
+    int32_t cost_kind, dtype, d, pad;
+    const void* cost;        // dense cost or coordinates X then Y
+    double scale;            // C = scale * raw
+    const double* r;         // original marginals
+    const double* c;
+    double* rt;        // [2n] smoothed marginals r~, c~
+    double* logt;      // [2n] log r~, log c~
+    double* z;         // [2n] u, v
+    double* zprev;     // [2n] previous-stage solution
+    double* zbest;     // [2n] potentials of the best UB stage
+    double* p;         // [2n] search direction
+    double* g;         // [2n] gradient at z
+    double* lz;        // [2n] log r(P), log c(P) at z (or a prediction)
+    double* lzt;       // [2n] at the current trial
+    double* xr;        // [n]  Round row factors x
+    double* yc;        // [n]  Round column factors y
+    double* errc;      // [n]  err_c
+    double* gp;        // [2n] g' (two variants) from R1
+    double* fpp;       // [2n] f'' (two variants) from R1
+    double* rowpart;   // [nct * n]    per-tile row partials
+    double* colpart;   // [nrt * n]    per-tile column partials
+    double* rowpart2;  // [nct * n]    second row partial (R2)
+    double* rowpart3;  // [nct * n]    third row partial (R2)
+    double* rowmin;    // [2 * nct * n] per-tile row minima (two variants)
+    double* colmin;    // [2 * nrt * n] per-tile column minima
+    double* tshift;    // [nrt] per-row-tile column shift S_I
+    double* bdots;     // [(nrt + nct) * kNDot]
+    uint32_t* cnt;     // [nrt + nct] arrival counters (self-resetting)
+    State* st;         // [2] state slots: step k reads slot k % 2, its control kernel writes the other
+    DevParams* prm;
+};
+
+// Host-side launchers (mdot_kernels.hip). `wd` is the device copy of the Work struct.
+int launch_step(const Work* wd, int n, int tiles, int parity, void* stream);  // control kernel + sweep kernel
+int launch_init(const Work* wd, void* stream);                    // state + first stage
+int launch_intake(const Work* wd, double* out8, void* stream);
+int launch_cost_range(const Work* wd, int tiles, double* part, void* stream);
+int launch_finish(const Work* wd, double* u_out, double* v_out, void* stream);
+
+}  // namespace mdot
