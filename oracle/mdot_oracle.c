@@ -45,6 +45,10 @@
  *     Delta gamma^0 = gamma_i; later steps use the actual (clipped) Delta gamma.
  *   - Round: r(P)_i = 0 gives x_i = 1, c(F)_j = 0 gives y_j = 1, ||err_r||_1 = 0
  *     gives G = F'.
+ *   - the PNCG tolerance is floored at 1e-14 (a point-mass marginal has H_min = 0).
+ *   - sweep budget (max_sweeps, whole solve): the solve stops after the sweep that spends
+ *     it, keeps the last accepted iterate, rounds and certifies it, and reports a warning.
+ *   - adaptive mode reports OK exactly when the certified gap is at most the target.
  */
 #include <math.h>
 #include <stdint.h>
@@ -58,6 +62,7 @@
 #define ORC_W_NOT_CONVERGED 1
 #define ORC_E_ARG (-1)
 #define ORC_E_NOMEM (-4)
+#define TOL_FLOOR 1e-14 /* lower limit of the PNCG tolerance eps_d / 2 (H_min = 0 gives eps_d = 0) */
 
 typedef struct {
     double p;            /* tolerance exponent: eps_d = H_min / gamma^p        (Alg. 1) */
@@ -251,7 +256,7 @@ static double phi_prime(int n, const double* lr, const double* lc, const double*
  * On return zt = z + alpha p and lr, lc hold the LSEs at the accepted alpha, so the
  * next Sinkhorn direction needs no extra sweep (App. B).
  * Returns 0 on acceptance, 1 when the trial cap hit and alpha_lo > 0 was taken,
- * -1 when no step was found. */
+ * -1 when no step was found, -2 when the sweep budget ran out (no step). */
 static int line_search(int n, const double* C, double gamma, const double* rt, const double* ct,
                        const double* z, const double* p, double dphi0, double alpha0,
                        const orc_params* prm, double* zt, double* lr, double* lc, double* alpha_out,
@@ -260,7 +265,8 @@ static int line_search(int n, const double* C, double gamma, const double* rt, c
     const double c1 = prm->ls_c1, c2 = prm->ls_c2;
     double alo = 0.0, dlo = dphi0, ahi = INFINITY, dhi = 0.0;
     double a = alpha0;
-    for (int t = 0; t < prm->max_ls_trials && budget_left(prm, cn); ++t) {
+    for (int t = 0; t < prm->max_ls_trials; ++t) {
+        if (!budget_left(prm, cn)) return -2; /* sweep budget spent: no step */
         for (int k = 0; k < 2 * n; ++k) zt[k] = z[k] + a * p[k];
         orc_lse2(n, C, zt, zt + n, gamma, lr, lc);
         cn->sweeps++;
@@ -363,7 +369,7 @@ static int pncg(int n, const double* C, double gamma, const double* rt, const do
         double alpha;
         int ls = line_search(n, C, gamma, rt, ct, z, p, dphi0, alpha_prev, prm, zt, lrt, lrt + n,
                              &alpha, cn);
-        if (ls < 0) {
+        if (ls < 0) { /* no step (line search failed or budget spent): keep the last iterate */
             status = ORC_W_NOT_CONVERGED;
             break;
         }
@@ -600,7 +606,7 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
     double gamma = fmin(prm->gamma_i, gf); /* Alg. 1: gamma <- min(gamma_i, gamma_f) */
     double gamma_prev = 0.0;               /* gamma^0 = 0 (Prop. 1) */
     double best_ub = INFINITY, best_lb = -INFINITY, best_gamma = gamma, best_me = 0.0, gnorm = 0.0;
-    int status = ORC_OK, t = 1;
+    int status = ORC_OK, inner_warn = 0, t = 1;
     for (;;) {
         double eps_d = hmin / pow(gamma, prm->p); /* entropy-aware tolerance (Alg. 1) */
         double w = fmin(eps_d / 4.0, 0.5);        /* variable smoothing weight (Alg. 1) */
@@ -615,16 +621,19 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
             }
             memcpy(zprev, z, sizeof(double) * m);
         }
-        counters cn = {0, 0, 0, 0, 0};
-        int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, eps_d / 2.0, z, prm, &cn, &gnorm)
-                                     : pncg(n, C, gamma, rt, ct, eps_d / 2.0, z, prm, &cn, &gnorm);
+        counters before = tot; /* the projector counts into the solve totals (one sweep budget) */
+        double tol = fmax(eps_d / 2.0, TOL_FLOOR);
+        int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm)
+                                     : pncg(n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm);
         if (st < 0) { status = st; break; }
-        if (st == ORC_W_NOT_CONVERGED) status = ORC_W_NOT_CONVERGED;
-        tot.pncg_iters += cn.pncg_iters; tot.ls_trials += cn.ls_trials; tot.sweeps += cn.sweeps;
-        tot.cg_resets += cn.cg_resets; tot.ls_failures += cn.ls_failures;
+        if (st == ORC_W_NOT_CONVERGED) inner_warn = 1;
+        counters cn = {tot.pncg_iters - before.pncg_iters, tot.ls_trials - before.ls_trials,
+                       tot.sweeps - before.sweeps, tot.cg_resets - before.cg_resets,
+                       tot.ls_failures - before.ls_failures};
         double ub = NAN, lb = NAN;
         int last = (gamma >= gf);
-        if (adaptive || last) {
+        const int budget_stop = !budget_left(prm, &tot);
+        if (adaptive || last || budget_stop) {
             double me;
             int rc = orc_round_certify(n, C, z, z + n, gamma, zprev, zprev + n, gamma_prev, r, c, &ub,
                                        &lb, &me, NULL);
@@ -642,12 +651,12 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
             L->cg_resets = cn.cg_resets;
         }
         res->stages = t;
-        if (adaptive && best_ub - best_lb <= prm->target_gap) break;
-        if (last) {
-            if (adaptive) status = ORC_W_NOT_CONVERGED; /* gamma cap reached above target */
+        if (adaptive && best_ub - best_lb <= prm->target_gap) { status = ORC_OK; break; }
+        if (budget_stop) { status = ORC_W_NOT_CONVERGED; break; }
+        if (last) { /* adaptive: gamma cap reached above target */
+            status = (adaptive || inner_warn) ? ORC_W_NOT_CONVERGED : ORC_OK;
             break;
         }
-        if (!budget_left(prm, &tot)) { status = ORC_W_NOT_CONVERGED; break; }
         /* Alg. 1: Delta gamma <- (q-1) gamma, gamma <- min(gamma + Delta gamma, gamma_f) */
         double gnew = fmin(gamma + (prm->q - 1.0) * gamma, gf);
         double dg = gnew - gamma, dg_prev = gamma - gamma_prev;

@@ -337,3 +337,16 @@ def test_caps_give_warning_not_error():
     s = O.mdot(C, r, c, O.default_params(target_gap=1e-7, max_sweeps=30))
     assert s.status == 1
     assert np.isfinite(s.result["primal_cost"]) or s.result["stages"] >= 1
+
+
+def test_sweep_budget_stops_and_certifies():
+    # the budget stops the solve after the sweep that spends it; the last accepted iterate is
+    # rounded and certified (schedule mode too), and the call reports a warning
+    C, r, c = W.grid_problem(6, "blobs", "sqeuclid", 2)
+    ot = exact_lp(C, r, c)
+    for prm in (O.default_params(target_gap=1e-8, max_sweeps=40), O.default_params(gamma_f=2.0**12, max_sweeps=40)):
+        s = O.mdot(C, r, c, prm)
+        R = s.result
+        assert s.status == 1
+        assert R["sweeps"] == 40
+        assert np.isfinite(R["primal_cost"]) and R["dual_bound"] <= ot + 1e-12 <= R["primal_cost"] + 2e-12
