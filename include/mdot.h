@@ -157,6 +157,44 @@ int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* 
                        double gamma, const double* u_prev, const double* v_prev, double gamma_prev,
                        const double* r, const double* c, double* ub, double* lb, double* marg_err);
 
+/* ---- Serving: continuous batching ----
+ * A context keeps up to 64 solves in flight. Each engine step advances every admitted solve by
+ * one solver step (one sweep each) in shared kernel launches; a solve that finishes frees its
+ * slot and workspace at the next chunk boundary (8 steps), where further requests can be
+ * admitted. Every solve in flight on one context must use the same cost kind and dtype. Each
+ * solve's arithmetic is independent of the others in flight (own workspace, state and
+ * fixed-order reductions), so its result is the same alone and in any mix.
+ *
+ * mdot_submit: admit one solve (arguments as mdot_solve). The inputs and u_out/v_out are
+ * borrowed until mdot_poll reports the ticket done. Returns MDOT_OK with *ticket set,
+ * MDOT_E_BUSY when no slot is free or the context's HBM budget (hbm_budget_bytes of
+ * mdot_ctx_create; workspace of n ~ 27 n^2 / 64 + 200 n bytes) would be exceeded -- retry after
+ * mdot_run -- or an error (intake validation as in mdot_solve). Synchronous intake. */
+int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c,
+                double target_gap, const mdot_params* params, double* u_out, double* v_out,
+                uint64_t* ticket);
+
+/* Advance every solve in flight by `steps` solver steps (rounded up to whole chunks of 8),
+ * retire the finished ones (potentials written to their u_out/v_out, results kept for
+ * mdot_poll). *n_done (host, may be NULL) receives the number retired. Synchronous. */
+int mdot_run(mdot_ctx* ctx, int steps, int* n_done);
+
+/* Result of a submitted solve. Returns MDOT_OK (res filled, ticket released) or 2 when still in
+ * flight and wait == 0; with wait != 0 it runs the engine until the ticket is done.
+ * res->seconds is 0 for engine solves (latency is the caller's clock). */
+int mdot_poll(mdot_ctx* ctx, uint64_t ticket, int wait, mdot_result* res);
+
+/* Number of solves in flight and the workspace bytes they hold (host pointers, may be NULL). */
+int mdot_inflight(mdot_ctx* ctx, int* n_active, size_t* bytes_in_use);
+
+/* Measurement hook: run the solver's fused LSE sweep kernel `iters` times back-to-back on the
+ * context stream at the potentials (u, v) and gamma (shifts set to the exact log-sums first,
+ * as in a line-search trial near the solution) and return the mean duration per sweep in
+ * milliseconds, taken with HIP events on that stream. u, v: device FP64[n]; ms_per_sweep: host.
+ * Synchronous. */
+int mdot_bench_sweep(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
+                     mdot_precision precision, int iters, double* ms_per_sweep);
+
 /* Text of the last error on this context (never NULL). */
 const char* mdot_last_error(const mdot_ctx* ctx);
 

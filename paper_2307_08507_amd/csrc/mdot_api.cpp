@@ -2,6 +2,11 @@
 // side of the solve loop. All solver decisions are taken on the device (mdot_kernels.hip);
 // the host replays a captured graph of solver steps and polls a done flag once per chunk,
 // keeping two chunks in flight so the GPU never waits for the host.
+//
+// The serving engine (mdot_submit / mdot_run / mdot_poll) keeps up to kMaxBatch solves in
+// flight. Every engine step advances all of them with one launch per kernel (grid-stride over
+// a device batch descriptor); a finished solve frees its slot and workspace at the next chunk
+// boundary, where new requests can be admitted if a slot and the HBM budget allow.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -9,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -18,12 +24,29 @@ using namespace mdot;
 
 namespace {
 
-constexpr int kChunk = 32;          // solver steps per graph launch (even: the state slot alternates)
-constexpr int kMaxN = 65536;        // column finalizer keeps n / 64 tile shifts in LDS
+constexpr int kChunk = 32;       // solver steps per graph launch (even: the state slot alternates)
+constexpr int kBatchChunk = 8;   // engine steps per graph launch (admission granularity, even)
+constexpr int kMaxN = 65536;     // the finalize kernel keeps n / 64 tile shifts in LDS
+constexpr int kSweepGrid = 2048; // engine: workgroups of the grid-stride sweep kernels
+constexpr int kFinGrid = 512;    // engine: workgroups of the grid-stride finalize kernel
 
-struct Buf {
-    void* p = nullptr;
-    size_t bytes = 0;
+// Device buffers of one problem: workspace, device copy of Work + 2 state slots, parameters.
+struct ProblemBufs {
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int cap_n = 0;
+    Work* d_work = nullptr;  // Work followed by State[2]
+    DevParams* d_prm = nullptr;
+    Work host_work{};
+};
+
+struct Slot {
+    bool used = false;
+    uint64_t ticket = 0;
+    ProblemBufs pb;
+    double* u_out = nullptr;
+    double* v_out = nullptr;
+    size_t footprint = 0;
 };
 
 }  // namespace
@@ -33,24 +56,30 @@ struct mdot_ctx {
     hipStream_t stream = nullptr;
     size_t budget = 0;
     std::string err;
-    // workspace for the current capacity
-    int cap_n = 0;
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    Work host_work{};
-    Work* d_work = nullptr;
+    ProblemBufs main;             // single solves and the standalone entry points
     State* h_state = nullptr;     // pinned
-    int* h_done = nullptr;        // pinned, two slots
+    int* h_done = nullptr;        // pinned, kMaxBatch + 2 slots
     double* h_scratch = nullptr;  // pinned, intake results
     double* d_scratch = nullptr;  // device, intake results / cost range partials
     size_t scratch_doubles = 0;
-    DevParams* d_prm = nullptr;
     DevParams* h_prm = nullptr;   // pinned
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    // captured chunk of solver steps for the current n
-    hipGraphExec_t graph = nullptr;
-    int graph_n = 0;
+    hipGraphExec_t graph = nullptr;  // captured chunk of solver steps for `main`
+    int graph_n = 0, graph_kind = -1, graph_dtype = -1;
+    // serving engine
+    Slot slots[kMaxBatch];
+    std::vector<ProblemBufs> pool;  // released problem buffers kept for reuse
+    BatchDesc* h_batch = nullptr;   // pinned
+    BatchDesc* d_batch = nullptr;
+    int* d_done = nullptr;
+    bool batch_dirty = true;
+    int engine_cc = -1;
+    hipGraphExec_t bgraph = nullptr;
+    int bgraph_cc = -1;
+    uint64_t next_ticket = 1;
+    size_t bytes_in_use = 0;
+    std::map<uint64_t, mdot_result> finished;
 };
 
 static int fail(mdot_ctx* ctx, int code, const char* fmt, ...)
@@ -74,6 +103,7 @@ static int fail(mdot_ctx* ctx, int code, const char* fmt, ...)
 
 static inline int tiles_r(int n) { return (n + kBR - 1) / kBR; }
 static inline int tiles_c(int n) { return (n + kBC - 1) / kBC; }
+static inline int fin_blocks(int n) { return (2 * n + kVecWG - 1) / kVecWG; }
 
 // Bytes of workspace for size n (see Work in mdot_internal.h).
 static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
@@ -85,7 +115,7 @@ static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
         2 * N, 2 * N,                                                 // gp fpp
         nct * N, nrt * N, nct * N, nct * N,                           // rowpart colpart rowpart2 rowpart3
         2 * nct * N, 2 * nrt * N,                                     // rowmin colmin
-        nrt, (nrt + nct) * kNDot,                                     // tshift bdots
+        nrt, (size_t)fin_blocks(n) * kNDot,                           // tshift bdots
     };
     size_t off = 0;
     const int k = sizeof(counts) / sizeof(counts[0]);
@@ -94,55 +124,76 @@ static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
         off += ((counts[i] * sizeof(double) + 255) / 256) * 256;
     }
     if (out_offsets) out_offsets[k] = off;  // counters
-    off += ((nrt + nct + 1) * sizeof(uint32_t) + 255) / 256 * 256;
+    off += 256;
     return off;
 }
 
-static int ensure_workspace(mdot_ctx* ctx, int n)
+static size_t problem_footprint(int n)
 {
-    if (n <= ctx->cap_n && ctx->ws) return MDOT_OK;
-    size_t need = workspace_bytes(n);
-    if (ctx->budget && need > ctx->budget)
-        return fail(ctx, MDOT_E_NOMEM, "workspace for n=%d needs %zu bytes > budget %zu", n, need, ctx->budget);
-    if (ctx->ws) {
-        (void)hipFree(ctx->ws);
-        ctx->ws = nullptr;
+    return workspace_bytes(n) + sizeof(Work) + 2 * sizeof(State) + sizeof(DevParams);
+}
+
+static void free_bufs(ProblemBufs& pb)
+{
+    if (pb.ws) (void)hipFree(pb.ws);
+    if (pb.d_work) (void)hipFree(pb.d_work);
+    if (pb.d_prm) (void)hipFree(pb.d_prm);
+    pb = ProblemBufs{};
+}
+
+static int ensure_scratch(mdot_ctx* ctx, int n)
+{
+    const size_t scr = std::max<size_t>(64, 2 * (size_t)tiles_r(n) * tiles_c(n));
+    if (scr <= ctx->scratch_doubles) return MDOT_OK;
+    if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+    if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
+    ctx->d_scratch = nullptr;
+    ctx->h_scratch = nullptr;
+    ctx->scratch_doubles = 0;
+    HIPCHK(ctx, hipMalloc(&ctx->d_scratch, scr * sizeof(double)));
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_scratch, scr * sizeof(double), hipHostMallocDefault));
+    ctx->scratch_doubles = scr;
+    return MDOT_OK;
+}
+
+// Make pb hold a workspace for size n (reallocating when it is too small).
+static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n)
+{
+    if (!pb.d_work) {
+        HIPCHK(ctx, hipMalloc(&pb.d_work, sizeof(Work) + 2 * sizeof(State)));
+        HIPCHK(ctx, hipMalloc(&pb.d_prm, sizeof(DevParams)));
     }
-    if (ctx->graph) {
+    if (n <= pb.cap_n && pb.ws) return ensure_scratch(ctx, n);
+    const size_t need = workspace_bytes(n);
+    if (pb.ws) {
+        (void)hipFree(pb.ws);
+        pb.ws = nullptr;
+        pb.cap_n = 0;
+    }
+    if (ctx->graph) {  // the captured graph may reference the old sizes
         (void)hipGraphExecDestroy(ctx->graph);
         ctx->graph = nullptr;
         ctx->graph_n = 0;
     }
-    hipError_t e = hipMalloc(&ctx->ws, need);
+    hipError_t e = hipMalloc(&pb.ws, need);
     if (e != hipSuccess) {
-        ctx->ws = nullptr;
-        ctx->cap_n = 0;
+        pb.ws = nullptr;
         return fail(ctx, MDOT_E_NOMEM, "hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
     }
-    ctx->ws_bytes = need;
-    ctx->cap_n = n;
-    HIPCHK(ctx, hipMemsetAsync(ctx->ws, 0, need, ctx->stream));
-    const size_t scr = std::max<size_t>(64, 2 * (size_t)tiles_r(n) * tiles_c(n));
-    if (scr > ctx->scratch_doubles) {
-        if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
-        if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
-        ctx->d_scratch = nullptr;
-        ctx->h_scratch = nullptr;
-        HIPCHK(ctx, hipMalloc(&ctx->d_scratch, scr * sizeof(double)));
-        HIPCHK(ctx, hipHostMalloc(&ctx->h_scratch, scr * sizeof(double), hipHostMallocDefault));
-        ctx->scratch_doubles = scr;
-    }
-    return MDOT_OK;
+    pb.ws_bytes = need;
+    pb.cap_n = n;
+    HIPCHK(ctx, hipMemsetAsync(pb.ws, 0, need, ctx->stream));
+    return ensure_scratch(ctx, n);
 }
 
-// Lay the Work struct out over the workspace for size n (n <= cap_n) and upload it.
-static int bind_work(mdot_ctx* ctx, int n, const mdot_cost_desc* cost, double scale, const double* r,
-                     const double* c)
+// Lay the Work struct out over pb's workspace for size n (n <= cap_n) and upload it.
+static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc* cost, double scale,
+                     const double* r, const double* c)
 {
     size_t off[32];
     workspace_bytes(n, off);
-    char* b = (char*)ctx->ws;
-    Work& w = ctx->host_work;
+    char* b = (char*)pb.ws;
+    Work& w = pb.host_work;
     memset(&w, 0, sizeof w);
     w.n = n;
     w.nrt = tiles_r(n);
@@ -160,9 +211,9 @@ static int bind_work(mdot_ctx* ctx, int n, const mdot_cost_desc* cost, double sc
     const int k = sizeof(vec) / sizeof(vec[0]);
     for (int i = 0; i < k; ++i) *vec[i] = (double*)(b + off[i]);
     w.cnt = (uint32_t*)(b + off[k]);
-    w.st = (State*)((char*)ctx->d_work + sizeof(Work));
-    w.prm = ctx->d_prm;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_work, &w, sizeof w, hipMemcpyHostToDevice, ctx->stream));
+    w.st = (State*)((char*)pb.d_work + sizeof(Work));
+    w.prm = pb.d_prm;
+    HIPCHK(ctx, hipMemcpyAsync(pb.d_work, &w, sizeof w, hipMemcpyHostToDevice, ctx->stream));
     return MDOT_OK;
 }
 
@@ -197,12 +248,25 @@ static int check_cost_desc(mdot_ctx* ctx, const mdot_cost_desc* cost)
     return MDOT_OK;
 }
 
+static int check_params(mdot_ctx* ctx, const mdot_params& prm, double target_gap)
+{
+    const bool adaptive = !(prm.gamma_f > 0.0);
+    if (adaptive && !(target_gap > 0.0 && std::isfinite(target_gap)))
+        return fail(ctx, MDOT_E_ARG, "target_gap must be > 0 in adaptive mode");
+    if (!(prm.p >= 1.0) || !(prm.q > 1.0) || !(prm.gamma_i > 0.0) ||
+        !(prm.ls_c1 > 0.0 && prm.ls_c1 < prm.ls_c2 && prm.ls_c2 < 1.0) || prm.max_ls_trials < 1 ||
+        prm.max_pncg_iters < 1 || prm.max_sweeps < 0 ||
+        (prm.precision != MDOT_PREC_F32 && prm.precision != MDOT_PREC_F64))
+        return fail(ctx, MDOT_E_ARG, "invalid parameters");
+    return MDOT_OK;
+}
+
 // Range of the raw cost (one pass) -> resolved scale; MDOT_E_COST if scale*raw leaves [0,1].
-static int resolve_scale(mdot_ctx* ctx, const mdot_cost_desc* cost, double* scale_out)
+static int resolve_scale(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, double* scale_out)
 {
     const int n = cost->n;
     const int tiles = tiles_r(n) * tiles_c(n);
-    if (launch_cost_range(ctx->d_work, tiles, ctx->d_scratch, ctx->stream))
+    if (launch_cost_range(pb.host_work, pb.d_work, ctx->d_scratch, ctx->stream))
         return fail(ctx, MDOT_E_DEVICE, "cost range kernel launch failed");
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 2 * tiles * sizeof(double), hipMemcpyDeviceToHost,
                                ctx->stream));
@@ -211,7 +275,7 @@ static int resolve_scale(mdot_ctx* ctx, const mdot_cost_desc* cost, double* scal
     bool nonfinite = false;
     for (int t = 0; t < tiles; ++t) {
         lo = std::min(lo, ctx->h_scratch[2 * t]);
-        double h = ctx->h_scratch[2 * t + 1];
+        const double h = ctx->h_scratch[2 * t + 1];
         if (std::isnan(h)) nonfinite = true;
         else hi = std::max(hi, h);
     }
@@ -225,9 +289,9 @@ static int resolve_scale(mdot_ctx* ctx, const mdot_cost_desc* cost, double* scal
     return MDOT_OK;
 }
 
-static int intake_marginals(mdot_ctx* ctx, int n, double* hmin)
+static int intake_marginals(mdot_ctx* ctx, ProblemBufs& pb, int n, double* hmin)
 {
-    if (launch_intake(ctx->d_work, ctx->d_scratch, ctx->stream))
+    if (launch_intake(pb.d_work, ctx->d_scratch, ctx->stream))
         return fail(ctx, MDOT_E_DEVICE, "intake kernel launch failed");
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -241,164 +305,27 @@ static int intake_marginals(mdot_ctx* ctx, int n, double* hmin)
     return MDOT_OK;
 }
 
-static int ensure_graph(mdot_ctx* ctx, int n)
+// Intake of one problem into pb: workspace, Work, cost scale, marginal checks, parameters,
+// initial state. Leaves the problem ready for its first solver step (state slot 0).
+static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, const double* r,
+                         const double* c, double target_gap, const mdot_params& prm)
 {
-    if (ctx->graph && ctx->graph_n == n) return MDOT_OK;
-    if (ctx->graph) {
-        (void)hipGraphExecDestroy(ctx->graph);
-        ctx->graph = nullptr;
-    }
-    const int tiles = tiles_r(n) * tiles_c(n);
-    hipStream_t cap;
-    HIPCHK(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        for (int k = 0; k < kChunk; ++k) launch_step(ctx->d_work, n, tiles, k & 1, cap);
-        e = hipStreamEndCapture(cap, &g);
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
-    (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) {
-        ctx->graph = nullptr;
-        return fail(ctx, MDOT_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    }
-    ctx->graph_n = n;
-    return MDOT_OK;
-}
-
-// Run solver steps until the device sets done (or max_chunks chunks have run).
-static int run_steps(mdot_ctx* ctx, int n, int max_chunks)
-{
-    int rc = ensure_graph(ctx, n);
-    if (rc) return rc;
-    State* st_dev = ctx->host_work.st;  // slot 0 holds the newest state after an even chunk
-    int launched = 0, checked = 0;
-    ctx->h_done[0] = ctx->h_done[1] = 0;
-    for (;;) {
-        while (launched < checked + 2 && launched < max_chunks) {
-            HIPCHK(ctx, hipGraphLaunch(ctx->graph, ctx->stream));
-            HIPCHK(ctx, hipMemcpyAsync(&ctx->h_done[launched & 1], &st_dev->done, sizeof(int), hipMemcpyDeviceToHost,
-                                       ctx->stream));
-            HIPCHK(ctx, hipEventRecord(ctx->ev[launched & 1], ctx->stream));
-            ++launched;
-        }
-        if (checked == launched) break;
-        HIPCHK(ctx, hipEventSynchronize(ctx->ev[checked & 1]));
-        const int done = ctx->h_done[checked & 1];
-        ++checked;
-        if (done) break;
-    }
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return MDOT_OK;
-}
-
-static int read_state(mdot_ctx* ctx)
-{
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_state, ctx->host_work.st, sizeof(State), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return MDOT_OK;
-}
-
-extern "C" {
-
-const char* mdot_version(void) { return "mdot-mi355x 0.1 (gfx950)"; }
-
-void mdot_default_params(mdot_params* out)
-{
-    if (out) fill_defaults(out);
-}
-
-const char* mdot_last_error(const mdot_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
-
-int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_ctx** out)
-{
-    if (!out) return MDOT_E_ARG;
-    *out = nullptr;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MDOT_E_DEVICE;
-    if (device < 0 || device >= ndev) return MDOT_E_ARG;
-    if (hipSetDevice(device) != hipSuccess) return MDOT_E_DEVICE;
-    mdot_ctx* ctx = new mdot_ctx();
-    ctx->device = device;
-    ctx->stream = (hipStream_t)hip_stream;
-    ctx->budget = hbm_budget_bytes;
-    bool ok = hipMalloc(&ctx->d_work, sizeof(Work) + 2 * sizeof(State)) == hipSuccess &&
-              hipMalloc(&ctx->d_prm, sizeof(DevParams)) == hipSuccess &&
-              hipHostMalloc(&ctx->h_state, sizeof(State), hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(&ctx->h_prm, sizeof(DevParams), hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(&ctx->h_done, 2 * sizeof(int), hipHostMallocDefault) == hipSuccess &&
-              hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming) == hipSuccess &&
-              hipEventCreate(&ctx->t0) == hipSuccess && hipEventCreate(&ctx->t1) == hipSuccess;
-    if (!ok) {
-        mdot_ctx_destroy(ctx);
-        return MDOT_E_DEVICE;
-    }
-    *out = ctx;
-    return MDOT_OK;
-}
-
-int mdot_ctx_destroy(mdot_ctx* ctx)
-{
-    if (!ctx) return MDOT_OK;
-    (void)hipSetDevice(ctx->device);
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    else (void)hipDeviceSynchronize();
-    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
-    if (ctx->ws) (void)hipFree(ctx->ws);
-    if (ctx->d_work) (void)hipFree(ctx->d_work);
-    if (ctx->d_prm) (void)hipFree(ctx->d_prm);
-    if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
-    if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
-    if (ctx->h_state) (void)hipHostFree(ctx->h_state);
-    if (ctx->h_prm) (void)hipHostFree(ctx->h_prm);
-    if (ctx->h_done) (void)hipHostFree(ctx->h_done);
-    for (auto& e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
-    if (ctx->t0) (void)hipEventDestroy(ctx->t0);
-    if (ctx->t1) (void)hipEventDestroy(ctx->t1);
-    delete ctx;
-    return MDOT_OK;
-}
-
-int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c, double target_gap,
-               const mdot_params* params, double* u_out, double* v_out, mdot_result* res)
-{
-    if (!ctx) return MDOT_E_ARG;
-    if (!res) return fail(ctx, MDOT_E_ARG, "result pointer is NULL");
-    int rc = check_cost_desc(ctx, cost);
-    if (rc) return rc;
-    if (!r || !c) return fail(ctx, MDOT_E_ARG, "marginal pointer is NULL");
-    mdot_params prm;
-    if (params) prm = *params;
-    else fill_defaults(&prm);
-    const bool adaptive = !(prm.gamma_f > 0.0);
-    if (adaptive && !(target_gap > 0.0 && std::isfinite(target_gap)))
-        return fail(ctx, MDOT_E_ARG, "target_gap must be > 0 in adaptive mode");
-    if (!(prm.p >= 1.0) || !(prm.q > 1.0) || !(prm.gamma_i > 0.0) || !(prm.ls_c1 > 0.0 && prm.ls_c1 < prm.ls_c2 &&
-                                                                       prm.ls_c2 < 1.0) ||
-        prm.max_ls_trials < 1 || prm.max_pncg_iters < 1 || prm.max_sweeps < 0 ||
-        (prm.precision != MDOT_PREC_F32 && prm.precision != MDOT_PREC_F64))
-        return fail(ctx, MDOT_E_ARG, "invalid parameters");
-    HIPCHK(ctx, hipSetDevice(ctx->device));
     const int n = cost->n;
-    rc = ensure_workspace(ctx, n);
+    int rc = ensure_workspace(ctx, pb, n);
     if (rc) return rc;
-    rc = bind_work(ctx, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c);
+    rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c);
     if (rc) return rc;
     double scale;
-    rc = resolve_scale(ctx, cost, &scale);
+    rc = resolve_scale(ctx, pb, cost, &scale);
     if (rc) return rc;
-    if (scale != ctx->host_work.scale) {
-        rc = bind_work(ctx, n, cost, scale, r, c);
+    if (scale != pb.host_work.scale) {
+        rc = bind_work(ctx, pb, n, cost, scale, r, c);
         if (rc) return rc;
     }
     double hmin;
-    rc = intake_marginals(ctx, n, &hmin);
+    rc = intake_marginals(ctx, pb, n, &hmin);
     if (rc) return rc;
-
+    const bool adaptive = !(prm.gamma_f > 0.0);
     DevParams& P = *ctx->h_prm;
     memset(&P, 0, sizeof P);
     P.p = prm.p;
@@ -419,21 +346,15 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
     P.exp64_default = prm.precision == MDOT_PREC_F64;
     P.warm_start = prm.warm_start;
     P.n = n;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_prm, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipEventRecord(ctx->t0, ctx->stream));
-    if (launch_init(ctx->d_work, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "init launch failed");
-    // hard cap on steps: every LSE sweep is one step, each stage adds at most a few more
-    const int64_t max_steps = prm.max_sweeps > 0 ? 4 * prm.max_sweeps + 4096 : (int64_t)1 << 22;
-    rc = run_steps(ctx, n, (int)std::min<int64_t>(max_steps / kChunk + 1, 1 << 30));
-    if (rc) return rc;
-    if (launch_finish(ctx->d_work, u_out, v_out, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
-    HIPCHK(ctx, hipEventRecord(ctx->t1, ctx->stream));
-    rc = read_state(ctx);
-    if (rc) return rc;
-    float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
-    const State& S = *ctx->h_state;
-    if (!S.done) return fail(ctx, MDOT_E_DEVICE, "solve did not finish within the step cap");
+    HIPCHK(ctx, hipMemcpyAsync(pb.d_prm, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
+    if (launch_init(pb.d_work, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "init launch failed");
+    // the pinned parameter block is reused by the next intake: let this copy land first
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MDOT_OK;
+}
+
+static void fill_result(const State& S, double seconds, mdot_result* res)
+{
     memset(res, 0, sizeof *res);
     res->primal_cost = S.best_ub;
     res->dual_bound = S.best_lb;
@@ -441,7 +362,7 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
     res->gamma_final = S.best_gamma;
     res->marg_err_l1 = S.best_me;
     res->grad_norm = S.gnorm;
-    res->seconds = ms * 1e-3;
+    res->seconds = seconds;
     res->stages = S.stage;
     res->status = S.status;
     res->pncg_iters = S.pncg_iters;
@@ -451,27 +372,266 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
     res->ls_failures = S.ls_failures;
     res->fp64_retries = S.fallbacks;
     res->cert_sweeps = S.cert_sweeps;
+}
+
+static int ensure_graph(mdot_ctx* ctx, int n)
+{
+    const Work& hw = ctx->main.host_work;
+    if (ctx->graph && ctx->graph_n == n && ctx->graph_kind == hw.cost_kind && ctx->graph_dtype == hw.dtype)
+        return MDOT_OK;
+    if (ctx->graph) {
+        (void)hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    hipStream_t cap;
+    HIPCHK(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < kChunk; ++k) launch_step(hw, ctx->main.d_work, k & 1, cap);
+        e = hipStreamEndCapture(cap, &g);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        ctx->graph = nullptr;
+        return fail(ctx, MDOT_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    ctx->graph_n = n;
+    ctx->graph_kind = hw.cost_kind;
+    ctx->graph_dtype = hw.dtype;
+    return MDOT_OK;
+}
+
+// Run solver steps of `main` until the device sets done (or max_chunks chunks have run).
+static int run_steps(mdot_ctx* ctx, int n, int max_chunks)
+{
+    int rc = ensure_graph(ctx, n);
+    if (rc) return rc;
+    State* st_dev = ctx->main.host_work.st;  // slot 0 holds the newest state after an even chunk
+    int launched = 0, checked = 0;
+    ctx->h_done[0] = ctx->h_done[1] = 0;
+    for (;;) {
+        while (launched < checked + 2 && launched < max_chunks) {
+            HIPCHK(ctx, hipGraphLaunch(ctx->graph, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(&ctx->h_done[launched & 1], &st_dev->done, sizeof(int), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            HIPCHK(ctx, hipEventRecord(ctx->ev[launched & 1], ctx->stream));
+            ++launched;
+        }
+        if (checked == launched) break;
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev[checked & 1]));
+        const int done = ctx->h_done[checked & 1];
+        ++checked;
+        if (done) break;
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MDOT_OK;
+}
+
+static int read_state(mdot_ctx* ctx, const ProblemBufs& pb)
+{
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_state, pb.host_work.st, sizeof(State), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return MDOT_OK;
+}
+
+// ---------------------------------------------------------------- serving engine helpers
+static int rebuild_batch(mdot_ctx* ctx)
+{
+    BatchDesc& B = *ctx->h_batch;
+    memset(&B, 0, sizeof B);
+    int nt = 0, nf = 0, m = 0;
+    for (int s = 0; s < kMaxBatch; ++s) {
+        const Slot& sl = ctx->slots[s];
+        if (!sl.used) continue;
+        const Work& w = sl.pb.host_work;
+        B.items[m] = sl.pb.d_work;
+        B.tile_prefix[m] = nt;
+        B.fin_prefix[m] = nf;
+        nt += w.nrt * w.nct;
+        nf += fin_blocks(w.n);
+        ++m;
+    }
+    B.nitems = m;
+    B.tile_prefix[m] = nt;
+    B.fin_prefix[m] = nf;
+    B.total_tiles = nt;
+    B.total_fin = nf;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_batch, &B, sizeof B, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // h_batch is reused on the next rebuild
+    ctx->batch_dirty = false;
+    return MDOT_OK;
+}
+
+static int ensure_batch_graph(mdot_ctx* ctx, int cc)
+{
+    if (ctx->bgraph && ctx->bgraph_cc == cc) return MDOT_OK;
+    if (ctx->bgraph) {
+        (void)hipGraphExecDestroy(ctx->bgraph);
+        ctx->bgraph = nullptr;
+    }
+    hipStream_t cap;
+    HIPCHK(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(cc, ctx->d_batch, k & 1, kSweepGrid, kFinGrid, cap);
+        launch_gather_done(ctx->d_batch, ctx->d_done, cap);
+        e = hipStreamEndCapture(cap, &g);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ctx->bgraph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        ctx->bgraph = nullptr;
+        return fail(ctx, MDOT_E_DEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
+    }
+    ctx->bgraph_cc = cc;
+    return MDOT_OK;
+}
+
+static void release_slot(mdot_ctx* ctx, Slot& sl)
+{
+    ctx->bytes_in_use -= sl.footprint;
+    ctx->pool.push_back(sl.pb);
+    sl = Slot{};
+    ctx->batch_dirty = true;
+    // keep the pool bounded: free the smallest buffers beyond kMaxBatch entries
+    while (ctx->pool.size() > (size_t)kMaxBatch) {
+        auto it = std::min_element(ctx->pool.begin(), ctx->pool.end(),
+                                   [](const ProblemBufs& a, const ProblemBufs& b) { return a.cap_n < b.cap_n; });
+        free_bufs(*it);
+        ctx->pool.erase(it);
+    }
+}
+
+extern "C" {
+
+const char* mdot_version(void) { return "mdot-mi355x 0.2 (gfx950)"; }
+
+void mdot_default_params(mdot_params* out)
+{
+    if (out) fill_defaults(out);
+}
+
+const char* mdot_last_error(const mdot_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_ctx** out)
+{
+    if (!out) return MDOT_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MDOT_E_DEVICE;
+    if (device < 0 || device >= ndev) return MDOT_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return MDOT_E_DEVICE;
+    mdot_ctx* ctx = new mdot_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->budget = hbm_budget_bytes;
+    bool ok = hipHostMalloc(&ctx->h_state, sizeof(State), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_prm, sizeof(DevParams), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_done, (kMaxBatch + 2) * sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_batch, sizeof(BatchDesc), hipHostMallocDefault) == hipSuccess &&
+              hipMalloc(&ctx->d_batch, sizeof(BatchDesc)) == hipSuccess &&
+              hipMalloc(&ctx->d_done, kMaxBatch * sizeof(int)) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreate(&ctx->t0) == hipSuccess && hipEventCreate(&ctx->t1) == hipSuccess;
+    if (!ok) {
+        mdot_ctx_destroy(ctx);
+        return MDOT_E_DEVICE;
+    }
+    *out = ctx;
+    return MDOT_OK;
+}
+
+int mdot_ctx_destroy(mdot_ctx* ctx)
+{
+    if (!ctx) return MDOT_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+    if (ctx->bgraph) (void)hipGraphExecDestroy(ctx->bgraph);
+    free_bufs(ctx->main);
+    for (auto& sl : ctx->slots)
+        if (sl.used) free_bufs(sl.pb);
+    for (auto& pb : ctx->pool) free_bufs(pb);
+    if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+    if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
+    if (ctx->h_state) (void)hipHostFree(ctx->h_state);
+    if (ctx->h_prm) (void)hipHostFree(ctx->h_prm);
+    if (ctx->h_done) (void)hipHostFree(ctx->h_done);
+    if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
+    if (ctx->d_batch) (void)hipFree(ctx->d_batch);
+    if (ctx->d_done) (void)hipFree(ctx->d_done);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->t0) (void)hipEventDestroy(ctx->t0);
+    if (ctx->t1) (void)hipEventDestroy(ctx->t1);
+    delete ctx;
+    return MDOT_OK;
+}
+
+int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c, double target_gap,
+               const mdot_params* params, double* u_out, double* v_out, mdot_result* res)
+{
+    if (!ctx) return MDOT_E_ARG;
+    if (!res) return fail(ctx, MDOT_E_ARG, "result pointer is NULL");
+    int rc = check_cost_desc(ctx, cost);
+    if (rc) return rc;
+    if (!r || !c) return fail(ctx, MDOT_E_ARG, "marginal pointer is NULL");
+    mdot_params prm;
+    if (params) prm = *params;
+    else fill_defaults(&prm);
+    rc = check_params(ctx, prm, target_gap);
+    if (rc) return rc;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int n = cost->n;
+    if (ctx->budget && problem_footprint(n) > ctx->budget)
+        return fail(ctx, MDOT_E_NOMEM, "workspace for n=%d needs %zu bytes > budget %zu", n, problem_footprint(n),
+                    ctx->budget);
+    rc = setup_problem(ctx, ctx->main, cost, r, c, target_gap, prm);
+    if (rc) return rc;
+    HIPCHK(ctx, hipEventRecord(ctx->t0, ctx->stream));
+    // hard cap on steps: every LSE sweep is one step, each stage adds at most a few more
+    const int64_t max_steps = prm.max_sweeps > 0 ? 4 * prm.max_sweeps + 4096 : (int64_t)1 << 22;
+    rc = run_steps(ctx, n, (int)std::min<int64_t>(max_steps / kChunk + 1, 1 << 30));
+    if (rc) return rc;
+    if (launch_finish(ctx->main.d_work, u_out, v_out, ctx->stream))
+        return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
+    HIPCHK(ctx, hipEventRecord(ctx->t1, ctx->stream));
+    rc = read_state(ctx, ctx->main);
+    if (rc) return rc;
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
+    const State& S = *ctx->h_state;
+    if (!S.done) return fail(ctx, MDOT_E_DEVICE, "solve did not finish within the step cap");
+    fill_result(S, ms * 1e-3, res);
     return S.status;
 }
 
-// Set up the state for a standalone sweep sequence (one LSE, or Round + certificate).
+// Set up `main` for a standalone sweep sequence (one LSE, or Round + certificate).
 static int standalone_setup(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
                             const double* shift, int exp64, int kind, const double* u_prev, const double* v_prev,
                             double gamma_prev, const double* r, const double* c)
 {
     const int n = cost->n;
-    int rc = ensure_workspace(ctx, n);
+    ProblemBufs& pb = ctx->main;
+    int rc = ensure_workspace(ctx, pb, n);
     if (rc) return rc;
-    rc = bind_work(ctx, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c);
+    rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c);
     if (rc) return rc;
     double scale;
-    rc = resolve_scale(ctx, cost, &scale);
+    rc = resolve_scale(ctx, pb, cost, &scale);
     if (rc) return rc;
-    if (scale != ctx->host_work.scale) {
-        rc = bind_work(ctx, n, cost, scale, r, c);
+    if (scale != pb.host_work.scale) {
+        rc = bind_work(ctx, pb, n, cost, scale, r, c);
         if (rc) return rc;
     }
-    const Work& w = ctx->host_work;
+    const Work& w = pb.host_work;
     HIPCHK(ctx, hipMemcpyAsync(w.z, u, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(w.z + n, v, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(w.p, 0, 2 * n * sizeof(double), ctx->stream));
@@ -489,7 +649,7 @@ static int standalone_setup(mdot_ctx* ctx, const mdot_cost_desc* cost, const dou
     P.exp64_default = exp64;
     P.n = n;
     P.gamma_f = gamma;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_prm, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(pb.d_prm, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
     State& S = *ctx->h_state;
     memset(&S, 0, sizeof S);
     S.standalone = kind;
@@ -502,7 +662,8 @@ static int standalone_setup(mdot_ctx* ctx, const mdot_cost_desc* cost, const dou
     S.best_ub = INFINITY;
     S.best_lb = -INFINITY;
     HIPCHK(ctx, hipMemcpyAsync(w.st, &S, sizeof S, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, (w.nrt + w.nct) * sizeof(uint32_t), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, sizeof(uint32_t), ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // the pinned blocks are reused later
     return MDOT_OK;
 }
 
@@ -521,10 +682,10 @@ int mdot_lse2(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const 
     if (rc) return rc;
     rc = run_steps(ctx, cost->n, 1);
     if (rc) return rc;
-    rc = read_state(ctx);
+    rc = read_state(ctx, ctx->main);
     if (rc) return rc;
     if (!ctx->h_state->done) return fail(ctx, MDOT_E_DEVICE, "standalone sweep did not finish");
-    const Work& w = ctx->host_work;
+    const Work& w = ctx->main.host_work;
     const int n = cost->n;
     HIPCHK(ctx, hipMemcpyAsync(lr_out, w.lzt, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(lc_out, w.lzt + n, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
@@ -546,13 +707,182 @@ int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* 
     if (rc) return rc;
     rc = run_steps(ctx, cost->n, 1);
     if (rc) return rc;
-    rc = read_state(ctx);
+    rc = read_state(ctx, ctx->main);
     if (rc) return rc;
     if (!ctx->h_state->done) return fail(ctx, MDOT_E_DEVICE, "round/certify sweeps did not finish");
     *ub = ctx->h_state->best_ub;
     *lb = ctx->h_state->best_lb;
     *marg_err = ctx->h_state->best_me;
     return ctx->h_state->status;
+}
+
+int mdot_bench_sweep(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
+                     mdot_precision precision, int iters, double* ms_per_sweep)
+{
+    if (!ctx) return MDOT_E_ARG;
+    int rc = check_cost_desc(ctx, cost);
+    if (rc) return rc;
+    if (!u || !v || !ms_per_sweep || iters < 1) return fail(ctx, MDOT_E_ARG, "bad argument");
+    if (precision != MDOT_PREC_F32 && precision != MDOT_PREC_F64) return fail(ctx, MDOT_E_ARG, "bad precision");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int exp64 = precision == MDOT_PREC_F64;
+    // exact log-sums first (max pass + LSE pass) so the timed sweeps run with converged shifts
+    rc = standalone_setup(ctx, cost, u, v, gamma, nullptr, exp64, 1, nullptr, nullptr, 0.0, nullptr, nullptr);
+    if (rc) return rc;
+    rc = run_steps(ctx, cost->n, 1);
+    if (rc) return rc;
+    const Work& w = ctx->main.host_work;
+    const int n = cost->n;
+    HIPCHK(ctx, hipMemcpyAsync(w.lz, w.lzt, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    State& S = *ctx->h_state;
+    HIPCHK(ctx, hipMemcpyAsync(&S, w.st, sizeof S, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    S.done = 0;
+    S.standalone = 1;
+    S.sweep_mode = SM_LSE;
+    S.ls_phase = LS_STANDALONE;
+    S.exp64 = exp64;
+    S.vec_action = 0;
+    HIPCHK(ctx, hipMemcpyAsync(w.st, &S, sizeof S, hipMemcpyHostToDevice, ctx->stream));
+    for (int k = 0; k < 3; ++k)
+        if (launch_sweep(w, ctx->main.d_work, 0, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "sweep launch failed");
+    HIPCHK(ctx, hipEventRecord(ctx->t0, ctx->stream));
+    for (int k = 0; k < iters; ++k)
+        if (launch_sweep(w, ctx->main.d_work, 0, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "sweep launch failed");
+    HIPCHK(ctx, hipEventRecord(ctx->t1, ctx->stream));
+    HIPCHK(ctx, hipEventSynchronize(ctx->t1));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
+    *ms_per_sweep = (double)ms / iters;
+    return MDOT_OK;
+}
+
+// ---------------------------------------------------------------- serving engine
+int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c, double target_gap,
+                const mdot_params* params, double* u_out, double* v_out, uint64_t* ticket)
+{
+    if (!ctx) return MDOT_E_ARG;
+    if (!ticket) return fail(ctx, MDOT_E_ARG, "ticket pointer is NULL");
+    int rc = check_cost_desc(ctx, cost);
+    if (rc) return rc;
+    if (!r || !c) return fail(ctx, MDOT_E_ARG, "marginal pointer is NULL");
+    mdot_params prm;
+    if (params) prm = *params;
+    else fill_defaults(&prm);
+    rc = check_params(ctx, prm, target_gap);
+    if (rc) return rc;
+    const int cc = cost_code_of(cost->kind, cost->dtype);
+    int active = 0;
+    for (const Slot& sl : ctx->slots) active += sl.used;
+    if (active == 0) ctx->engine_cc = cc;
+    if (cc != ctx->engine_cc)
+        return fail(ctx, MDOT_E_ARG, "every solve in flight must use the same cost kind and dtype");
+    const size_t fp = problem_footprint(cost->n);
+    if (ctx->budget && fp > ctx->budget)
+        return fail(ctx, MDOT_E_NOMEM, "n=%d needs %zu bytes > budget %zu", cost->n, fp, ctx->budget);
+    if (active == kMaxBatch || (ctx->budget && ctx->bytes_in_use + fp > ctx->budget))
+        return fail(ctx, MDOT_E_BUSY, "no free slot or HBM budget (%zu of %zu bytes in use)", ctx->bytes_in_use,
+                    ctx->budget);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    int s = 0;
+    while (ctx->slots[s].used) ++s;
+    Slot& sl = ctx->slots[s];
+    // reuse the smallest pooled workspace that fits
+    int best = -1;
+    for (int k = 0; k < (int)ctx->pool.size(); ++k)
+        if (ctx->pool[k].cap_n >= cost->n && (best < 0 || ctx->pool[k].cap_n < ctx->pool[best].cap_n)) best = k;
+    if (best >= 0) {
+        sl.pb = ctx->pool[best];
+        ctx->pool.erase(ctx->pool.begin() + best);
+    }
+    rc = setup_problem(ctx, sl.pb, cost, r, c, target_gap, prm);
+    if (rc) {
+        if (sl.pb.d_work) ctx->pool.push_back(sl.pb);
+        sl = Slot{};
+        return rc;
+    }
+    sl.used = true;
+    sl.ticket = ctx->next_ticket++;
+    sl.u_out = u_out;
+    sl.v_out = v_out;
+    sl.footprint = fp;
+    ctx->bytes_in_use += fp;
+    ctx->batch_dirty = true;
+    *ticket = sl.ticket;
+    return MDOT_OK;
+}
+
+int mdot_run(mdot_ctx* ctx, int steps, int* n_done)
+{
+    if (!ctx) return MDOT_E_ARG;
+    if (n_done) *n_done = 0;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    int completed = 0;
+    const int chunks = std::max(1, (steps + kBatchChunk - 1) / kBatchChunk);
+    for (int ch = 0; ch < chunks; ++ch) {
+        int active = 0;
+        for (const Slot& sl : ctx->slots) active += sl.used;
+        if (active == 0) break;
+        int rc;
+        if (ctx->batch_dirty) {
+            rc = rebuild_batch(ctx);
+            if (rc) return rc;
+        }
+        rc = ensure_batch_graph(ctx, ctx->engine_cc);
+        if (rc) return rc;
+        HIPCHK(ctx, hipGraphLaunch(ctx->bgraph, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_done, ctx->d_done, kMaxBatch * sizeof(int), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        // items are in slot order in the descriptor
+        int m = 0;
+        for (int s = 0; s < kMaxBatch; ++s) {
+            Slot& sl = ctx->slots[s];
+            if (!sl.used) continue;
+            const int done = ctx->h_done[m++];
+            if (!done) continue;
+            if (launch_finish(sl.pb.d_work, sl.u_out, sl.v_out, ctx->stream))
+                return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
+            rc = read_state(ctx, sl.pb);
+            if (rc) return rc;
+            mdot_result res;
+            fill_result(*ctx->h_state, 0.0, &res);
+            ctx->finished[sl.ticket] = res;
+            release_slot(ctx, sl);
+            ++completed;
+        }
+    }
+    if (n_done) *n_done = completed;
+    return MDOT_OK;
+}
+
+int mdot_poll(mdot_ctx* ctx, uint64_t ticket, int wait, mdot_result* res)
+{
+    if (!ctx) return MDOT_E_ARG;
+    for (;;) {
+        auto it = ctx->finished.find(ticket);
+        if (it != ctx->finished.end()) {
+            if (res) *res = it->second;
+            ctx->finished.erase(it);
+            return MDOT_OK;
+        }
+        bool inflight = false;
+        for (const Slot& sl : ctx->slots) inflight |= (sl.used && sl.ticket == ticket);
+        if (!inflight) return fail(ctx, MDOT_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+        if (!wait) return 2;
+        int rc = mdot_run(ctx, kBatchChunk, nullptr);
+        if (rc) return rc;
+    }
+}
+
+int mdot_inflight(mdot_ctx* ctx, int* n_active, size_t* bytes_in_use)
+{
+    if (!ctx) return MDOT_E_ARG;
+    int a = 0;
+    for (const Slot& sl : ctx->slots) a += sl.used;
+    if (n_active) *n_active = a;
+    if (bytes_in_use) *bytes_in_use = ctx->bytes_in_use;
+    return MDOT_OK;
 }
 
 }  // extern "C"

@@ -64,7 +64,7 @@ struct State {
     int32_t done, status, sweep_mode, vec_action;
     int32_t exp64, ls_phase, stage, reset;
     int32_t save_best, inner_warn, ls_trials_cur, standalone;  // standalone: 0 solve, 1 LSE only, 2 round+certify
-    int32_t budget_stop, exp64_stage, pending, pad2;  // pending: a sweep ran with this state
+    int32_t budget_stop, exp64_stage;
     double gamma, gamma_prev, eps_d, w, ws_ratio, tol;
     double alpha, alpha_acc, alpha_prev, beta;
     double dphi0, alo, dlo, ahi, dhi, gnorm;
@@ -103,17 +103,35 @@ struct Work {
     double* rowmin;    // [2 * nct * n] per-tile row minima (two variants)
     double* colmin;    // [2 * nrt * n] per-tile column minima
     double* tshift;    // [nrt] per-row-tile column shift S_I
-    double* bdots;     // [(nrt + nct) * kNDot]
-    uint32_t* cnt;     // [nrt + nct] arrival counters (self-resetting)
-    State* st;         // [2] state slots: step k reads slot k % 2, its control kernel writes the other
+    double* bdots;     // [ceil(2n / kVecWG) * kNDot] per-block dot products
+    uint32_t* cnt;     // [0]: arrival counter of the finalize kernel (self-resetting)
+    State* st;         // [2] state slots: step k reads slot k % 2, its finalize kernel writes the other
     DevParams* prm;
 };
 
-// Host-side launchers (mdot_kernels.hip). `wd` is the device copy of the Work struct.
-int launch_step(const Work* wd, int n, int tiles, int parity, void* stream);  // control kernel + sweep kernel
-int launch_init(const Work* wd, void* stream);                    // state + first stage
+// Problems in flight in one batched launch: logical tile g of the step belongs to item b with
+// tile_prefix[b] <= g < tile_prefix[b+1] (same for finalize blocks). Every item has its own
+// Work, state slots and counters, so its results do not depend on the rest of the batch.
+constexpr int kMaxBatch = 64;
+struct BatchDesc {
+    int32_t nitems, total_tiles, total_fin, pad;
+    int32_t tile_prefix[kMaxBatch + 1];
+    int32_t fin_prefix[kMaxBatch + 1];
+    const Work* items[kMaxBatch];
+};
+
+// Host-side launchers (mdot_kernels.hip). `hw` is the host copy of the Work struct (sizes
+// and cost type pick the grid and the kernel instance), `wd` its device copy.
+int launch_step(const Work& hw, const Work* wd, int parity, void* stream);  // control + sweep kernels
+int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream); // the LSE sweep kernel alone
+int launch_init(const Work* wd, void* stream);                               // state + first stage
 int launch_intake(const Work* wd, double* out8, void* stream);
-int launch_cost_range(const Work* wd, int tiles, double* part, void* stream);
+int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream);
 int launch_finish(const Work* wd, double* u_out, double* v_out, void* stream);
+// Batched step over a BatchDesc in device memory (cost type cost_code for every item), with
+// fixed grids (grid-stride over the descriptor), and a gather of the items' done flags.
+int cost_code_of(int cost_kind, int dtype);
+int launch_step_batch(int cost_code, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, void* stream);
+int launch_gather_done(const BatchDesc* bd, int* out, void* stream);
 
 }  // namespace mdot

@@ -1,20 +1,23 @@
 // HIP kernels of the MDOT-PNCG hot path for gfx950 (MI355X).
 //
-// One solver step is two kernels on the context stream:
-//   k_ctrl  : every workgroup reduces the per-block results of the previous sweep in a fixed
-//             order and runs the scalar logic of the line search (App. B), PNCG (Alg. 2) and
-//             the annealing loop (Alg. 1) on identical inputs, so all reach the same decision
-//             without synchronising; each then applies the O(n) vector update for its slice
-//             (accept a step, start a stage with smoothing + warm start, prepare Round), and
-//             workgroup 0 stores the new state in the other state slot.
-//   k_sweep : one fused O(n^2) pass over the cost: every workgroup forms
-//             X_ij = u_i + v_j - gamma C_ij for a BR x BC tile (FP64 argument), takes one
-//             exp per element and accumulates BOTH the row sums and the column sums from
-//             that single read of C (row sums reduced across the wave64, column sums across
-//             the four waves through LDS). The last workgroup of each row block / column
-//             block combines the tile partials in FP64 (fixed order, so results do not
-//             depend on scheduling) and reduces that block's contribution to the dot
-//             products the next k_ctrl needs.
+// One solver step is three kernels on the context stream, with no synchronisation between
+// workgroups inside the O(n^2) kernels:
+//   k_sweep : one fused pass over the cost for a line-search trial: every workgroup forms
+//             X_ij = u_i + v_j - gamma C_ij for a BR x BC tile (FP64 argument), takes one exp
+//             per element and accumulates BOTH the row sums and the column sums from that
+//             single read of C (row sums reduced across the wave64 through an LDS transpose,
+//             column sums across the four waves). It writes per-tile partials only.
+//   k_round : the same tile structure for the two Round / certificate passes (it returns at
+//             once in steps that do not need it; its larger register footprint stays out of
+//             the hot kernel).
+//   k_fin   : one thread per entry of the 2n-vectors: stores the vector update decided by the
+//             previous step (accept a line-search step, start a stage with smoothing and warm
+//             start, prepare Round), combines the tile partials of its row or column in FP64
+//             in a fixed order and reduces the dot products of the line search and of PNCG;
+//             the last workgroup to finish runs the scalar logic of the line search (App. B),
+//             PNCG (Alg. 2) and the annealing loop (Alg. 1) and stores the next state.
+// The sweeps evaluate the pending vector update on the fly for their own rows and columns
+// with the same function k_fin uses to store it (explicit fma, so both are bit-identical).
 // The host never reads a value between steps; it replays a captured graph of steps and
 // polls the done flag once per chunk.
 //
@@ -28,6 +31,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "mdot_internal.h"
 
@@ -56,70 +61,103 @@ __device__ __forceinline__ double wave_max(double v)
 }
 
 // ------------------------------------------------------------------ cost access
-// Raw cost of row i at the lane's 4 consecutive columns j0..j0+3 (C = scale * raw).
-// Columns >= n are returned as 0 and masked by the caller.
+// Dense costs are read with buffer loads through a resource descriptor based at the first
+// row of the tile (offsets stay far below 2^31 for any supported n). Each wave issues the
+// loads of all of its rows before computing on any of them, so a workgroup keeps
+// 4 x 16 rows x 1 KiB of the cost in flight.
+constexpr int kBufDword3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data format)
+
 template <int DT>
 struct DenseCost {
-    const void* base;
+    // raw element bytes and per-lane raw type for 4 consecutive columns
+    static constexpr int kBytes = (DT == MDOT_DT_F64) ? 8 : (DT == MDOT_DT_F32 ? 4 : 2);
+    using Raw = typename std::conditional<DT == MDOT_DT_F64, double4,
+                typename std::conditional<DT == MDOT_DT_F32, float4, uint2>::type>::type;
+    __amdgpu_buffer_rsrc_t rs;
     int n;
     bool vec;
-    __device__ DenseCost(const Work& w) : base(w.cost), n(w.n), vec((w.n & 3) == 0) {}
-    __device__ __forceinline__ void cols(int) {}
-    __device__ __forceinline__ void row(int i, int j0, double c[4]) const
+    __device__ __forceinline__ DenseCost(const Work& w, int i0) : n(w.n), vec((w.n & 3) == 0)
     {
-        const size_t off = (size_t)i * n + j0;
-        if constexpr (DT == MDOT_DT_F32) {
-            const float* p = (const float*)base + off;
-            if (vec && j0 + 3 < n) {
-                float4 v = *(const float4*)p;
-                c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+        const char* base = (const char*)w.cost + (size_t)i0 * w.n * kBytes;
+        const size_t rem = ((size_t)w.n - i0) * w.n * kBytes;
+        rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(rem > 0x7fffffffu ? 0x7fffffffu : rem),
+                                               kBufDword3);
+    }
+    __device__ __forceinline__ void cols(int) {}
+    // row r of the tile (global row i0 + r), columns j0..j0+3; columns >= n are masked by
+    // the caller, their values are unspecified (or 0 past the end of the matrix)
+    __device__ __forceinline__ Raw load(int r, int j0) const
+    {
+        const int off = (r * n + j0) * kBytes;
+        Raw v;
+        if constexpr (DT == MDOT_DT_F64) {
+            if (vec) {
+                auto a = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+                auto b = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+                double2 da = *(double2*)&a, db = *(double2*)&b;
+                v.x = da.x; v.y = da.y; v.z = db.x; v.w = db.y;
             } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) c[k] = (j0 + k < n) ? (double)p[k] : 0.0;
+                auto a = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+                auto b = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8, 0, 0);
+                auto c = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 16, 0, 0);
+                auto d = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 24, 0, 0);
+                v.x = *(double*)&a; v.y = *(double*)&b; v.z = *(double*)&c; v.w = *(double*)&d;
             }
-        } else if constexpr (DT == MDOT_DT_F64) {
-            const double* p = (const double*)base + off;
-            if (vec && j0 + 3 < n) {
-                double2 a = *(const double2*)p;
-                double2 b = *(const double2*)(p + 2);
-                c[0] = a.x; c[1] = a.y; c[2] = b.x; c[3] = b.y;
+        } else if constexpr (DT == MDOT_DT_F32) {
+            if (vec) {
+                auto a = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+                v = *(float4*)&a;
             } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) c[k] = (j0 + k < n) ? p[k] : 0.0;
+                v.x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                v.y = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0));
+                v.z = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0));
+                v.w = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 12, 0, 0));
             }
-        } else if constexpr (DT == MDOT_DT_F16) {
-            const __half* p = (const __half*)base + off;
-            if (vec && j0 + 3 < n) {
-                uint2 raw = *(const uint2*)p;
-                __half2 a = *(__half2*)&raw.x, b = *(__half2*)&raw.y;
-                c[0] = __low2float(a); c[1] = __high2float(a); c[2] = __low2float(b); c[3] = __high2float(b);
+        } else {
+            if (vec) {
+                auto a = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+                v = *(uint2*)&a;
             } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) c[k] = (j0 + k < n) ? (double)__half2float(p[k]) : 0.0;
-            }
-        } else {  // BF16
-            const __hip_bfloat16* p = (const __hip_bfloat16*)base + off;
-            if (vec && j0 + 3 < n) {
-                uint2 raw = *(const uint2*)p;
-                c[0] = __uint_as_float(raw.x << 16); c[1] = __uint_as_float(raw.x & 0xffff0000u);
-                c[2] = __uint_as_float(raw.y << 16); c[3] = __uint_as_float(raw.y & 0xffff0000u);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) c[k] = (j0 + k < n) ? (double)__bfloat162float(p[k]) : 0.0;
+                uint32_t h0 = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+                uint32_t h1 = __builtin_amdgcn_raw_buffer_load_b16(rs, off + 2, 0, 0);
+                uint32_t h2 = __builtin_amdgcn_raw_buffer_load_b16(rs, off + 4, 0, 0);
+                uint32_t h3 = __builtin_amdgcn_raw_buffer_load_b16(rs, off + 6, 0, 0);
+                v.x = (h0 & 0xffffu) | (h1 << 16);
+                v.y = (h2 & 0xffffu) | (h3 << 16);
             }
         }
+        return v;
     }
+    __device__ __forceinline__ void decode(const Raw& v, double c[4]) const
+    {
+        if constexpr (DT == MDOT_DT_F64) {
+            c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+        } else if constexpr (DT == MDOT_DT_F32) {
+            c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+        } else if constexpr (DT == MDOT_DT_F16) {
+            c[0] = __half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu)));
+            c[1] = __half2float(__ushort_as_half((unsigned short)(v.x >> 16)));
+            c[2] = __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu)));
+            c[3] = __half2float(__ushort_as_half((unsigned short)(v.y >> 16)));
+        } else {  // BF16: the high half of an FP32
+            c[0] = __uint_as_float(v.x << 16); c[1] = __uint_as_float(v.x & 0xffff0000u);
+            c[2] = __uint_as_float(v.y << 16); c[3] = __uint_as_float(v.y & 0xffff0000u);
+        }
+    }
+    __device__ __forceinline__ void row(int r, int j0, double c[4]) const { decode(load(r, j0), c); }
 };
 
 // Point clouds: raw C_ij = sum_k (x_ik - y_jk)^2 (KIND 1) or sum_k |x_ik - y_jk| (KIND 2),
-// evaluated in FP64 from FP32 coordinates (d <= 3).
+// evaluated in FP64 from FP32 coordinates (d <= 3). "Raw" is the row's coordinates.
 template <int KIND>
 struct PointCost {
+    using Raw = float4;
     const float* X;
     const float* Y;
-    int n, d;
+    int n, d, i0;
     double y[4][3];
-    __device__ PointCost(const Work& w) : X((const float*)w.cost), Y((const float*)w.cost + (size_t)w.n * w.d), n(w.n), d(w.d) {}
+    __device__ __forceinline__ PointCost(const Work& w, int i0_)
+        : X((const float*)w.cost), Y((const float*)w.cost + (size_t)w.n * w.d), n(w.n), d(w.d), i0(i0_) {}
     __device__ __forceinline__ void cols(int j0)
     {
 #pragma unroll
@@ -127,22 +165,31 @@ struct PointCost {
 #pragma unroll
             for (int e = 0; e < 3; ++e) y[k][e] = (j0 + k < n && e < d) ? (double)Y[(size_t)(j0 + k) * d + e] : 0.0;
     }
-    __device__ __forceinline__ void row(int i, int, double c[4]) const
+    __device__ __forceinline__ Raw load(int r, int) const
     {
-        double x[3];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) x[e] = (e < d) ? (double)X[(size_t)i * d + e] : 0.0;
+        const int i = i0 + r;
+        Raw v;
+        v.x = (i < n) ? X[(size_t)i * d] : 0.f;
+        v.y = (i < n && d > 1) ? X[(size_t)i * d + 1] : 0.f;
+        v.z = (i < n && d > 2) ? X[(size_t)i * d + 2] : 0.f;
+        v.w = 0.f;
+        return v;
+    }
+    __device__ __forceinline__ void decode(const Raw& x, double c[4]) const
+    {
+        const double xs[3] = {x.x, x.y, x.z};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             double s = 0.0;
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
-                double t = x[e] - y[k][e];
+                double t = xs[e] - y[k][e];
                 s = (KIND == 1) ? fma(t, t, s) : s + fabs(t);
             }
             c[k] = s;
         }
     }
+    __device__ __forceinline__ void row(int r, int j0, double c[4]) const { decode(load(r, j0), c); }
 };
 
 // ------------------------------------------------------------------ tile bodies
@@ -150,10 +197,80 @@ struct TileCtx {
     int I, J, i0, j0lane, lane, wave, tid;
 };
 
-// Scalars a sweep needs from the state.
+// Scalars a kernel needs from the state: the trial and the pending vector update.
 struct SweepArgs {
     double alpha, gamma, gamma_prev;
+    double alpha_acc, beta, w, ws_ratio;
+    int va, reset, stage;
 };
+
+__device__ __forceinline__ SweepArgs args_of(const State* S)
+{
+    SweepArgs a;
+    const int mode = S->sweep_mode, ph = S->ls_phase;
+    a.alpha = (mode == SM_LSE && (ph == LS_TRIAL || ph == LS_FORCE)) ? S->alpha : 0.0;
+    a.gamma = S->gamma;
+    a.gamma_prev = S->gamma_prev;
+    a.alpha_acc = S->alpha_acc;
+    a.beta = S->beta;
+    a.w = S->w;
+    a.ws_ratio = S->ws_ratio;
+    a.va = S->vec_action;
+    a.reset = S->reset;
+    a.stage = S->stage;
+    return a;
+}
+
+// Entry k of the 2n-vectors (rows then columns) after the pending vector update:
+//   accept : (u, v) += alpha p, log r(P) <- trial log-sums, p <- s + beta p or s (Alg. 2)
+//   stage  : smoothed marginals (Alg. 1), rank-1 start (stage 1) or warm start
+//            z' = z + ratio (z - z_prev) (eq. (approx-znext)), p = 0, shifts = log r~.
+// zacc is z after the accept and before the stage start (the stage's solution).
+struct Entry {
+    double z, zacc, p, lz, logt, rt, zprev;
+};
+
+__device__ __forceinline__ Entry entry_after(const Work& w, const SweepArgs& a, int k)
+{
+    Entry e;
+    e.z = w.z[k];
+    e.p = w.p[k];
+    e.lz = w.lz[k];
+    e.logt = w.logt[k];
+    e.rt = w.rt[k];
+    e.zprev = w.zprev[k];
+    if (a.va & VA_ACCEPT) {
+        e.z = fma(a.alpha_acc, e.p, e.z);
+        e.lz = w.lzt[k];
+        const double sdir = e.logt - e.lz;  // Sinkhorn direction, eq. (sinkhorn-direction)
+        e.p = a.reset ? sdir : fma(a.beta, e.p, sdir);
+    }
+    e.zacc = e.z;
+    if (a.va & VA_STAGE_INIT) {
+        const int n = w.n;
+        const double m = (k < n) ? w.r[k] : w.c[k - n];
+        e.rt = fma(1.0 - a.w, m, a.w / n);
+        e.logt = log(e.rt);
+        if (a.stage == 1) {
+            e.z = e.logt;
+            e.zprev = e.logt;  // z^0 at gamma^0 = 0
+        } else {
+            const double zp = e.zprev;
+            e.zprev = e.z;
+            e.z = fma(a.ws_ratio, e.z - zp, e.z);
+        }
+        e.p = 0.0;
+        e.lz = e.logt;
+    }
+    return e;
+}
+
+// Round row factor x_i = r_i / r(P)_i ^ 1 (Alg. 3), with r(P)_i = 0 giving 1.
+__device__ __forceinline__ double round_x(double ri, double lz)
+{
+    const double rp = exp(lz);
+    return (rp > 0.0) ? fmin(ri / rp, 1.0) : 1.0;
+}
 
 template <bool E64>
 __device__ __forceinline__ double exp2_sel(double x)
@@ -179,118 +296,200 @@ __device__ __forceinline__ void col_combine_store(double* sbuf, const double v[4
     __syncthreads();
 }
 
-// LDS of one sweep workgroup: five per-row arrays and the per-wave column buffer.
-constexpr int kSmem = 5 * kBR + 4 * kBC;
+// LDS of one sweep workgroup: five per-row arrays, the per-wave column buffer, and the
+// per-wave row-partial transpose buffer (kRPW rows x 64 lanes, padded to 65, FP32).
+constexpr int kRowPad = 65;
+constexpr int kSmem = 5 * kBR + 4 * kBC + (4 * kRPW * kRowPad + 1) / 2;
 
-template <class Cost, bool E64>
-__device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, int mode, double* sm)
+// Sum the per-lane FP32 row partials rp[r] of the wave's kRPW rows across the 64 lanes:
+// a transpose through LDS, then 4 lanes per row each sum 16 values in FP64 and combine.
+// Returns the row total in the lane with (lane & 3) == 0 of row lane >> 2.
+__device__ __forceinline__ double rows_reduce_f32(const float rp[kRPW], float* rb, int lane)
 {
-    // mode SM_LSE: sums of exp; SM_MAX: maxima of X (FP64)
+#pragma unroll
+    for (int r = 0; r < kRPW; ++r) rb[r * kRowPad + lane] = rp[r];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const int rr = lane >> 2, q = lane & 3;
+    const float* src = rb + rr * kRowPad + q * 16;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += (double)src[k];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    return s;
+}
+
+// Row and column maxima of X_ij (log units), used to seed the shifts of a standalone LSE.
+template <class Cost>
+__device__ void tile_max(const Work& w, const SweepArgs& S, const TileCtx& t, double* sm)
+{
+    double* sA = sm;
+    double* sCol = sm + 5 * kBR;
+    const int n = w.n;
+    if (t.tid < kBR) {
+        const int i = t.i0 + t.tid;
+        sA[t.tid] = (i < n) ? (w.z[i] + S.alpha * w.p[i]) * LOG2E_D : 0.0;
+    }
+    __syncthreads();
+    const double g2 = S.gamma * w.scale * LOG2E_D;
+    Cost cost(w, t.i0);
+    const int j0 = t.j0lane;
+    cost.cols(j0);
+    double V[4], colmx[4];
+    bool ok[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ok[k] = j0 + k < n;
+        V[k] = ok[k] ? (w.z[n + j0 + k] + S.alpha * w.p[n + j0 + k]) * LOG2E_D : 0.0;
+        colmx[k] = -INFINITY;
+    }
+    for (int rr = 0; rr < kRPW; ++rr) {
+        const int r = t.wave * kRPW + rr;
+        const int i = t.i0 + r;
+        if (i >= n) break;
+        double c[4];
+        cost.row(r, j0, c);
+        double m = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double x = ok[k] ? fma(-g2, c[k], V[k]) + sA[r] : -INFINITY;
+            m = fmax(m, x);
+            colmx[k] = fmax(colmx[k], x);
+        }
+        m = wave_max(m);
+        if (t.lane == 0) w.rowmin[(size_t)t.J * n + i] = m * LN2_D;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) colmx[k] *= LN2_D;
+    col_combine_store(sCol, colmx, t, 2, w.colmin + (size_t)t.I * n, n, t.J * kBC);
+}
+
+// The fused LSE tile (the hot loop of every line-search trial):
+//   e_ij = exp(X_ij - s_i),  row partial sum_j e_ij,  column partial sum_i w_i e_ij,
+// with w_i = exp(s_i - S_I). Exponent argument in FP64 (log2 units), exp2 in FP32 (E64 =
+// false) or FP64 (E64 = true).
+template <class Cost, bool E64>
+__device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, double* sm)
+{
     double* sA = sm;
     double* sWt = sm + kBR;
     double* sS = sm + 2 * kBR;
     double* sCol = sm + 5 * kBR;
+    float* sRow = (float*)(sm + 5 * kBR + 4 * kBC) + t.wave * kRPW * kRowPad;
     const int n = w.n;
     const double alpha = S.alpha;
     const double g2 = S.gamma * w.scale * LOG2E_D;
-    // per-row values: s_i (shift), A_i = (u_i - lz_i) log2 e, stored for the tile rows
+    // per-row values: shift s_i (predicted log row sum) and A_i = (u_i - lz_i) log2 e;
+    // per-column V_j = (v_j + alpha p_j) log2 e, one column per thread, through LDS
     if (t.tid < kBR) {
-        int i = t.i0 + t.tid;
-        double s = -INFINITY, a = 0.0;
+        const int i = t.i0 + t.tid;
+        double sh = -INFINITY, aa = 0.0;
         if (i < n) {
-            double ui = w.z[i], pi = w.p[i], li = w.lz[i];
-            if (mode == SM_MAX) {
-                a = (ui + alpha * pi) * LOG2E_D;
-                s = 0.0;
-            } else {
-                s = li + alpha * pi;
-                a = (ui - li) * LOG2E_D;
-            }
+            const Entry e = entry_after(w, S, i);
+            sh = fma(alpha, e.p, e.lz);
+            aa = (e.z - e.lz) * LOG2E_D;
         }
-        sS[t.tid] = s;
-        sA[t.tid] = a;
+        sS[t.tid] = sh;
+        sA[t.tid] = aa;
+    }
+    {
+        const int j = t.J * kBC + t.tid;
+        double vv = 0.0;
+        if (j < n) {
+            const Entry e = entry_after(w, S, n + j);
+            vv = fma(alpha, e.p, e.z) * LOG2E_D;
+        }
+        sCol[t.tid] = vv;
     }
     __syncthreads();
-    // S_I = max_i s_i (identical in every workgroup of this row tile)
-    double SI = -INFINITY;
+    double SI = -INFINITY;  // S_I = max_i s_i (identical in every workgroup of this row tile)
     for (int k = 0; k < kBR; ++k) SI = fmax(SI, sS[k]);
-    if (t.tid < kBR) sWt[t.tid] = (mode == SM_MAX) ? 1.0 : exp(sS[t.tid] - SI);
-    __syncthreads();
-
-    Cost cost(w);
+    if (t.tid < kBR) sWt[t.tid] = exp(sS[t.tid] - SI);
     const int j0 = t.j0lane;
-    cost.cols(j0);
     double V[4];
     bool ok[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int j = j0 + k;
-        ok[k] = j < n;
-        V[k] = ok[k] ? (w.z[n + j] + alpha * w.p[n + j]) * LOG2E_D : 0.0;
+        ok[k] = j0 + k < n;
+        V[k] = sCol[t.lane * 4 + k];
     }
-    double col64[4] = {0, 0, 0, 0};
-    float col32[4] = {0, 0, 0, 0};
-    double colmx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    __syncthreads();
+
+    Cost cost(w, t.i0);
+    cost.cols(j0);
     const int rbase = t.wave * kRPW;
-    for (int rr = 0; rr < kRPW; ++rr) {
-        const int ir = rbase + rr;
-        const int i = t.i0 + ir;
-        if (i >= n) break;
-        double c[4];
-        cost.row(i, j0, c);
-        const double A = sA[ir];
-        if (mode == SM_MAX) {
-            double m = -INFINITY;
+    const int nrows = min(kRPW, n - (t.i0 + rbase));  // rows of this wave (may be <= 0)
+    // issue the loads of a batch of rows before any compute on them (16 rows for <= 8 B per
+    // lane-row, 8 rows for wider ones)
+    constexpr int RB = sizeof(typename Cost::Raw) <= 8 ? kRPW : kRPW / 2;
+    double col64[4] = {0, 0, 0, 0};
+    if constexpr (!E64) {
+        float col32[4] = {0, 0, 0, 0};
+        float rp[kRPW];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                double x = ok[k] ? fma(-g2, c[k], V[k]) + A : -INFINITY;  // log2 units
-                m = fmax(m, x);
-                colmx[k] = fmax(colmx[k], x);
+        for (int b = 0; b < kRPW; b += RB) {
+            typename Cost::Raw raw[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+#pragma unroll
+            for (int r0 = 0; r0 < RB; ++r0) {
+                const int r = b + r0;
+                rp[r] = 0.f;
+                if (r < nrows) {
+                    double c[4];
+                    cost.decode(raw[r0], c);
+                    const double A = sA[rbase + r];
+                    const float wt = (float)sWt[rbase + r];
+                    float e[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        e[k] = ok[k] ? __builtin_amdgcn_exp2f((float)(fma(-g2, c[k], V[k]) + A)) : 0.f;
+                    rp[r] = (e[0] + e[1]) + (e[2] + e[3]);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) col32[k] = fmaf(wt, e[k], col32[k]);
+                }
+                if ((r & 7) == 7) {  // FP32 column sums over at most 8 rows, then FP64
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        col64[k] += (double)col32[k];
+                        col32[k] = 0.f;
+                    }
+                }
             }
-            m = wave_max(m);
-            if (t.lane == 0) w.rowmin[(size_t)t.J * n + i] = m * LN2_D;
-            continue;
         }
-        if constexpr (E64) {
-            const double wt = sWt[ir];
-            double rs = 0.0;
+        const double rs = rows_reduce_f32(rp, sRow, t.lane);
+        const int rr = t.lane >> 2;
+        if ((t.lane & 3) == 0 && rr < nrows) w.rowpart[(size_t)t.J * n + t.i0 + rbase + rr] = rs;
+    } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                double e = ok[k] ? exp2(fma(-g2, c[k], V[k]) + A) : 0.0;
-                rs += e;
-                col64[k] = fma(wt, e, col64[k]);
-            }
-            rs = wave_sum(rs);
-            if (t.lane == 0) w.rowpart[(size_t)t.J * n + i] = rs;
-        } else {
-            const float wt = (float)sWt[ir];
-            float rs = 0.f;
+        for (int b = 0; b < kRPW; b += RB) {
+            typename Cost::Raw raw[RB];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float e = ok[k] ? __builtin_amdgcn_exp2f((float)(fma(-g2, c[k], V[k]) + A)) : 0.f;
-                rs += e;
-                col32[k] = fmaf(wt, e, col32[k]);
-            }
-            double rsd = wave_sum((double)rs);
-            if (t.lane == 0) w.rowpart[(size_t)t.J * n + i] = rsd;
-            if ((rr & 7) == 7) {
+            for (int r = 0; r < RB; ++r)
+                if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    col64[k] += (double)col32[k];
-                    col32[k] = 0.f;
+            for (int r0 = 0; r0 < RB; ++r0) {
+                const int r = b + r0;
+                if (r < nrows) {
+                    double c[4];
+                    cost.decode(raw[r0], c);
+                    const double A = sA[rbase + r];
+                    const double wt = sWt[rbase + r];
+                    double rs = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double e = ok[k] ? exp2(fma(-g2, c[k], V[k]) + A) : 0.0;
+                        rs += e;
+                        col64[k] = fma(wt, e, col64[k]);
+                    }
+                    rs = wave_sum(rs);
+                    if (t.lane == 0) w.rowpart[(size_t)t.J * n + t.i0 + rbase + r] = rs;
                 }
             }
         }
     }
-    if (mode == SM_MAX) {
-        double out[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) out[k] = colmx[k] * LN2_D;
-        col_combine_store(sCol, out, t, 2, w.colmin + (size_t)t.I * n, n, t.J * kBC);
-        return;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) col64[k] += (double)col32[k];
     col_combine_store(sCol, col64, t, 0, w.colpart + (size_t)t.I * n, n, t.J * kBC);
     // every tile of row block I writes the same S_I, so the finalizer of any column block
     // reads it from one of the tiles it waited for
@@ -315,40 +514,51 @@ __device__ void tile_r1(const Work& w, const SweepArgs& S, const TileCtx& t, dou
     const double dg = S.gamma - S.gamma_prev;
     const bool ext = dg > 0.0;
     const double inv_dg = ext ? 1.0 / dg : 0.0;
+    double* sX = sWt;  // Round row factors, then weights
     if (t.tid < kBR) {
         int i = t.i0 + t.tid;
-        double s = -INFINITY, a = 0.0, f1 = INFINITY, f2 = INFINITY;
+        double sh = -INFINITY, aa = 0.0, f1 = INFINITY, f2 = INFINITY, x = 0.0;
         if (i < n) {
-            double ui = w.z[i], li = w.lz[i];
-            s = li;
-            a = (ui - li) * LOG2E_D;
-            f1 = ui * inv_g;
-            f2 = ext ? (ui - w.zprev[i]) * inv_dg : f1;
+            const Entry e = entry_after(w, S, i);
+            sh = e.lz;
+            aa = (e.z - e.lz) * LOG2E_D;
+            f1 = e.z * inv_g;
+            f2 = ext ? (e.z - e.zprev) * inv_dg : f1;
+            x = round_x(w.r[i], e.lz);
         }
-        sS[t.tid] = s; sA[t.tid] = a; sF1[t.tid] = f1; sF2[t.tid] = f2;
+        sS[t.tid] = sh; sA[t.tid] = aa; sF1[t.tid] = f1; sF2[t.tid] = f2; sX[t.tid] = x;
+    }
+    {
+        const int j = t.J * kBC + t.tid;
+        double vv = 0.0, g1 = INFINITY, g2v = INFINITY;
+        if (j < n) {
+            const Entry e = entry_after(w, S, n + j);
+            vv = e.z * LOG2E_D;
+            g1 = e.z * inv_g;
+            g2v = ext ? (e.z - e.zprev) * inv_dg : g1;
+        }
+        sCol[t.tid] = vv;
+        sCol[kBC + t.tid] = g1;
+        sCol[2 * kBC + t.tid] = g2v;
     }
     __syncthreads();
     double SI = -INFINITY;
     for (int k = 0; k < kBR; ++k) SI = fmax(SI, sS[k]);
-    if (t.tid < kBR) {
-        int i = t.i0 + t.tid;
-        sWt[t.tid] = (i < n) ? exp(sS[t.tid] - SI) * w.xr[i] : 0.0;
-    }
-    __syncthreads();
-    Cost cost(w);
     const int j0 = t.j0lane;
-    cost.cols(j0);
     double V[4], G1[4], G2[4];
     bool ok[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int j = j0 + k;
-        ok[k] = j < n;
-        double vj = ok[k] ? w.z[n + j] : 0.0;
-        V[k] = vj * LOG2E_D;
-        G1[k] = ok[k] ? vj * inv_g : INFINITY;
-        G2[k] = ok[k] ? (ext ? (vj - w.zprev[n + j]) * inv_dg : vj * inv_g) : INFINITY;
+        ok[k] = j0 + k < n;
+        V[k] = sCol[t.lane * 4 + k];
+        G1[k] = sCol[kBC + t.lane * 4 + k];
+        G2[k] = sCol[2 * kBC + t.lane * 4 + k];
     }
+    __syncthreads();
+    if (t.tid < kBR) sWt[t.tid] = exp(sS[t.tid] - SI) * sX[t.tid];
+    __syncthreads();
+    Cost cost(w, t.i0);
+    cost.cols(j0);
     double col64[4] = {0, 0, 0, 0};
     double cm1[4] = {INFINITY, INFINITY, INFINITY, INFINITY}, cm2[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     const double sc = w.scale;
@@ -358,7 +568,7 @@ __device__ void tile_r1(const Work& w, const SweepArgs& S, const TileCtx& t, dou
         const int i = t.i0 + ir;
         if (i >= n) break;
         double c[4];
-        cost.row(i, j0, c);
+        cost.row(ir, j0, c);
         const double A = sA[ir], wt = sWt[ir], f1 = sF1[ir], f2 = sF2[ir];
         double rm1 = INFINITY, rm2 = INFINITY;
 #pragma unroll
@@ -401,32 +611,40 @@ __device__ void tile_r2(const Work& w, const SweepArgs& S, const TileCtx& t, dou
     const double g2 = S.gamma * w.scale * LOG2E_D;
     if (t.tid < kBR) {
         int i = t.i0 + t.tid;
-        double a = 0.0, f1 = INFINITY, f2 = INFINITY;
+        double aa = 0.0, f1 = INFINITY, f2 = INFINITY;
         if (i < n) {
-            a = (w.z[i] - w.lz[i]) * LOG2E_D;
+            const Entry e = entry_after(w, S, i);
+            aa = (e.z - e.lz) * LOG2E_D;
             f1 = w.fpp[i];
             f2 = w.fpp[n + i];
         }
-        sA[t.tid] = a; sF1[t.tid] = f1; sF2[t.tid] = f2;
+        sA[t.tid] = aa; sF1[t.tid] = f1; sF2[t.tid] = f2;
+    }
+    {
+        const int j = t.J * kBC + t.tid;
+        double vv = 0.0;
+        if (j < n) vv = entry_after(w, S, n + j).z * LOG2E_D;
+        sCol[t.tid] = vv;
     }
     __syncthreads();
-    Cost cost(w);
-    const int j0 = t.j0lane;
-    cost.cols(j0);
     // V is the same as in pass 1, so every exp below is bit-identical to pass 1's and the
     // implicit plan F' = D(x) P D(y) is one matrix across both passes; y is applied in FP64.
+    const int j0 = t.j0lane;
     double V[4], Y[4], GP1[4], GP2[4], EC[4];
     bool ok[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int j = j0 + k;
         ok[k] = j < n;
+        V[k] = sCol[t.lane * 4 + k];
         Y[k] = ok[k] ? w.yc[j] : 0.0;
-        V[k] = ok[k] ? w.z[n + j] * LOG2E_D : 0.0;
         GP1[k] = ok[k] ? w.gp[j] : INFINITY;
         GP2[k] = ok[k] ? w.gp[n + j] : INFINITY;
         EC[k] = ok[k] ? w.errc[j] : 0.0;
     }
+    __syncthreads();
+    Cost cost(w, t.i0);
+    cost.cols(j0);
     double cm1[4] = {INFINITY, INFINITY, INFINITY, INFINITY}, cm2[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     const double sc = w.scale;
     const int rbase = t.wave * kRPW;
@@ -435,7 +653,7 @@ __device__ void tile_r2(const Work& w, const SweepArgs& S, const TileCtx& t, dou
         const int i = t.i0 + ir;
         if (i >= n) break;
         double c[4];
-        cost.row(i, j0, c);
+        cost.row(ir, j0, c);
         const double A = sA[ir], f1 = sF1[ir], f2 = sF2[ir];
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, rm1 = INFINITY, rm2 = INFINITY;
 #pragma unroll
@@ -483,72 +701,52 @@ __device__ void block_dots(double v[kNDot], double* dst, int tid, double* sred)
     __syncthreads();
 }
 
-__device__ __forceinline__ bool in_range(double s, bool e64)
+__device__ __forceinline__ bool in_range(double s, bool e64)  // shifted sum representable
 {
     const double lo = e64 ? 0x1p-900 : 0x1p-64, hi = e64 ? 0x1p900 : 0x1p64;
     return s >= lo && s <= hi;  // false for NaN
 }
 
-// Rows i0 .. i0+kBR-1 of row block I.
-__device__ void finalize_rows(const Work& w, const SweepArgs& S, int I, int tid, bool e64, int mode, double* sred)
+// Finalize entry k of the 2n-vector after a sweep (row k < n, column k - n otherwise):
+// combine the tile partials in a fixed order and add this entry's terms to the dots.
+// fac[I] = exp(S_I - M) (column tiles), M = max_I S_I.
+__device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a, const Entry& e, double g_cur, int k,
+                                               int mode, bool e64, const double* fac, double M, double v[kNDot])
 {
     const int n = w.n;
-    const int i = I * kBR + (tid >> 2);
-    const int q = tid & 3;  // 4 threads per row share the column tiles
-    const bool live = i < n;
-    double v[kNDot];
-#pragma unroll
-    for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
-    if (mode == SM_MAX) {
-        double m = -INFINITY;
-        if (live)
-            for (int J = q; J < w.nct; J += 4) m = fmax(m, w.rowmin[(size_t)J * n + i]);
-        m = fmax(m, __shfl_xor(m, 1, 64));
-        m = fmax(m, __shfl_xor(m, 2, 64));
-        if (live && q == 0) w.lz[i] = m;
-        block_dots(v, w.bdots + (size_t)I * kNDot, tid, sred);
-        return;
-    }
-    if (mode == SM_LSE) {
-        double s = 0.0;
-        if (live)
-            for (int J = q; J < w.nct; J += 4) s += w.rowpart[(size_t)J * n + i];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (live && q == 0) {
-            const double pi = w.p[i];
-            const double sh = w.lz[i] + S.alpha * pi;
-            const double l = sh + log(s);
+    if (k < n) {  // row i = k
+        const int i = k;
+        if (mode == SM_MAX) {
+            double m = -INFINITY;
+            for (int J = 0; J < w.nct; ++J) m = fmax(m, w.rowmin[(size_t)J * n + i]);
+            w.lz[i] = m;
+        } else if (mode == SM_LSE) {
+            double sum = 0.0;
+            for (int J = 0; J < w.nct; ++J) sum += w.rowpart[(size_t)J * n + i];
+            const double l = fma(a.alpha, e.p, e.lz) + log(sum);  // shift used by the sweep
             w.lzt[i] = l;
-            const double gnew = exp(l) - w.rt[i];
-            const double snew = w.logt[i] - l;
-            const double y = gnew - w.g[i];
-            v[D_PHI] = pi * gnew;
+            const double gnew = exp(l) - e.rt;
+            const double snew = e.logt - l;
+            const double y = gnew - g_cur;
+            v[D_PHI] = e.p * gnew;
             v[D_NUM] = -y * snew;
-            v[D_DEN] = y * pi;
+            v[D_DEN] = y * e.p;
             v[D_SG] = snew * gnew;
             v[D_GN] = fabs(gnew);
-            v[D_BAD] = in_range(s, e64) ? 0.0 : 1.0;
-        }
-    } else if (mode == SM_R1) {
-        double m1 = INFINITY, m2 = INFINITY;
-        if (live)
-            for (int J = q; J < w.nct; J += 4) {
+            v[D_BAD] = in_range(sum, e64) ? 0.0 : 1.0;
+        } else if (mode == SM_R1) {
+            double m1 = INFINITY, m2 = INFINITY;
+            for (int J = 0; J < w.nct; ++J) {
                 m1 = fmin(m1, w.rowmin[(size_t)J * n + i]);
                 m2 = fmin(m2, w.rowmin[(size_t)(w.nct + J) * n + i]);
             }
-        m1 = fmin(m1, __shfl_xor(m1, 1, 64)); m1 = fmin(m1, __shfl_xor(m1, 2, 64));
-        m2 = fmin(m2, __shfl_xor(m2, 1, 64)); m2 = fmin(m2, __shfl_xor(m2, 2, 64));
-        if (live && q == 0) {
             w.fpp[i] = m1;
             w.fpp[n + i] = m2;
             v[D_RF1] = w.r[i] * m1;
             v[D_RF2] = w.r[i] * m2;
-        }
-    } else {  // SM_R2
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, m1 = INFINITY, m2 = INFINITY;
-        if (live)
-            for (int J = q; J < w.nct; J += 4) {
+        } else {  // SM_R2
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, m1 = INFINITY, m2 = INFINITY;
+            for (int J = 0; J < w.nct; ++J) {
                 const size_t o = (size_t)J * n + i;
                 s0 += w.rowpart[o];
                 s1 += w.rowpart2[o];
@@ -556,111 +754,63 @@ __device__ void finalize_rows(const Work& w, const SweepArgs& S, int I, int tid,
                 m1 = fmin(m1, w.rowmin[o]);
                 m2 = fmin(m2, w.rowmin[(size_t)(w.nct + J) * n + i]);
             }
-#pragma unroll
-        for (int o = 1; o <= 2; o <<= 1) {
-            s0 += __shfl_xor(s0, o, 64);
-            s1 += __shfl_xor(s1, o, 64);
-            s2 += __shfl_xor(s2, o, 64);
-            m1 = fmin(m1, __shfl_xor(m1, o, 64));
-            m2 = fmin(m2, __shfl_xor(m2, o, 64));
-        }
-        if (live && q == 0) {
-            const double ex = w.xr[i] * exp(w.lz[i]);
-            const double rF = ex * s0;             // r(F')_i
-            const double er = w.r[i] - rF;         // err_r
+            const double ex = w.xr[i] * exp(e.lz);
+            const double er = w.r[i] - ex * s0;  // err_r = r - r(F')
             v[D_A] = ex * s1;
             v[D_ERRR] = er;
             v[D_EC] = er * s2;
             v[D_RFP1] = w.r[i] * m1;
             v[D_RFP2] = w.r[i] * m2;
         }
-    }
-    block_dots(v, w.bdots + (size_t)I * kNDot, tid, sred);
-}
-
-// Columns of column block J (one thread per column).
-__device__ void finalize_cols(const Work& w, const SweepArgs& S, int J, int tid, bool e64, int mode, double* sm,
-                              double* sred)
-{
-    double* sfac = sm;  // [nrt] (nrt <= 1024 < kSmem)
-    double* pM = sm + 1300;
-    const int n = w.n;
-    const int j = J * kBC + tid;
-    const bool live = j < n;
-    double v[kNDot];
-#pragma unroll
-    for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
-    if (mode == SM_MAX) {
-        double m = -INFINITY;
-        if (live)
-            for (int I = 0; I < w.nrt; ++I) m = fmax(m, w.colmin[(size_t)I * n + j]);
-        if (live) w.lz[n + j] = m;
-        block_dots(v, w.bdots + (size_t)(w.nrt + J) * kNDot, tid, sred);
         return;
     }
-    if (mode == SM_LSE || mode == SM_R1) {
-        // combine tile partials taken relative to S_I
-        if (tid == 0) {
-            double M = -INFINITY;
-            for (int I = 0; I < w.nrt; ++I) M = fmax(M, w.tshift[I]);
-            *pM = M;
-        }
-        __syncthreads();
-        const double M = *pM;
-        for (int I = tid; I < w.nrt; I += kWG) sfac[I] = exp(w.tshift[I] - M);
-        __syncthreads();
-        double s = 0.0;
-        if (live)
-            for (int I = 0; I < w.nrt; ++I) s = fma(w.colpart[(size_t)I * n + j], sfac[I], s);
+    const int j = k - n;  // column
+    if (mode == SM_MAX) {
+        double m = -INFINITY;
+        for (int I = 0; I < w.nrt; ++I) m = fmax(m, w.colmin[(size_t)I * n + j]);
+        w.lz[n + j] = m;
+    } else if (mode == SM_LSE || mode == SM_R1) {
+        double sum = 0.0;
+        for (int I = 0; I < w.nrt; ++I) sum = fma(w.colpart[(size_t)I * n + j], fac[I], sum);
         if (mode == SM_LSE) {
-            if (live) {
-                const double pj = w.p[n + j];
-                const double l = M + log(s);
-                w.lzt[n + j] = l;
-                const double gnew = exp(l) - w.rt[n + j];
-                const double snew = w.logt[n + j] - l;
-                const double y = gnew - w.g[n + j];
-                v[D_PHI] = pj * gnew;
-                v[D_NUM] = -y * snew;
-                v[D_DEN] = y * pj;
-                v[D_SG] = snew * gnew;
-                v[D_GN] = fabs(gnew);
-                v[D_BAD] = in_range(s, e64) ? 0.0 : 1.0;
-            }
-        } else {  // R1: c(F)_j, y_j, err_c, g'_j
+            const double l = M + log(sum);
+            w.lzt[n + j] = l;
+            const double gnew = exp(l) - e.rt;
+            const double snew = e.logt - l;
+            const double y = gnew - g_cur;
+            v[D_PHI] = e.p * gnew;
+            v[D_NUM] = -y * snew;
+            v[D_DEN] = y * e.p;
+            v[D_SG] = snew * gnew;
+            v[D_GN] = fabs(gnew);
+            v[D_BAD] = in_range(sum, e64) ? 0.0 : 1.0;
+        } else {  // R1: c(F)_j, y_j = c_j / c(F)_j ^ 1, err_c, g'_j (Alg. 3)
             double m1 = INFINITY, m2 = INFINITY;
-            if (live)
-                for (int I = 0; I < w.nrt; ++I) {
-                    m1 = fmin(m1, w.colmin[(size_t)I * n + j]);
-                    m2 = fmin(m2, w.colmin[(size_t)(w.nrt + I) * n + j]);
-                }
-            if (live) {
-                const double cF = exp(M) * s;
-                const double cj = w.c[j];
-                const double y = (cF > 0.0) ? fmin(cj / cF, 1.0) : 1.0;
-                const double ec = cj - y * cF;
-                w.yc[j] = y;
-                w.errc[j] = ec;
-                w.gp[j] = m1;
-                w.gp[n + j] = m2;
-                v[D_CG1] = cj * m1;
-                v[D_CG2] = cj * m2;
-                v[D_ERRC] = ec;
-            }
-        }
-    } else {  // R2: g''_j
-        double m1 = INFINITY, m2 = INFINITY;
-        if (live)
             for (int I = 0; I < w.nrt; ++I) {
                 m1 = fmin(m1, w.colmin[(size_t)I * n + j]);
                 m2 = fmin(m2, w.colmin[(size_t)(w.nrt + I) * n + j]);
             }
-        if (live) {
-            v[D_CGP1] = w.c[j] * m1;
-            v[D_CGP2] = w.c[j] * m2;
+            const double cF = exp(M) * sum;
+            const double cj = w.c[j];
+            const double y = (cF > 0.0) ? fmin(cj / cF, 1.0) : 1.0;
+            const double ec = cj - y * cF;
+            w.yc[j] = y;
+            w.errc[j] = ec;
+            w.gp[j] = m1;
+            w.gp[n + j] = m2;
+            v[D_CG1] = cj * m1;
+            v[D_CG2] = cj * m2;
+            v[D_ERRC] = ec;
         }
+    } else {  // R2: g''_j
+        double m1 = INFINITY, m2 = INFINITY;
+        for (int I = 0; I < w.nrt; ++I) {
+            m1 = fmin(m1, w.colmin[(size_t)I * n + j]);
+            m2 = fmin(m2, w.colmin[(size_t)(w.nrt + I) * n + j]);
+        }
+        v[D_CGP1] = w.c[j] * m1;
+        v[D_CGP2] = w.c[j] * m2;
     }
-    block_dots(v, w.bdots + (size_t)(w.nrt + J) * kNDot, tid, sred);
 }
 
 // ------------------------------------------------------------------ scalar state machine
@@ -863,171 +1013,213 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
 }
 
 // ------------------------------------------------------------------ the sweep kernel
-template <bool E64, bool ROUND>
+// Cost types of a kernel instance (one per stored dtype / point metric).
+enum CostCode { CC_F64 = 0, CC_F32 = 1, CC_F16 = 2, CC_BF16 = 3, CC_PTS_SQ = 4, CC_PTS_L1 = 5 };
+template <int CC> struct CostOf;
+template <> struct CostOf<CC_F64> { using T = DenseCost<MDOT_DT_F64>; };
+template <> struct CostOf<CC_F32> { using T = DenseCost<MDOT_DT_F32>; };
+template <> struct CostOf<CC_F16> { using T = DenseCost<MDOT_DT_F16>; };
+template <> struct CostOf<CC_BF16> { using T = DenseCost<MDOT_DT_BF16>; };
+template <> struct CostOf<CC_PTS_SQ> { using T = PointCost<1>; };
+template <> struct CostOf<CC_PTS_L1> { using T = PointCost<2>; };
+
+template <int CC, bool E64, bool ROUND>
 __device__ __forceinline__ void sweep_tiles(const Work& w, const SweepArgs& a, const TileCtx& t, int mode, double* smem)
 {
-#define MDOT_DISPATCH(COST)                                                  \
-    do {                                                                     \
-        if constexpr (!ROUND) tile_lse<COST, E64>(w, a, t, mode, smem);      \
-        else if (mode == SM_R1) tile_r1<COST, E64>(w, a, t, smem);           \
-        else tile_r2<COST, E64>(w, a, t, smem);                              \
-    } while (0)
-    if (w.cost_kind == MDOT_COST_DENSE) {
-        switch (w.dtype) {
-            case MDOT_DT_F32: MDOT_DISPATCH(DenseCost<MDOT_DT_F32>); break;
-            case MDOT_DT_F64: MDOT_DISPATCH(DenseCost<MDOT_DT_F64>); break;
-            case MDOT_DT_F16: MDOT_DISPATCH(DenseCost<MDOT_DT_F16>); break;
-            default: MDOT_DISPATCH(DenseCost<MDOT_DT_BF16>); break;
-        }
-    } else if (w.cost_kind == MDOT_COST_POINTS_SQEUCLID) {
-        MDOT_DISPATCH(PointCost<1>);
+    using Cost = typename CostOf<CC>::T;
+    if constexpr (!ROUND) {
+        if (mode == SM_MAX) tile_max<Cost>(w, a, t, smem);
+        else tile_lse<Cost, E64>(w, a, t, smem);
     } else {
-        MDOT_DISPATCH(PointCost<2>);
+        if (mode == SM_R1) tile_r1<Cost, E64>(w, a, t, smem);
+        else tile_r2<Cost, E64>(w, a, t, smem);
     }
-#undef MDOT_DISPATCH
 }
 
 // Shared body of the two sweep kernels. ROUND = false: LSE and max sweeps (the hot path);
 // ROUND = true: the two Round/certificate sweeps, kept in their own kernel so their larger
 // register footprint does not lower the occupancy of the LSE sweep.
-template <bool ROUND>
-__device__ __forceinline__ void sweep_kernel_body(const Work& w, int parity)
+template <int CC, bool ROUND>
+__device__ __forceinline__ void sweep_kernel_body(const Work& w, int parity, int blk, double* smem)
 {
-    __shared__ double smem[kSmem];
-    __shared__ double sred[kNDot * 4];
-    __shared__ int sflag[2];
-    const State* Sp = w.st + (parity ^ 1);  // written by this step's control kernel
+    const State* Sp = w.st + parity;
     const int mode = Sp->sweep_mode;
     if (mode == SM_NONE || Sp->done) return;
     if ((mode == SM_R1 || mode == SM_R2) != ROUND) return;
     const bool e64 = Sp->exp64 != 0;
-    const int ph = Sp->ls_phase;
-    SweepArgs a;
-    a.alpha = (mode == SM_LSE && (ph == LS_TRIAL || ph == LS_FORCE)) ? Sp->alpha : 0.0;
-    a.gamma = Sp->gamma;
-    a.gamma_prev = Sp->gamma_prev;
+    const SweepArgs a = args_of(Sp);
     TileCtx t;
     t.tid = threadIdx.x;
     t.lane = t.tid & 63;
     t.wave = t.tid >> 6;
-    t.I = blockIdx.x / w.nct;
-    t.J = blockIdx.x % w.nct;
+    t.I = blk / w.nct;
+    t.J = blk % w.nct;
     t.i0 = t.I * kBR;
     t.j0lane = t.J * kBC + t.lane * 4;
-    if (e64) sweep_tiles<true, ROUND>(w, a, t, mode, smem);
-    else sweep_tiles<false, ROUND>(w, a, t, mode, smem);
-
-    // arrival: the last tile of row block I / column block J finalizes it
-    __threadfence();
-    __syncthreads();
-    if (t.tid == 0) {
-        uint32_t x = __hip_atomic_fetch_add(&w.cnt[t.I], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t y = __hip_atomic_fetch_add(&w.cnt[w.nrt + t.J], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        sflag[0] = (x == (uint32_t)w.nct - 1);
-        sflag[1] = (y == (uint32_t)w.nrt - 1);
-    }
-    __syncthreads();
-    const bool lastR = sflag[0], lastC = sflag[1];
-    if (!lastR && !lastC) return;
-    __threadfence();
-    if (lastR) {
-        finalize_rows(w, a, t.I, t.tid, e64, mode, sred);
-        if (t.tid == 0) w.cnt[t.I] = 0;
-    }
-    if (lastC) {
-        finalize_cols(w, a, t.J, t.tid, e64, mode, smem, sred);
-        if (t.tid == 0) w.cnt[w.nrt + t.J] = 0;
-    }
+    if (e64) sweep_tiles<CC, true, ROUND>(w, a, t, mode, smem);
+    else sweep_tiles<CC, false, ROUND>(w, a, t, mode, smem);
 }
 
+template <int CC>
 __global__ void __launch_bounds__(kWG) k_sweep(const Work* __restrict__ wp, int parity)
 {
-    sweep_kernel_body<false>(*wp, parity);
+    __shared__ double smem[kSmem];
+    sweep_kernel_body<CC, false>(*wp, parity, blockIdx.x, smem);
 }
 
+template <int CC>
 __global__ void __launch_bounds__(kWG) k_round(const Work* __restrict__ wp, int parity)
 {
-    sweep_kernel_body<true>(*wp, parity);
+    __shared__ double smem[kSmem];
+    sweep_kernel_body<CC, true>(*wp, parity, blockIdx.x, smem);
 }
 
-// ------------------------------------------------------------------ the control kernel
-__global__ void __launch_bounds__(kVecWG) k_ctrl(const Work* __restrict__ wp, int parity)
+// ------------------------------------------------------------------ the finalize kernel
+// One thread per entry of the 2n-vectors. Reads state slot `parity` (the one the sweeps of
+// this step used) and writes the next state into the other slot.
+struct FinShared {
+    double fac[1024];
+    double red[kNDot * 4];
+    double glob[kNDot];
+    double M;
+    int last;
+};
+
+// Finalize block `blk` of `nblk` blocks of one problem (entries blk * kVecWG + tid).
+__device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int nblk, FinShared& sh)
 {
-    __shared__ double sred[kNDot * 4];
-    __shared__ double sglob[kNDot];
-    __shared__ double sf[8];
-    __shared__ int si[4];
-    const Work w = *wp;
+    double* sfac = sh.fac;
+    double* sred = sh.red;
+    double* sglob = sh.glob;
+    const State* Sp = w.st + parity;
     const int tid = threadIdx.x;
-    // fixed-order reduction of the previous sweep's block results (identical in every WG)
-    const int nb = w.nrt + w.nct;
+    const int n = w.n;
+    const int k = blk * kVecWG + tid;
+    const SweepArgs a = args_of(Sp);
+    const int mode = Sp->sweep_mode;
+    const bool done = Sp->done != 0;
+    const bool e64 = Sp->exp64 != 0;
+    // 1. store the pending vector update of this entry
+    Entry e;
+    double g_cur = 0.0;
+    if (k < 2 * n) {
+        e = entry_after(w, a, k);
+        const int va = a.va;
+        if (va & (VA_ACCEPT | VA_STAGE_INIT)) {
+            w.z[k] = e.z;
+            w.p[k] = e.p;
+            w.lz[k] = e.lz;
+        }
+        if (va & VA_STAGE_INIT) {
+            w.rt[k] = e.rt;
+            w.logt[k] = e.logt;
+            w.zprev[k] = e.zprev;
+            w.g[k] = 0.0;
+        } else if (va & VA_ACCEPT) {
+            w.g[k] = exp(e.lz) - e.rt;
+        }
+        if (va & VA_SAVE_BEST) w.zbest[k] = e.zacc;
+        if ((va & VA_ROUND_PREP) && k < n) w.xr[k] = round_x(w.r[k], e.lz);
+        g_cur = (va & (VA_ACCEPT | VA_STAGE_INIT)) ? ((va & VA_STAGE_INIT) ? 0.0 : exp(e.lz) - e.rt) : w.g[k];
+    }
+    if (done || mode == SM_NONE) {
+        if (blk == 0 && tid == 0) {
+            State S = *Sp;
+            S.vec_action = 0;
+            w.st[parity ^ 1] = S;
+        }
+        return;
+    }
+    // 2. combine the tile partials of this entry
+    if (mode == SM_LSE || mode == SM_R1) {
+        if (tid == 0) {
+            double M = -INFINITY;
+            for (int I = 0; I < w.nrt; ++I) M = fmax(M, w.tshift[I]);
+            sh.M = M;
+        }
+        __syncthreads();
+        for (int I = tid; I < w.nrt; I += kVecWG) sfac[I] = exp(w.tshift[I] - sh.M);
+        __syncthreads();
+    }
     double v[kNDot];
 #pragma unroll
     for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
-    for (int b = tid; b < nb; b += kVecWG)
+    if (k < 2 * n) finalize_entry(w, a, e, g_cur, k, mode, e64, sfac, sh.M, v);
+    block_dots(v, w.bdots + (size_t)blk * kNDot, tid, sred);
+    // 3. the last workgroup reduces the block dots in a fixed order and decides
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        const uint32_t old = __hip_atomic_fetch_add(&w.cnt[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        sh.last = (old == (uint32_t)nblk - 1);
+    }
+    __syncthreads();
+    if (!sh.last) return;
+    __threadfence();
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
+    for (int b = tid; b < nblk; b += kVecWG)
 #pragma unroll
         for (int d = 0; d < kNDot; ++d) v[d] += w.bdots[(size_t)b * kNDot + d];
     block_dots(v, sglob, tid, sred);
     if (tid == 0) {
-        State S = w.st[parity];
-        const DevParams P = *w.prm;
-        if (S.pending && !S.done) {
-            double sum[kNDot];
+        double sum[kNDot];
 #pragma unroll
-            for (int d = 0; d < kNDot; ++d) sum[d] = sglob[d];
-            decide(S, P, sum);
-        }
-        si[0] = S.vec_action;
-        si[1] = S.reset;
-        si[2] = S.stage;
-        sf[0] = S.alpha_acc;
-        sf[1] = S.beta;
-        sf[2] = S.w;
-        sf[3] = S.ws_ratio;
-        S.vec_action = 0;
-        S.pending = (S.sweep_mode != SM_NONE && !S.done);
-        if (blockIdx.x == 0) w.st[parity ^ 1] = S;
+        for (int d = 0; d < kNDot; ++d) sum[d] = sglob[d];
+        State S = *Sp;
+        const DevParams P = *w.prm;
+        decide(S, P, sum);
+        w.st[parity ^ 1] = S;
+        w.cnt[0] = 0;
     }
-    __syncthreads();
-    const int va = si[0];
-    if (va == 0) return;
-    const int n = w.n;
-    const int k = blockIdx.x * blockDim.x + tid;
-    if (k >= 2 * n) return;
-    double zk = w.z[k];
-    if (va & VA_ACCEPT) {  // (u, v) += alpha p; new direction p = s + beta p, or s on reset (Alg. 2)
-        zk = fma(sf[0], w.p[k], zk);
-        w.z[k] = zk;
-        const double l = w.lzt[k];
-        w.lz[k] = l;
-        w.g[k] = exp(l) - w.rt[k];
-        const double sdir = w.logt[k] - l;  // Sinkhorn direction, eq. (sinkhorn-direction)
-        w.p[k] = si[1] ? sdir : fma(sf[1], w.p[k], sdir);
+}
+
+__global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int parity)
+{
+    __shared__ FinShared sh;
+    fin_body(*wp, parity, blockIdx.x, gridDim.x, sh);
+}
+
+// ------------------------------------------------------------------ batched kernels
+__device__ __forceinline__ int batch_item(const int32_t* prefix, int nitems, int g)
+{
+    int lo = 0, hi = nitems - 1;  // largest b with prefix[b] <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid - 1;
     }
-    if (va & VA_SAVE_BEST) w.zbest[k] = zk;
-    if (va & VA_STAGE_INIT) {  // Alg. 1: smoothing, rank-1 start or warm start eq. (approx-znext)
-        const double m = (k < n) ? w.r[k] : w.c[k - n];
-        const double rt = (1.0 - sf[2]) * m + sf[2] / n;
-        const double lt = log(rt);
-        w.rt[k] = rt;
-        w.logt[k] = lt;
-        if (si[2] == 1) {
-            zk = lt;
-            w.zprev[k] = lt;  // z^0 at gamma^0 = 0
-        } else {
-            const double zp = w.zprev[k];
-            w.zprev[k] = zk;
-            zk = zk + sf[3] * (zk - zp);
-        }
-        w.z[k] = zk;
-        w.p[k] = 0.0;
-        w.g[k] = 0.0;
-        w.lz[k] = lt;  // predicted log marginals of the warm-started plan (row shifts)
+    return lo;
+}
+
+template <int CC, bool ROUND>
+__global__ void __launch_bounds__(kWG) k_sweep_batch(const BatchDesc* __restrict__ bd, int parity)
+{
+    __shared__ double smem[kSmem];
+    const int total = bd->total_tiles, nitems = bd->nitems;
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int b = batch_item(bd->tile_prefix, nitems, g);
+        sweep_kernel_body<CC, ROUND>(*bd->items[b], parity, g - bd->tile_prefix[b], smem);
+        __syncthreads();
     }
-    if ((va & VA_ROUND_PREP) && k < n) {  // Alg. 3: x = r / r(P) ^ 1
-        const double rp = exp(w.lz[k]);
-        w.xr[k] = (rp > 0.0) ? fmin(w.r[k] / rp, 1.0) : 1.0;
+}
+
+__global__ void __launch_bounds__(kVecWG) k_fin_batch(const BatchDesc* __restrict__ bd, int parity)
+{
+    __shared__ FinShared sh;
+    const int total = bd->total_fin, nitems = bd->nitems;
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int b = batch_item(bd->fin_prefix, nitems, g);
+        fin_body(*bd->items[b], parity, g - bd->fin_prefix[b], bd->fin_prefix[b + 1] - bd->fin_prefix[b], sh);
+        __syncthreads();
     }
+}
+
+__global__ void k_gather_done(const BatchDesc* __restrict__ bd, int* out)
+{
+    const int b = threadIdx.x;
+    if (b < bd->nitems) out[b] = bd->items[b]->st[0].done;
 }
 
 // ------------------------------------------------------------------ set-up kernels
@@ -1053,7 +1245,6 @@ __global__ void k_init(const Work* __restrict__ wp)
     S.best_ub = INFINITY;
     S.best_lb = -INFINITY;
     S.best_gamma = S.gamma;
-    S.pending = 0;
     w.st[0] = S;
     w.st[1] = S;
     for (int k = 0; k < w.nrt + w.nct; ++k) w.cnt[k] = 0;
@@ -1098,14 +1289,14 @@ __device__ void cost_range_body(const Work& w, double* mn, double* mx)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int I = blockIdx.x / w.nct, J = blockIdx.x % w.nct;
     const int j0 = J * kBC + lane * 4;
-    Cost cost(w);
+    Cost cost(w, I * kBR);
     cost.cols(j0);
     double lo = INFINITY, hi = -INFINITY;
     for (int rr = 0; rr < kRPW; ++rr) {
         const int i = I * kBR + wave * kRPW + rr;
         if (i >= n) break;
         double c[4];
-        cost.row(i, j0, c);
+        cost.row(wave * kRPW + rr, j0, c);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (j0 + k < n) {
@@ -1118,22 +1309,12 @@ __device__ void cost_range_body(const Work& w, double* mn, double* mx)
     *mx = hi;
 }
 
+template <int CC>
 __global__ void __launch_bounds__(kWG) k_cost_range(const Work* __restrict__ wp, double* part)
 {
     const Work w = *wp;
     double lo, hi;
-    if (w.cost_kind == MDOT_COST_DENSE) {
-        switch (w.dtype) {
-            case MDOT_DT_F32: cost_range_body<DenseCost<MDOT_DT_F32>>(w, &lo, &hi); break;
-            case MDOT_DT_F64: cost_range_body<DenseCost<MDOT_DT_F64>>(w, &lo, &hi); break;
-            case MDOT_DT_F16: cost_range_body<DenseCost<MDOT_DT_F16>>(w, &lo, &hi); break;
-            default: cost_range_body<DenseCost<MDOT_DT_BF16>>(w, &lo, &hi); break;
-        }
-    } else if (w.cost_kind == MDOT_COST_POINTS_SQEUCLID) {
-        cost_range_body<PointCost<1>>(w, &lo, &hi);
-    } else {
-        cost_range_body<PointCost<2>>(w, &lo, &hi);
-    }
+    cost_range_body<typename CostOf<CC>::T>(w, &lo, &hi);
     __shared__ double s0[kWG], s1[kWG];
     const int t = threadIdx.x;
     s0[t] = lo;
@@ -1154,16 +1335,23 @@ __global__ void __launch_bounds__(kWG) k_cost_range(const Work* __restrict__ wp,
 }
 
 // Copy the reported potentials out, gauge-fixed so that sum(u) = sum(v) (the dual is
-// invariant under (u + delta, v - delta), paper Sec. 4.1 footnote).
+// invariant under (u + delta, v - delta), paper Sec. 4.1 footnote). Reads the newest state
+// (slot 0 after an even number of steps): when the save of the best potentials is still
+// pending there, they are the accepted iterate of that state.
+__device__ __forceinline__ double best_entry(const Work& w, const SweepArgs& a, int k)
+{
+    return (a.va & VA_SAVE_BEST) ? entry_after(w, a, k).zacc : w.zbest[k];
+}
+
 __global__ void k_finish(const Work* __restrict__ wp, double* u_out, double* v_out)
 {
-    const Work w = *wp;
     __shared__ double sred[kWG];
     __shared__ double sdelta;
+    const Work& w = *wp;
+    const SweepArgs a = args_of(w.st);
     const int n = w.n, t = threadIdx.x;
-    const double* zb = w.zbest;
     double s = 0.0;
-    for (int i = t; i < n; i += kWG) s += zb[n + i] - zb[i];
+    for (int i = t; i < n; i += kWG) s += best_entry(w, a, n + i) - best_entry(w, a, i);
     sred[t] = s;
     __syncthreads();
     for (int h = kWG / 2; h > 0; h >>= 1) {
@@ -1174,18 +1362,73 @@ __global__ void k_finish(const Work* __restrict__ wp, double* u_out, double* v_o
     __syncthreads();
     const double dl = sdelta;
     for (int i = t; i < n; i += kWG) {
-        if (u_out) u_out[i] = zb[i] + dl;
-        if (v_out) v_out[i] = zb[n + i] - dl;
+        if (u_out) u_out[i] = best_entry(w, a, i) + dl;
+        if (v_out) v_out[i] = best_entry(w, a, n + i) - dl;
     }
 }
 
 // ------------------------------------------------------------------ launchers
-int launch_step(const Work* wd, int n, int tiles, int parity, void* stream)
+int cost_code_of(int cost_kind, int dtype)
+{
+    if (cost_kind == MDOT_COST_POINTS_SQEUCLID) return CC_PTS_SQ;
+    if (cost_kind == MDOT_COST_POINTS_L1) return CC_PTS_L1;
+    switch (dtype) {
+        case MDOT_DT_F64: return CC_F64;
+        case MDOT_DT_F16: return CC_F16;
+        case MDOT_DT_BF16: return CC_BF16;
+        default: return CC_F32;
+    }
+}
+
+static int cost_code(const Work& w) { return cost_code_of(w.cost_kind, w.dtype); }
+
+#define MDOT_CC_SWITCH(cc, F)         \
+    switch (cc) {                     \
+        case CC_F64: F(CC_F64); break;       \
+        case CC_F32: F(CC_F32); break;       \
+        case CC_F16: F(CC_F16); break;       \
+        case CC_BF16: F(CC_BF16); break;     \
+        case CC_PTS_SQ: F(CC_PTS_SQ); break; \
+        default: F(CC_PTS_L1); break;        \
+    }
+
+int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_ctrl, dim3((2 * n + kVecWG - 1) / kVecWG), dim3(kVecWG), 0, s, wd, parity);
-    hipLaunchKernelGGL(k_sweep, dim3(tiles), dim3(kWG), 0, s, wd, parity);
-    hipLaunchKernelGGL(k_round, dim3(tiles), dim3(kWG), 0, s, wd, parity);
+    const int tiles = hw.nrt * hw.nct;
+#define L_(CC)                                                                      \
+    hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity);     \
+    hipLaunchKernelGGL(k_round<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity)
+    MDOT_CC_SWITCH(cost_code(hw), L_)
+#undef L_
+    hipLaunchKernelGGL(k_fin, dim3((2 * hw.n + kVecWG - 1) / kVecWG), dim3(kVecWG), 0, s, wd, parity);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream)
+{
+    const int tiles = hw.nrt * hw.nct;
+#define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, parity)
+    MDOT_CC_SWITCH(cost_code(hw), L_)
+#undef L_
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_step_batch(int cc, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+#define L_(CC)                                                                                        \
+    hipLaunchKernelGGL((k_sweep_batch<CC, false>), dim3(sweep_grid), dim3(kWG), 0, s, bd, parity);   \
+    hipLaunchKernelGGL((k_sweep_batch<CC, true>), dim3(sweep_grid), dim3(kWG), 0, s, bd, parity)
+    MDOT_CC_SWITCH(cc, L_)
+#undef L_
+    hipLaunchKernelGGL(k_fin_batch, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_gather_done(const BatchDesc* bd, int* out, void* stream)
+{
+    hipLaunchKernelGGL(k_gather_done, dim3(1), dim3(kMaxBatch), 0, (hipStream_t)stream, bd, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1201,9 +1444,12 @@ int launch_intake(const Work* wd, double* out8, void* stream)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_cost_range(const Work* wd, int tiles, double* part, void* stream)
+int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream)
 {
-    hipLaunchKernelGGL(k_cost_range, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, part);
+    const int tiles = hw.nrt * hw.nct;
+#define L_(CC) hipLaunchKernelGGL(k_cost_range<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, part)
+    MDOT_CC_SWITCH(cost_code(hw), L_)
+#undef L_
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -74,6 +74,13 @@ def lib():
         L.mdot_round_certify.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, dp, dp, ct.c_double,
                                          dp, dp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                                          ct.POINTER(ct.c_double)]
+        L.mdot_bench_sweep.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, ct.c_int, ct.c_int,
+                                       ct.POINTER(ct.c_double)]
+        L.mdot_submit.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, ct.POINTER(Params), dp, dp,
+                                  ct.POINTER(ct.c_uint64)]
+        L.mdot_run.argtypes = [vp, ct.c_int, ct.POINTER(ct.c_int)]
+        L.mdot_poll.argtypes = [vp, ct.c_uint64, ct.c_int, ct.POINTER(Result)]
+        L.mdot_inflight.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_size_t)]
         _lib = L
     return _lib
 
@@ -192,6 +199,47 @@ class Context:
         rc = lib().mdot_lse2(self._h, ct.byref(cost), _ptr(u), _ptr(v), float(gamma), _ptr(shift), prec,
                              _ptr(lr_out), _ptr(lc_out))
         return self._check(rc)
+
+    # ---- serving: continuous batching
+    def submit(self, cost: CostDesc, r, c, target_gap: float = 1e-6, params: Params | None = None,
+               u_out=None, v_out=None) -> int | None:
+        """Admit one solve; returns its ticket, or None when no slot / HBM budget is free."""
+        t = ct.c_uint64()
+        rc = lib().mdot_submit(self._h, ct.byref(cost), _ptr(r), _ptr(c), float(target_gap),
+                               ct.byref(params) if params is not None else None, _ptr(u_out), _ptr(v_out),
+                               ct.byref(t))
+        if rc == -6:
+            return None
+        self._check(rc)
+        return t.value
+
+    def run(self, steps: int = 8) -> int:
+        """Advance all solves in flight; returns how many finished."""
+        nd = ct.c_int()
+        self._check(lib().mdot_run(self._h, int(steps), ct.byref(nd)))
+        return nd.value
+
+    def poll(self, ticket: int, wait: bool = False) -> SolveResult | None:
+        res = Result()
+        rc = lib().mdot_poll(self._h, ct.c_uint64(ticket), 1 if wait else 0, ct.byref(res))
+        if rc == 2:
+            return None
+        self._check(rc)
+        return SolveResult(status=res.status, **{f: getattr(res, f) for f, _ in Result._fields_ if f != "status"})
+
+    def inflight(self) -> tuple[int, int]:
+        a, b = ct.c_int(), ct.c_size_t()
+        self._check(lib().mdot_inflight(self._h, ct.byref(a), ct.byref(b)))
+        return a.value, b.value
+
+    def bench_sweep(self, cost: CostDesc, u, v, gamma: float, precision: str = "f32", iters: int = 100) -> float:
+        """Mean milliseconds per fused LSE sweep (HIP events on the context stream)."""
+        ms = ct.c_double()
+        prec = PREC_F64 if precision == "f64" else PREC_F32
+        rc = lib().mdot_bench_sweep(self._h, ct.byref(cost), _ptr(u), _ptr(v), float(gamma), prec, int(iters),
+                                    ct.byref(ms))
+        self._check(rc)
+        return ms.value
 
     def round_certify(self, cost: CostDesc, u, v, gamma: float, r, c, u_prev=None, v_prev=None,
                       gamma_prev: float = 0.0):
