@@ -103,7 +103,6 @@ static int fail(mdot_ctx* ctx, int code, const char* fmt, ...)
 
 static inline int tiles_r(int n) { return (n + kBR - 1) / kBR; }
 static inline int tiles_c(int n) { return (n + kBC - 1) / kBC; }
-static inline int fin_blocks(int n) { return (2 * n + kVecWG - 1) / kVecWG; }
 
 // Bytes of workspace for size n (see Work in mdot_internal.h).
 static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
@@ -115,7 +114,7 @@ static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
         2 * N, 2 * N,                                                 // gp fpp
         nct * N, nrt * N, nct * N, nct * N,                           // rowpart colpart rowpart2 rowpart3
         2 * nct * N, 2 * nrt * N,                                     // rowmin colmin
-        nrt, (size_t)fin_blocks(n) * kNDot,                           // tshift bdots
+        nrt, (size_t)fin_grid(n) * kNDot,                           // tshift bdots
     };
     size_t off = 0;
     const int k = sizeof(counts) / sizeof(counts[0]);
@@ -123,8 +122,7 @@ static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
         if (out_offsets) out_offsets[i] = off;
         off += ((counts[i] * sizeof(double) + 255) / 256) * 256;
     }
-    if (out_offsets) out_offsets[k] = off;  // counters
-    off += 256;
+    if (out_offsets) out_offsets[k] = off;
     return off;
 }
 
@@ -210,7 +208,6 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
                       &w.colmin, &w.tshift, &w.bdots};
     const int k = sizeof(vec) / sizeof(vec[0]);
     for (int i = 0; i < k; ++i) *vec[i] = (double*)(b + off[i]);
-    w.cnt = (uint32_t*)(b + off[k]);
     w.st = (State*)((char*)pb.d_work + sizeof(Work));
     w.prm = pb.d_prm;
     HIPCHK(ctx, hipMemcpyAsync(pb.d_work, &w, sizeof w, hipMemcpyHostToDevice, ctx->stream));
@@ -451,7 +448,7 @@ static int rebuild_batch(mdot_ctx* ctx)
         B.tile_prefix[m] = nt;
         B.fin_prefix[m] = nf;
         nt += w.nrt * w.nct;
-        nf += fin_blocks(w.n);
+        nf += fin_grid(w.n);
         ++m;
     }
     B.nitems = m;
@@ -662,7 +659,6 @@ static int standalone_setup(mdot_ctx* ctx, const mdot_cost_desc* cost, const dou
     S.best_ub = INFINITY;
     S.best_lb = -INFINITY;
     HIPCHK(ctx, hipMemcpyAsync(w.st, &S, sizeof S, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(w.cnt, 0, sizeof(uint32_t), ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // the pinned blocks are reused later
     return MDOT_OK;
 }

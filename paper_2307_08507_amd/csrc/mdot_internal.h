@@ -15,6 +15,23 @@ constexpr int kRPW = 16;
 constexpr int kBR = 4 * kRPW;
 constexpr int kVecWG = 256;
 
+// Finalize kernel geometry: the tile partials of each 2n-vector entry are combined by a group of
+// L lanes (a power of two, at most 64) that each fold about kFinPer of them; the groups fill
+// fin_vblocks(n) virtual workgroups, run on fin_grid(n) workgroups. Depends on n only, so the
+// summation order of every entry is fixed by n.
+constexpr int kFinPer = 8;
+constexpr int kFinMaxGrid = 1024;
+constexpr int fin_lanes(int n)
+{
+    const int nrt = (n + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
+    const int m = nrt > nct ? nrt : nct;
+    int L = 1;
+    while (L < 64 && L * kFinPer < m) L <<= 1;
+    return L;
+}
+constexpr int fin_vblocks(int n) { return (2 * n * fin_lanes(n) + kVecWG - 1) / kVecWG; }
+constexpr int fin_grid(int n) { return fin_vblocks(n) < kFinMaxGrid ? fin_vblocks(n) : kFinMaxGrid; }
+
 // What the next sweep does.
 enum SweepMode : int32_t { SM_NONE = 0, SM_LSE = 1, SM_R1 = 2, SM_R2 = 3, SM_MAX = 4 };
 // Phase of an LSE sweep.
@@ -103,9 +120,8 @@ struct Work {
     double* rowmin;    // [2 * nct * n] per-tile row minima (two variants)
     double* colmin;    // [2 * nrt * n] per-tile column minima
     double* tshift;    // [nrt] per-row-tile column shift S_I
-    double* bdots;     // [ceil(2n / kVecWG) * kNDot] per-block dot products
-    uint32_t* cnt;     // [0]: arrival counter of the finalize kernel (self-resetting)
-    State* st;         // [2] state slots: step k reads slot k % 2, its finalize kernel writes the other
+    double* bdots;     // [fin_grid(n) * kNDot] per-workgroup dot products of the finalize kernel
+    State* st;         // [2] state slots: step k reads slot k % 2, its decide kernel writes the other
     DevParams* prm;
 };
 
@@ -122,7 +138,7 @@ struct BatchDesc {
 
 // Host-side launchers (mdot_kernels.hip). `hw` is the host copy of the Work struct (sizes
 // and cost type pick the grid and the kernel instance), `wd` its device copy.
-int launch_step(const Work& hw, const Work* wd, int parity, void* stream);  // control + sweep kernels
+int launch_step(const Work& hw, const Work* wd, int parity, void* stream);  // sweep, finalize, decide
 int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream); // the LSE sweep kernel alone
 int launch_init(const Work* wd, void* stream);                               // state + first stage
 int launch_intake(const Work* wd, double* out8, void* stream);

@@ -7,15 +7,15 @@
 //             per element and accumulates BOTH the row sums and the column sums from that
 //             single read of C (row sums reduced across the wave64 through an LDS transpose,
 //             column sums across the four waves). It writes per-tile partials only.
-//   k_round : the same tile structure for the two Round / certificate passes (it returns at
-//             once in steps that do not need it; its larger register footprint stays out of
-//             the hot kernel).
-//   k_fin   : one thread per entry of the 2n-vectors: stores the vector update decided by the
-//             previous step (accept a line-search step, start a stage with smoothing and warm
-//             start, prepare Round), combines the tile partials of its row or column in FP64
-//             in a fixed order and reduces the dot products of the line search and of PNCG;
-//             the last workgroup to finish runs the scalar logic of the line search (App. B),
-//             PNCG (Alg. 2) and the annealing loop (Alg. 1) and stores the next state.
+//             The same kernel runs the two Round / certificate passes of a stage.
+//   k_fin   : a group of lanes per entry of the 2n-vectors: stores the vector update decided
+//             by the previous step (accept a line-search step, start a stage with smoothing
+//             and warm start, prepare Round), combines the tile partials of its row or column
+//             in FP64 in a fixed order and reduces the dot products of the line search and of
+//             PNCG per workgroup.
+//   k_decide: one workgroup: reduces those dots in a fixed order and runs the scalar logic of
+//             the line search (App. B), PNCG (Alg. 2) and the annealing loop (Alg. 1), then
+//             stores the next state. Kernel boundaries order the three; no atomics or fences.
 // The sweeps evaluate the pending vector update on the fly for their own rows and columns
 // with the same function k_fin uses to store it (explicit fma, so both are bit-identical).
 // The host never reads a value between steps; it replays a captured graph of steps and
@@ -40,6 +40,8 @@ namespace mdot {
 
 #define LOG2E_D 1.4426950408889634074
 #define LN2_D 0.6931471805599453094
+
+static_assert(kBR == 64, "a sweep tile has one row per lane of a wave64");
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -403,8 +405,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
         sCol[t.tid] = vv;
     }
     __syncthreads();
-    double SI = -INFINITY;  // S_I = max_i s_i (identical in every workgroup of this row tile)
-    for (int k = 0; k < kBR; ++k) SI = fmax(SI, sS[k]);
+    const double SI = wave_max(sS[t.lane]);  // S_I = max_i s_i over the kBR (= 64) rows
     if (t.tid < kBR) sWt[t.tid] = exp(sS[t.tid] - SI);
     const int j0 = t.j0lane;
     double V[4];
@@ -542,8 +543,7 @@ __device__ void tile_r1(const Work& w, const SweepArgs& S, const TileCtx& t, dou
         sCol[2 * kBC + t.tid] = g2v;
     }
     __syncthreads();
-    double SI = -INFINITY;
-    for (int k = 0; k < kBR; ++k) SI = fmax(SI, sS[k]);
+    const double SI = wave_max(sS[t.lane]);  // S_I = max_i s_i over the kBR (= 64) rows
     const int j0 = t.j0lane;
     double V[4], G1[4], G2[4];
     bool ok[4];
@@ -707,109 +707,156 @@ __device__ __forceinline__ bool in_range(double s, bool e64)  // shifted sum rep
     return s >= lo && s <= hi;  // false for NaN
 }
 
-// Finalize entry k of the 2n-vector after a sweep (row k < n, column k - n otherwise):
-// combine the tile partials in a fixed order and add this entry's terms to the dots.
-// fac[I] = exp(S_I - M) (column tiles), M = max_I S_I.
+// Tile partials of one entry, combined (the fields a sweep mode uses):
+//   a: sum of the LSE partials (columns: each scaled by exp(S_I - M))
+//   b: min (R1, R2) or max (max pass) of the first minima array
+//   c: min of the second minima array (finite-difference variant)
+//   d, e: sums of the second and third row partials (R2)
+struct Comb {
+    double a, b, c, d, e;
+};
+
+template <int OP>  // 0: fma(x, f, acc), 1: min, 2: max
+__device__ __forceinline__ double fold_op(double acc, double x, double f)
+{
+    if constexpr (OP == 0) return fma(x, f, acc);
+    else if constexpr (OP == 1) return fmin(acc, x);
+    else return fmax(acc, x);
+}
+
+// Lane l of an entry's L-lane group folds partials l, l + L, l + 2L, ... of the m partials at
+// base[I * stride], in that order, 8 loads in flight at a time. With `shift` (column LSE
+// partials) partial I is scaled by exp(shift[I] - M).
+template <int OP>
+__device__ __forceinline__ double lane_fold(const double* __restrict__ base, size_t stride, int l, int L, int m,
+                                            const double* __restrict__ shift, double M, bool use)
+{
+    double acc = (OP == 0) ? 0.0 : (OP == 1 ? INFINITY : -INFINITY);
+    if (!use) return acc;
+    for (int q0 = l; q0 < m; q0 += 8 * L) {
+        double x[8], f[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int I = q0 + u * L;
+            x[u] = (I < m) ? base[(size_t)I * stride] : 0.0;
+            f[u] = (shift && I < m) ? shift[I] : M;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int I = q0 + u * L;
+            if (I < m) acc = fold_op<OP>(acc, x[u], shift ? exp(f[u] - M) : 1.0);
+        }
+    }
+    return acc;
+}
+
+// Xor butterfly over the L lanes of a group: every lane ends with the same value (each
+// pairwise step is commutative), and the order depends only on L. Called by whole waves.
+template <int OP>
+__device__ __forceinline__ double group_fold(double v, int L)
+{
+    for (int s = 1; s < L; s <<= 1) v = fold_op<OP>(v, __shfl_xor(v, s, 64), 1.0);
+    return v;
+}
+
+// Combine the tile partials of entry k (row k < n, column k - n otherwise) for `mode`.
+// Called by every lane of the wave; `valid` is false past the end of the 2n-vector.
+__device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool valid, int l, int L, double M)
+{
+    const int n = w.n;
+    const bool row = k < n;
+    const int m = row ? w.nct : w.nrt;
+    const size_t ix = row ? (size_t)k : (size_t)(k - n);
+    Comb cb{0.0, INFINITY, INFINITY, 0.0, 0.0};
+    if (mode == SM_LSE) {
+        cb.a = group_fold<0>(lane_fold<0>((row ? w.rowpart : w.colpart) + ix, n, l, L, m, row ? nullptr : w.tshift, M, valid), L);
+    } else if (mode == SM_MAX) {
+        cb.b = group_fold<2>(lane_fold<2>((row ? w.rowmin : w.colmin) + ix, n, l, L, m, nullptr, 0.0, valid), L);
+    } else {
+        const double* mn = (row ? w.rowmin : w.colmin) + ix;
+        cb.b = group_fold<1>(lane_fold<1>(mn, n, l, L, m, nullptr, 0.0, valid), L);
+        cb.c = group_fold<1>(lane_fold<1>(mn + (size_t)m * n, n, l, L, m, nullptr, 0.0, valid), L);
+        if (mode == SM_R1) {
+            cb.a = group_fold<0>(lane_fold<0>(w.colpart + ix, n, l, L, m, w.tshift, M, valid && !row), L);
+        } else {
+            cb.a = group_fold<0>(lane_fold<0>(w.rowpart + ix, n, l, L, m, nullptr, 0.0, valid && row), L);
+            cb.d = group_fold<0>(lane_fold<0>(w.rowpart2 + ix, n, l, L, m, nullptr, 0.0, valid && row), L);
+            cb.e = group_fold<0>(lane_fold<0>(w.rowpart3 + ix, n, l, L, m, nullptr, 0.0, valid && row), L);
+        }
+    }
+    return cb;
+}
+
+// Finalize entry k of the 2n-vector after a sweep from its combined partials and add this
+// entry's terms to the dots. M = max_I S_I (column entries of LSE and R1 sweeps).
 __device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a, const Entry& e, double g_cur, int k,
-                                               int mode, bool e64, const double* fac, double M, double v[kNDot])
+                                               int mode, bool e64, const Comb& cb, double M, double v[kNDot])
 {
     const int n = w.n;
     if (k < n) {  // row i = k
         const int i = k;
         if (mode == SM_MAX) {
-            double m = -INFINITY;
-            for (int J = 0; J < w.nct; ++J) m = fmax(m, w.rowmin[(size_t)J * n + i]);
-            w.lz[i] = m;
+            w.lz[i] = cb.b;
         } else if (mode == SM_LSE) {
-            double sum = 0.0;
-            for (int J = 0; J < w.nct; ++J) sum += w.rowpart[(size_t)J * n + i];
+            const double sum = cb.a;
             const double l = fma(a.alpha, e.p, e.lz) + log(sum);  // shift used by the sweep
             w.lzt[i] = l;
             const double gnew = exp(l) - e.rt;
             const double snew = e.logt - l;
             const double y = gnew - g_cur;
-            v[D_PHI] = e.p * gnew;
-            v[D_NUM] = -y * snew;
-            v[D_DEN] = y * e.p;
-            v[D_SG] = snew * gnew;
-            v[D_GN] = fabs(gnew);
-            v[D_BAD] = in_range(sum, e64) ? 0.0 : 1.0;
+            v[D_PHI] += e.p * gnew;
+            v[D_NUM] += -y * snew;
+            v[D_DEN] += y * e.p;
+            v[D_SG] += snew * gnew;
+            v[D_GN] += fabs(gnew);
+            v[D_BAD] += in_range(sum, e64) ? 0.0 : 1.0;
         } else if (mode == SM_R1) {
-            double m1 = INFINITY, m2 = INFINITY;
-            for (int J = 0; J < w.nct; ++J) {
-                m1 = fmin(m1, w.rowmin[(size_t)J * n + i]);
-                m2 = fmin(m2, w.rowmin[(size_t)(w.nct + J) * n + i]);
-            }
-            w.fpp[i] = m1;
-            w.fpp[n + i] = m2;
-            v[D_RF1] = w.r[i] * m1;
-            v[D_RF2] = w.r[i] * m2;
+            w.fpp[i] = cb.b;
+            w.fpp[n + i] = cb.c;
+            v[D_RF1] += w.r[i] * cb.b;
+            v[D_RF2] += w.r[i] * cb.c;
         } else {  // SM_R2
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, m1 = INFINITY, m2 = INFINITY;
-            for (int J = 0; J < w.nct; ++J) {
-                const size_t o = (size_t)J * n + i;
-                s0 += w.rowpart[o];
-                s1 += w.rowpart2[o];
-                s2 += w.rowpart3[o];
-                m1 = fmin(m1, w.rowmin[o]);
-                m2 = fmin(m2, w.rowmin[(size_t)(w.nct + J) * n + i]);
-            }
             const double ex = w.xr[i] * exp(e.lz);
-            const double er = w.r[i] - ex * s0;  // err_r = r - r(F')
-            v[D_A] = ex * s1;
-            v[D_ERRR] = er;
-            v[D_EC] = er * s2;
-            v[D_RFP1] = w.r[i] * m1;
-            v[D_RFP2] = w.r[i] * m2;
+            const double er = w.r[i] - ex * cb.a;  // err_r = r - r(F')
+            v[D_A] += ex * cb.d;
+            v[D_ERRR] += er;
+            v[D_EC] += er * cb.e;
+            v[D_RFP1] += w.r[i] * cb.b;
+            v[D_RFP2] += w.r[i] * cb.c;
         }
         return;
     }
     const int j = k - n;  // column
     if (mode == SM_MAX) {
-        double m = -INFINITY;
-        for (int I = 0; I < w.nrt; ++I) m = fmax(m, w.colmin[(size_t)I * n + j]);
-        w.lz[n + j] = m;
-    } else if (mode == SM_LSE || mode == SM_R1) {
-        double sum = 0.0;
-        for (int I = 0; I < w.nrt; ++I) sum = fma(w.colpart[(size_t)I * n + j], fac[I], sum);
-        if (mode == SM_LSE) {
-            const double l = M + log(sum);
-            w.lzt[n + j] = l;
-            const double gnew = exp(l) - e.rt;
-            const double snew = e.logt - l;
-            const double y = gnew - g_cur;
-            v[D_PHI] = e.p * gnew;
-            v[D_NUM] = -y * snew;
-            v[D_DEN] = y * e.p;
-            v[D_SG] = snew * gnew;
-            v[D_GN] = fabs(gnew);
-            v[D_BAD] = in_range(sum, e64) ? 0.0 : 1.0;
-        } else {  // R1: c(F)_j, y_j = c_j / c(F)_j ^ 1, err_c, g'_j (Alg. 3)
-            double m1 = INFINITY, m2 = INFINITY;
-            for (int I = 0; I < w.nrt; ++I) {
-                m1 = fmin(m1, w.colmin[(size_t)I * n + j]);
-                m2 = fmin(m2, w.colmin[(size_t)(w.nrt + I) * n + j]);
-            }
-            const double cF = exp(M) * sum;
-            const double cj = w.c[j];
-            const double y = (cF > 0.0) ? fmin(cj / cF, 1.0) : 1.0;
-            const double ec = cj - y * cF;
-            w.yc[j] = y;
-            w.errc[j] = ec;
-            w.gp[j] = m1;
-            w.gp[n + j] = m2;
-            v[D_CG1] = cj * m1;
-            v[D_CG2] = cj * m2;
-            v[D_ERRC] = ec;
-        }
+        w.lz[n + j] = cb.b;
+    } else if (mode == SM_LSE) {
+        const double sum = cb.a;
+        const double l = M + log(sum);
+        w.lzt[n + j] = l;
+        const double gnew = exp(l) - e.rt;
+        const double snew = e.logt - l;
+        const double y = gnew - g_cur;
+        v[D_PHI] += e.p * gnew;
+        v[D_NUM] += -y * snew;
+        v[D_DEN] += y * e.p;
+        v[D_SG] += snew * gnew;
+        v[D_GN] += fabs(gnew);
+        v[D_BAD] += in_range(sum, e64) ? 0.0 : 1.0;
+    } else if (mode == SM_R1) {  // c(F)_j, y_j = c_j / c(F)_j ^ 1, err_c, g'_j (Alg. 3)
+        const double cF = exp(M) * cb.a;
+        const double cj = w.c[j];
+        const double y = (cF > 0.0) ? fmin(cj / cF, 1.0) : 1.0;
+        const double ec = cj - y * cF;
+        w.yc[j] = y;
+        w.errc[j] = ec;
+        w.gp[j] = cb.b;
+        w.gp[n + j] = cb.c;
+        v[D_CG1] += cj * cb.b;
+        v[D_CG2] += cj * cb.c;
+        v[D_ERRC] += ec;
     } else {  // R2: g''_j
-        double m1 = INFINITY, m2 = INFINITY;
-        for (int I = 0; I < w.nrt; ++I) {
-            m1 = fmin(m1, w.colmin[(size_t)I * n + j]);
-            m2 = fmin(m2, w.colmin[(size_t)(w.nrt + I) * n + j]);
-        }
-        v[D_CGP1] = w.c[j] * m1;
-        v[D_CGP2] = w.c[j] * m2;
+        v[D_CGP1] += w.c[j] * cb.b;
+        v[D_CGP2] += w.c[j] * cb.c;
     }
 }
 
@@ -1036,16 +1083,14 @@ __device__ __forceinline__ void sweep_tiles(const Work& w, const SweepArgs& a, c
     }
 }
 
-// Shared body of the two sweep kernels. ROUND = false: LSE and max sweeps (the hot path);
-// ROUND = true: the two Round/certificate sweeps, kept in their own kernel so their larger
-// register footprint does not lower the occupancy of the LSE sweep.
+// Body of the sweep kernel for one tile. ROUND = false: LSE and max sweeps (the hot path);
+// ROUND = true: the two Round/certificate sweeps (twice per stage).
 template <int CC, bool ROUND>
 __device__ __forceinline__ void sweep_kernel_body(const Work& w, int parity, int blk, double* smem)
 {
     const State* Sp = w.st + parity;
     const int mode = Sp->sweep_mode;
     if (mode == SM_NONE || Sp->done) return;
-    if ((mode == SM_R1 || mode == SM_R2) != ROUND) return;
     const bool e64 = Sp->exp64 != 0;
     const SweepArgs a = args_of(Sp);
     TileCtx t;
@@ -1060,125 +1105,147 @@ __device__ __forceinline__ void sweep_kernel_body(const Work& w, int parity, int
     else sweep_tiles<CC, false, ROUND>(w, a, t, mode, smem);
 }
 
+// One kernel for every sweep mode, so a step is a fixed sequence of launches. The register
+// cap keeps four workgroups per CU (the LDS limit is five): the LSE path needs 84 VGPRs, the
+// Round paths (twice per stage) spill a few values.
 template <int CC>
-__global__ void __launch_bounds__(kWG) k_sweep(const Work* __restrict__ wp, int parity)
+__device__ __forceinline__ void sweep_any(const Work& w, int parity, int blk, double* smem)
 {
-    __shared__ double smem[kSmem];
-    sweep_kernel_body<CC, false>(*wp, parity, blockIdx.x, smem);
+    const int mode = w.st[parity].sweep_mode;
+    if (mode == SM_R1 || mode == SM_R2) sweep_kernel_body<CC, true>(w, parity, blk, smem);
+    else sweep_kernel_body<CC, false>(w, parity, blk, smem);
 }
 
 template <int CC>
-__global__ void __launch_bounds__(kWG) k_round(const Work* __restrict__ wp, int parity)
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
+k_sweep(const Work* __restrict__ wp, int parity)
 {
     __shared__ double smem[kSmem];
-    sweep_kernel_body<CC, true>(*wp, parity, blockIdx.x, smem);
+    sweep_any<CC>(*wp, parity, blockIdx.x, smem);
 }
 
 // ------------------------------------------------------------------ the finalize kernel
-// One thread per entry of the 2n-vectors. Reads state slot `parity` (the one the sweeps of
-// this step used) and writes the next state into the other slot.
+// Reads state slot `parity` (the one this step's sweep used): stores the pending vector
+// update, combines the tile partials of every entry of the 2n-vectors and writes per-workgroup
+// dot products. The decide kernel that follows reduces them and writes the other slot.
 struct FinShared {
-    double fac[1024];
     double red[kNDot * 4];
-    double glob[kNDot];
-    double M;
-    int last;
 };
 
-// Finalize block `blk` of `nblk` blocks of one problem (entries blk * kVecWG + tid).
+// Finalize workgroup `blk` of the problem's `nblk` (= fin_grid(n)) workgroups. Entry k is
+// handled by an L-lane group (L = fin_lanes(n)); the groups are laid out in virtual blocks of
+// kVecWG / L entries, which the workgroups take in a grid-stride loop. Every load of an
+// iteration is issued before its first use (the kernel is latency-bound).
 __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int nblk, FinShared& sh)
 {
-    double* sfac = sh.fac;
-    double* sred = sh.red;
-    double* sglob = sh.glob;
     const State* Sp = w.st + parity;
     const int tid = threadIdx.x;
     const int n = w.n;
-    const int k = blk * kVecWG + tid;
+    const int L = fin_lanes(n);
+    const int lgL = __ffs(L) - 1;
+    const int l = tid & (L - 1);
     const SweepArgs a = args_of(Sp);
     const int mode = Sp->sweep_mode;
-    const bool done = Sp->done != 0;
+    const bool active = !Sp->done && mode != SM_NONE;
     const bool e64 = Sp->exp64 != 0;
-    // 1. store the pending vector update of this entry
-    Entry e;
-    double g_cur = 0.0;
-    if (k < 2 * n) {
-        e = entry_after(w, a, k);
+    // M = max_I S_I (uniform loads); column partials are scaled by exp(S_I - M) when combined
+    double M = 0.0;
+    if (active && (mode == SM_LSE || mode == SM_R1)) {
+        double mx = -INFINITY;  // every wave forms the same maximum
+        for (int I = tid & 63; I < w.nrt; I += 64) mx = fmax(mx, w.tshift[I]);
+        M = wave_max(mx);
+    }
+    double v[kNDot];
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
+    const int nvb = fin_vblocks(n);
+    for (int vb = blk; vb < nvb; vb += nblk) {
+        const int k = (vb * kVecWG + tid) >> lgL;
+        const bool valid = k < 2 * n;
+        const bool lead = valid && l == 0;
+        Entry e{};
+        double g_old = 0.0;
+        if (lead) {
+            e = entry_after(w, a, k);
+            g_old = w.g[k];
+        }
+        Comb cb{};
+        if (active) cb = combine(w, mode, k, valid, l, L, M);
+        if (!lead) continue;
+        // store the pending vector update of this entry
         const int va = a.va;
         if (va & (VA_ACCEPT | VA_STAGE_INIT)) {
             w.z[k] = e.z;
             w.p[k] = e.p;
             w.lz[k] = e.lz;
         }
+        double g_cur = g_old;
         if (va & VA_STAGE_INIT) {
             w.rt[k] = e.rt;
             w.logt[k] = e.logt;
             w.zprev[k] = e.zprev;
-            w.g[k] = 0.0;
+            g_cur = 0.0;
+            w.g[k] = g_cur;
         } else if (va & VA_ACCEPT) {
-            w.g[k] = exp(e.lz) - e.rt;
+            g_cur = exp(e.lz) - e.rt;
+            w.g[k] = g_cur;
         }
         if (va & VA_SAVE_BEST) w.zbest[k] = e.zacc;
         if ((va & VA_ROUND_PREP) && k < n) w.xr[k] = round_x(w.r[k], e.lz);
-        g_cur = (va & (VA_ACCEPT | VA_STAGE_INIT)) ? ((va & VA_STAGE_INIT) ? 0.0 : exp(e.lz) - e.rt) : w.g[k];
+        if (active) finalize_entry(w, a, e, g_cur, k, mode, e64, cb, M, v);
     }
-    if (done || mode == SM_NONE) {
-        if (blk == 0 && tid == 0) {
-            State S = *Sp;
-            S.vec_action = 0;
-            w.st[parity ^ 1] = S;
-        }
-        return;
-    }
-    // 2. combine the tile partials of this entry
-    if (mode == SM_LSE || mode == SM_R1) {
-        if (tid == 0) {
-            double M = -INFINITY;
-            for (int I = 0; I < w.nrt; ++I) M = fmax(M, w.tshift[I]);
-            sh.M = M;
-        }
-        __syncthreads();
-        for (int I = tid; I < w.nrt; I += kVecWG) sfac[I] = exp(w.tshift[I] - sh.M);
-        __syncthreads();
-    }
-    double v[kNDot];
-#pragma unroll
-    for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
-    if (k < 2 * n) finalize_entry(w, a, e, g_cur, k, mode, e64, sfac, sh.M, v);
-    block_dots(v, w.bdots + (size_t)blk * kNDot, tid, sred);
-    // 3. the last workgroup reduces the block dots in a fixed order and decides
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(&w.cnt[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        sh.last = (old == (uint32_t)nblk - 1);
-    }
-    __syncthreads();
-    if (!sh.last) return;
-    __threadfence();
-#pragma unroll
-    for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
-    for (int b = tid; b < nblk; b += kVecWG)
-#pragma unroll
-        for (int d = 0; d < kNDot; ++d) v[d] += w.bdots[(size_t)b * kNDot + d];
-    block_dots(v, sglob, tid, sred);
-    if (tid == 0) {
-        double sum[kNDot];
-#pragma unroll
-        for (int d = 0; d < kNDot; ++d) sum[d] = sglob[d];
-        State S = *Sp;
-        const DevParams P = *w.prm;
-        decide(S, P, sum);
-        w.st[parity ^ 1] = S;
-        w.cnt[0] = 0;
-    }
+    if (active) block_dots(v, w.bdots + (size_t)blk * kNDot, tid, sh.red);
 }
 
 __global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int parity)
 {
     __shared__ FinShared sh;
     fin_body(*wp, parity, blockIdx.x, gridDim.x, sh);
+}
+
+// ------------------------------------------------------------------ the decide kernel
+// One workgroup per problem: reduce the finalize kernel's per-workgroup dots in a fixed order,
+// run the scalar state machine on slot `parity` and write the next state into the other slot
+// (a finished or idle state is carried over with its vector update cleared).
+struct DecideShared {
+    double red[kNDot * 4];
+    double glob[kNDot];
+};
+
+__device__ __forceinline__ void decide_body(const Work& w, int parity, DecideShared& sh)
+{
+    const State* Sp = w.st + parity;
+    const int tid = threadIdx.x;
+    const bool active = !Sp->done && Sp->sweep_mode != SM_NONE;
+    if (active) {
+        const int nblk = fin_grid(w.n);
+        double v[kNDot];
+#pragma unroll
+        for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
+        for (int b = tid; b < nblk; b += kVecWG)
+#pragma unroll
+            for (int d = 0; d < kNDot; ++d) v[d] += w.bdots[(size_t)b * kNDot + d];
+        block_dots(v, sh.glob, tid, sh.red);
+    }
+    if (tid == 0) {
+        State S = *Sp;
+        if (active) {
+            double sum[kNDot];
+#pragma unroll
+            for (int d = 0; d < kNDot; ++d) sum[d] = sh.glob[d];
+            const DevParams P = *w.prm;
+            decide(S, P, sum);
+        } else {
+            S.vec_action = 0;
+        }
+        w.st[parity ^ 1] = S;
+    }
+}
+
+__global__ void __launch_bounds__(kVecWG) k_decide(const Work* __restrict__ wp, int parity)
+{
+    __shared__ DecideShared sh;
+    decide_body(*wp, parity, sh);
 }
 
 // ------------------------------------------------------------------ batched kernels
@@ -1193,14 +1260,16 @@ __device__ __forceinline__ int batch_item(const int32_t* prefix, int nitems, int
     return lo;
 }
 
-template <int CC, bool ROUND>
+// Batched sweep: a grid-stride loop over the tiles of every problem in flight. Its register
+// count is left to the compiler (capping it spills inside the tile loop).
+template <int CC>
 __global__ void __launch_bounds__(kWG) k_sweep_batch(const BatchDesc* __restrict__ bd, int parity)
 {
     __shared__ double smem[kSmem];
     const int total = bd->total_tiles, nitems = bd->nitems;
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int b = batch_item(bd->tile_prefix, nitems, g);
-        sweep_kernel_body<CC, ROUND>(*bd->items[b], parity, g - bd->tile_prefix[b], smem);
+        sweep_any<CC>(*bd->items[b], parity, g - bd->tile_prefix[b], smem);
         __syncthreads();
     }
 }
@@ -1212,6 +1281,15 @@ __global__ void __launch_bounds__(kVecWG) k_fin_batch(const BatchDesc* __restric
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int b = batch_item(bd->fin_prefix, nitems, g);
         fin_body(*bd->items[b], parity, g - bd->fin_prefix[b], bd->fin_prefix[b + 1] - bd->fin_prefix[b], sh);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kVecWG) k_decide_batch(const BatchDesc* __restrict__ bd, int parity)
+{
+    __shared__ DecideShared sh;
+    for (int b = blockIdx.x; b < bd->nitems; b += gridDim.x) {
+        decide_body(*bd->items[b], parity, sh);
         __syncthreads();
     }
 }
@@ -1247,7 +1325,6 @@ __global__ void k_init(const Work* __restrict__ wp)
     S.best_gamma = S.gamma;
     w.st[0] = S;
     w.st[1] = S;
-    for (int k = 0; k < w.nrt + w.nct; ++k) w.cnt[k] = 0;
 }
 
 // Intake statistics: out8 = {sum r, sum c, min r, min c, H(r), H(c), nonfinite count, 0}
@@ -1396,12 +1473,11 @@ int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     const int tiles = hw.nrt * hw.nct;
-#define L_(CC)                                                                      \
-    hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity);     \
-    hipLaunchKernelGGL(k_round<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity)
+#define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity)
     MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
-    hipLaunchKernelGGL(k_fin, dim3((2 * hw.n + kVecWG - 1) / kVecWG), dim3(kVecWG), 0, s, wd, parity);
+    hipLaunchKernelGGL(k_fin, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kVecWG), 0, s, wd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1417,12 +1493,11 @@ int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream)
 int launch_step_batch(int cc, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-#define L_(CC)                                                                                        \
-    hipLaunchKernelGGL((k_sweep_batch<CC, false>), dim3(sweep_grid), dim3(kWG), 0, s, bd, parity);   \
-    hipLaunchKernelGGL((k_sweep_batch<CC, true>), dim3(sweep_grid), dim3(kWG), 0, s, bd, parity)
+#define L_(CC) hipLaunchKernelGGL(k_sweep_batch<CC>, dim3(sweep_grid), dim3(kWG), 0, s, bd, parity)
     MDOT_CC_SWITCH(cc, L_)
 #undef L_
     hipLaunchKernelGGL(k_fin_batch, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
+    hipLaunchKernelGGL(k_decide_batch, dim3(kMaxBatch), dim3(kVecWG), 0, s, bd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

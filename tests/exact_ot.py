@@ -22,8 +22,10 @@ def exact_lp(C, r, c) -> float:
     c = np.asarray(c, dtype=np.float64)
     c = c * (r.sum() / c.sum())
     n, m = C.shape
-    A = sp.vstack([sp.kron(sp.eye(n), np.ones((1, m))), sp.kron(np.ones((1, n)), sp.eye(m))]).tocsr()
-    res = linprog(C.ravel(), A_eq=A, b_eq=np.concatenate([r, c]), bounds=(0, None), method="highs")
+    # the n + m equalities have rank n + m - 1: drop the last column constraint, which the
+    # others imply, so rounding in the sums cannot make the system look inconsistent
+    A = sp.vstack([sp.kron(sp.eye(n), np.ones((1, m))), sp.kron(np.ones((1, n)), sp.eye(m))]).tocsr()[:-1]
+    res = linprog(C.ravel(), A_eq=A, b_eq=np.concatenate([r, c])[:-1], bounds=(0, None), method="highs")
     assert res.status == 0, res.message
     return float(res.fun)
 

@@ -1,0 +1,239 @@
+"""Parity of the HIP path for the other cost encodings and for the batched serving engine.
+
+Cost encodings: FP16 / BF16 stored dense costs (the stored values are the cost: the oracle
+runs on the decoded values) and point-cloud costs evaluated on the fly in FP64 from FP32
+coordinates (the oracle runs on the same cost formed in numpy FP64; the two differ by the
+summation order of d <= 3 squares, a few ulp). Tolerances as for the FP32 / FP64 sweeps.
+
+Engine: solves advanced together by mdot_run return exactly (bit for bit) what mdot_solve
+returns for each of them alone, and admission refuses work beyond the HBM budget.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2307_08507_amd import mdot as M  # noqa: E402
+from paper_2307_08507_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _potentials(n, seed, C, gamma):
+    from scipy.special import logsumexp
+
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal(n) * 0.5 - np.log(n)
+    v = -np.log(n) - logsumexp(u[:, None] - gamma * C, axis=0)
+    return u, v
+
+
+def _lse2(ctx, cost, u, v, gamma, prec):
+    n = u.size
+    lr = torch.empty(n, dtype=torch.float64, device="cuda")
+    lc = torch.empty_like(lr)
+    assert ctx.lse2(cost, dev(u), dev(v), gamma, lr, lc, precision=prec) == 0
+    torch.cuda.synchronize()
+    return lr.cpu().numpy(), lc.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [300, 512])
+@pytest.mark.parametrize("tdtype", ["f16", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lse2_half_costs(ctx, n, tdtype, prec):
+    print(f"lse2 {tdtype} n={n} prec={prec}", flush=True)
+    gamma = 200.0
+    C = np.random.default_rng(n + 7).random((n, n))
+    Cd = dev(C, torch.float16 if tdtype == "f16" else torch.bfloat16)
+    C64 = Cd.double().cpu().numpy()
+    u, v = _potentials(n, n, C64, gamma)
+    lr_o, lc_o = O.lse2(C64, u, v, gamma)
+    lr, lc = _lse2(ctx, M.dense_cost(Cd), u, v, gamma, prec)
+    tol = 1e-12 * gamma if prec == "f64" else 2e-6
+    np.testing.assert_allclose(lr, lr_o, rtol=0, atol=tol)
+    np.testing.assert_allclose(lc, lc_o, rtol=0, atol=tol)
+
+
+def _points(n, d, seed, kind):
+    x = W.gmm_points(n, d, seed)
+    y = W.gmm_points(n, d, seed + 1)
+    dd = x.astype(np.float64)[:, None, :] - y.astype(np.float64)[None, :, :]
+    raw = (dd * dd).sum(-1) if kind == "sqeuclid" else np.abs(dd).sum(-1)
+    scale = 1.0 / raw.max()
+    XY = dev(np.concatenate([x, y], 0), torch.float32)
+    return XY, raw * scale, scale
+
+
+@pytest.mark.parametrize("n,d,kind", [(300, 3, "sqeuclid"), (512, 2, "l1"), (257, 1, "sqeuclid")])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lse2_point_costs(ctx, n, d, kind, prec):
+    print(f"lse2 points n={n} d={d} {kind} prec={prec}", flush=True)
+    gamma = 500.0
+    XY, C64, scale = _points(n, d, 11 * n + d, kind)
+    u, v = _potentials(n, n + 3, C64, gamma)
+    lr_o, lc_o = O.lse2(C64, u, v, gamma)
+    lr, lc = _lse2(ctx, M.point_cost(XY, n, d, kind, scale=scale), u, v, gamma, prec)
+    tol = 1e-11 * gamma if prec == "f64" else 2e-6
+    np.testing.assert_allclose(lr, lr_o, rtol=0, atol=tol)
+    np.testing.assert_allclose(lc, lc_o, rtol=0, atol=tol)
+
+
+def test_point_cost_default_scale(ctx):
+    # scale 0: the library normalises by the largest pairwise value
+    n, d = 200, 3
+    XY, C64, scale = _points(n, d, 5, "sqeuclid")
+    gamma = 100.0
+    u, v = _potentials(n, 9, C64, gamma)
+    lr_o, lc_o = O.lse2(C64, u, v, gamma)
+    lr, lc = _lse2(ctx, M.point_cost(XY, n, d, "sqeuclid"), u, v, gamma, "f64")
+    np.testing.assert_allclose(lr, lr_o, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(lc, lc_o, rtol=0, atol=1e-9)
+
+
+def test_solve_point_cloud_brackets_exact_ot(ctx):
+    from tests.exact_ot import exact_lp
+
+    n, d = 256, 3
+    XY, C64, scale = _points(n, d, 21, "sqeuclid")
+    r = W.dirichlet_marginal(n, 1)
+    c = W.dirichlet_marginal(n, 2)
+    u = torch.empty(n, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+    res = ctx.solve(M.point_cost(XY, n, d, "sqeuclid", scale=scale), dev(r), dev(c), 1e-5,
+                    M.default_params(precision="f32"), u, v)
+    ot = exact_lp(C64, r, c)
+    print(f"points: gap={res.gap:.3e} UB-OT={res.primal_cost - ot:.3e} sweeps={res.sweeps}")
+    assert res.status == 0 and res.gap <= 1e-5
+    assert res.dual_bound <= ot + 1e-9 and res.primal_cost >= ot - 1e-9
+    assert res.marg_err_l1 <= 1e-12
+
+
+@pytest.mark.parametrize("tdtype", ["f16", "bf16"])
+def test_solve_half_cost_brackets_exact_ot(ctx, tdtype):
+    from tests.exact_ot import exact_lp
+
+    C, r, c = W.grid_problem(16, "blobs", "sqeuclid", 3)
+    Cd = dev(C, torch.float16 if tdtype == "f16" else torch.bfloat16)
+    C64 = Cd.double().cpu().numpy()
+    u = torch.empty(r.size, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+    res = ctx.solve(M.dense_cost(Cd), dev(r), dev(c), 1e-5, M.default_params(precision="f32"), u, v)
+    ot = exact_lp(C64, r, c)
+    print(f"{tdtype}: gap={res.gap:.3e} UB-OT={res.primal_cost - ot:.3e}")
+    assert res.status == 0 and res.gap <= 1e-5
+    assert res.dual_bound <= ot + 1e-12 and res.primal_cost >= ot - 1e-12
+
+
+# ---------------------------------------------------------------- serving engine
+def _engine_problems():
+    out = []
+    for k, fam, cost, seed in [(16, "smooth", "sqeuclid", 1), (24, "uniform", "l1", 2), (32, "blobs", "sqeuclid", 3),
+                               (17, "cauchy", "l1", 4), (40, "smooth", "l1", 5)]:
+        C, r, c = W.grid_problem(k, fam, cost, seed)
+        out.append((dev(C, torch.float32), dev(r), dev(c)))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_engine_bitwise_equals_solve(ctx, prec):
+    probs = _engine_problems()
+    prm = M.default_params(precision=prec)
+    alone = []
+    for C, r, c in probs:
+        u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+        res = ctx.solve(M.dense_cost(C), r, c, 1e-5, prm, u, v)
+        alone.append((res, u.cpu(), v.cpu()))
+    eng = M.Context(0)
+    try:
+        tickets, outs = [], []
+        for C, r, c in probs:
+            u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+            v = torch.empty_like(u)
+            t = eng.submit(M.dense_cost(C), r, c, 1e-5, prm, u, v)
+            assert t is not None
+            tickets.append(t)
+            outs.append((u, v))
+        assert eng.inflight()[0] == len(probs)
+        for _ in range(100000):
+            if eng.inflight()[0] == 0:
+                break
+            eng.run(64)
+        assert eng.inflight() == (0, 0)
+        for t, (u, v), (ra, ua, va) in zip(tickets, outs, alone):
+            rb = eng.poll(t)
+            assert rb is not None
+            assert torch.equal(u.cpu(), ua) and torch.equal(v.cpu(), va)
+            for f in ("status", "primal_cost", "dual_bound", "gap", "gamma_final", "stages", "pncg_iters", "sweeps"):
+                assert getattr(rb, f) == getattr(ra, f), f
+            with pytest.raises(M.MdotError):
+                eng.poll(t)  # a ticket is released once polled
+    finally:
+        eng.close()
+
+
+def test_engine_staggered_submission(ctx):
+    # a request admitted while others are half-way gets the same result as alone
+    probs = _engine_problems()
+    prm = M.default_params(precision="f32")
+    C, r, c = probs[2]
+    u0 = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+    v0 = torch.empty_like(u0)
+    ref = ctx.solve(M.dense_cost(C), r, c, 1e-5, prm, u0, v0)
+    eng = M.Context(0)
+    try:
+        keep = []
+        for C1, r1, c1 in probs[:2]:
+            u = torch.empty(r1.numel(), dtype=torch.float64, device="cuda")
+            keep.append((u, torch.empty_like(u)))
+            assert eng.submit(M.dense_cost(C1), r1, c1, 1e-5, prm, *keep[-1]) is not None
+        eng.run(40)
+        u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+        t = eng.submit(M.dense_cost(C), r, c, 1e-5, prm, u, v)
+        res = eng.poll(t, wait=True)
+        assert torch.equal(u, u0) and torch.equal(v, v0)
+        assert res.primal_cost == ref.primal_cost and res.sweeps == ref.sweeps
+    finally:
+        eng.close()
+
+
+def test_engine_admission_budget():
+    probs = _engine_problems()
+    prm = M.default_params(precision="f32")
+    C, r, c = probs[4]  # n = 1600
+    eng = M.Context(0, hbm_budget_bytes=2_500_000)
+    try:
+        keep = []
+        u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        keep.append((u, torch.empty_like(u)))
+        t1 = eng.submit(M.dense_cost(C), r, c, 1e-5, prm, *keep[-1])
+        assert t1 is not None
+        _, used = eng.inflight()
+        assert 0 < used <= 2_500_000
+        u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        keep.append((u, torch.empty_like(u)))
+        assert eng.submit(M.dense_cost(C), r, c, 1e-5, prm, *keep[-1]) is None  # over budget: busy
+        res = eng.poll(t1, wait=True)
+        assert res.status == 0
+        t2 = eng.submit(M.dense_cost(C), r, c, 1e-5, prm, *keep[-1])
+        assert t2 is not None
+        assert eng.poll(t2, wait=True).primal_cost == res.primal_cost
+    finally:
+        eng.close()
