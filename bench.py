@@ -14,6 +14,15 @@ measured over `--steps` solves after `--warmup` solves, inputs resident in HBM, 
 torch.cuda.synchronize(). `roofline` reports the dominant kernel (the fused LSE sweep) timed
 with HIP events on the library stream; `cpu_baseline` times the FP64 CPU oracle on a bounded
 sample of the same workload and extrapolates to a full solve.
+
+Other workloads (not the default line):
+  --grid 128             n = 16384 on a 128 x 128 grid (the cost is 1 GiB in FP32)
+  --cost-storage S       f32 (default), f16, bf16 (stored dense cost) or points (the cost is
+                         recomputed in registers from FP32 grid coordinates, in FP64)
+  --workload serving     continuous batching: Poisson arrivals of point-cloud OT requests
+                         (n log-uniform in [512, 8192], d = 3, target gap in {1e-4 .. 1e-7});
+                         reports throughput and p50 / p99 latency at 0.7x the measured
+                         saturation rate
 """
 from __future__ import annotations
 
@@ -30,36 +39,70 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 FAMILIES = ("uniform", "smooth", "blobs", "cauchy")
 COSTS = ("sqeuclid", "l1")
+BYTES = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}
 
 
-def build_problems(k: int):
+def build_problems(k: int, count: int):
     from paper_2307_08507_amd import workloads as W
 
     probs = []
     for fi, fam in enumerate(FAMILIES):
         for ci, cost in enumerate(COSTS):
-            seed = 1000 * (fi + 1) + 10 * ci
-            C, r, c = W.grid_problem(k, fam, cost, seed)
-            probs.append({"family": fam, "cost": cost, "seed": seed, "C": C, "r": r, "c": c})
+            if len(probs) < count:
+                seed = 1000 * (fi + 1) + 10 * ci
+                probs.append({"family": fam, "cost": cost, "seed": seed,
+                              "r": W.grid_problem_marginals(k, fam, seed),
+                              "c": W.grid_problem_marginals(k, fam, seed + 1)})
     return probs
 
 
-def cpu_baseline(prob, sweeps: int, stages: int, n_sweeps_sample: int = 20, n_cert_sample: int = 3):
+def grid_cost_device(k: int, kind: str, storage: str, dev):
+    """The normalised grid cost on the device: (descriptor maker, FP64 host copy maker).
+    Integer numerators are exact in FP64; num / max is rounded once, as in the generator."""
+    import torch
+
+    from paper_2307_08507_amd import mdot as M
+    from paper_2307_08507_amd import workloads as W
+
+    X = torch.tensor(W.grid_coords(k), dtype=torch.float64, device=dev)
+    mx = 2.0 * (k - 1) ** 2 if kind == "sqeuclid" else 2.0 * (k - 1)
+    if storage == "points":
+        XY = torch.cat([X, X]).float().contiguous()
+        n = k * k
+        return {"desc": lambda: M.point_cost(XY, n, 2, kind, scale=1.0 / mx), "keep": XY,
+                "host64": lambda: _grid_num(X, kind).div_(mx).cpu().numpy()}
+    dt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16, "f64": torch.float64}[storage]
+    C = _grid_num(X, kind).div_(mx).to(dt).contiguous()
+    return {"desc": lambda: M.dense_cost(C), "keep": C, "host64": lambda: C.double().cpu().numpy()}
+
+
+def _grid_num(X, kind):
+    import torch
+
+    n = X.shape[0]
+    out = torch.empty((n, n), dtype=torch.float64, device=X.device)
+    step = 2048
+    for a in range(0, n, step):
+        d = X[a:a + step, None, :] - X[None, :, :]
+        out[a:a + step] = (d * d).sum(-1) if kind == "sqeuclid" else d.abs().sum(-1)
+    return out
+
+
+def cpu_baseline(C64, prob, sweeps: int, stages: int, n_sweeps_sample: int, n_cert_sample: int, label: str):
     """Time the FP64 CPU oracle on a bounded sample and extrapolate to one full solve."""
     import numpy as np
 
     from oracle import oracle as O
 
-    C = prob["C"].astype(np.float32).astype(np.float64)
     r, c = prob["r"], prob["c"]
     u, v = np.log(r), np.log(c)
     t0 = time.perf_counter()
     for k in range(n_sweeps_sample):
-        O.lse2(C, u, v, 16.0 * 2 ** (k / 3))
+        O.lse2(C64, u, v, 16.0 * 2 ** (k / 3))
     t_sweep = (time.perf_counter() - t0) / n_sweeps_sample
     t0 = time.perf_counter()
     for k in range(n_cert_sample):
-        O.round_certify(C, u, v, 64.0, r, c, u_prev=0.9 * u, v_prev=0.9 * v, gamma_prev=50.0)
+        O.round_certify(C64, u, v, 64.0, r, c, u_prev=0.9 * u, v_prev=0.9 * v, gamma_prev=50.0)
     t_cert = (time.perf_counter() - t0) / n_cert_sample
     est = sweeps * t_sweep + stages * t_cert
     return {
@@ -67,37 +110,28 @@ def cpu_baseline(prob, sweeps: int, stages: int, n_sweeps_sample: int = 20, n_ce
         "unit": "s",
         "cores": O.num_threads(),
         "kind": "oracle",
-        "sample": (f"FP64 C oracle on the first problem ({prob['family']}/{prob['cost']}, n={r.size}): "
-                   f"{n_sweeps_sample} two-sided LSE sweeps ({t_sweep:.4f} s each) and {n_cert_sample} "
-                   f"round+certify evaluations ({t_cert:.3f} s each), extrapolated to the GPU solve's "
-                   f"{sweeps} sweeps and {stages} certified stages"),
+        "sample": (f"FP64 C oracle on {label} (n={r.size}): {n_sweeps_sample} two-sided LSE sweeps "
+                   f"({t_sweep:.4f} s each) and {n_cert_sample} round+certify evaluations ({t_cert:.3f} s each), "
+                   f"extrapolated to the GPU solve's {sweeps} sweeps and {stages} certified stages"),
     }
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--target", type=float, default=1e-6)
-    ap.add_argument("--grid", type=int, default=64, help="grid side k (n = k*k)")
-    ap.add_argument("--precision", default="f32", choices=("f32", "f64"))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is "
-              f"design-only in this build)", file=sys.stderr)
-        return 2
-
+def bench_grid(args) -> dict:
     import torch
 
     from paper_2307_08507_amd import mdot as M
 
     dev = torch.device("cuda", 0)
-    probs = build_problems(args.grid)
-    n = args.grid * args.grid
+    # reference for hardware byte counters in profiling runs of this command: one plain
+    # device-to-device copy of 64 MiB (64 MiB read, 64 MiB written)
+    ref = torch.empty(16 << 20, dtype=torch.float32, device=dev)
+    torch.empty_like(ref).copy_(ref)
+    del ref
+    k = args.grid
+    n = k * k
+    probs = build_problems(k, args.problems)
+    costs = {kind: grid_cost_device(k, kind, args.cost_storage, dev) for kind in {p["cost"] for p in probs}}
     for p in probs:
-        p["Cd"] = torch.tensor(p["C"], dtype=torch.float32, device=dev)
         p["rd"] = torch.tensor(p["r"], dtype=torch.float64, device=dev)
         p["cd"] = torch.tensor(p["c"], dtype=torch.float64, device=dev)
     ctx = M.Context(0)
@@ -106,33 +140,39 @@ def main() -> int:
     v = torch.empty_like(u)
 
     def solve(p):
-        return ctx.solve(M.dense_cost(p["Cd"]), p["rd"], p["cd"], args.target, prm, u, v)
+        return ctx.solve(costs[p["cost"]]["desc"](), p["rd"], p["cd"], args.target, prm, u, v)
 
-    for k in range(args.warmup):
-        solve(probs[k % len(probs)])
+    for i in range(args.warmup):
+        solve(probs[i % len(probs)])
     torch.cuda.synchronize()
-    results = []
-    step_times = []
+    results, step_times = [], []
     t_start = time.perf_counter()
-    for k in range(args.steps):
+    for i in range(args.steps):
         t0 = time.perf_counter()
-        res = solve(probs[k % len(probs)])
+        res = solve(probs[i % len(probs)])
         torch.cuda.synchronize()
         step_times.append(time.perf_counter() - t0)
         results.append(res)
     torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    mean_s = total / args.steps
+    mean_s = (time.perf_counter() - t_start) / args.steps
 
     # roofline of the dominant kernel: the fused LSE sweep at the first problem's solution
     p0 = probs[0]
     r0 = solve(p0)
-    ms = ctx.bench_sweep(M.dense_cost(p0["Cd"]), u, v, r0.gamma_final, precision=args.precision, iters=200)
-    bytes_per_sweep = n * n * 4  # algorithmic: every FP32 cost entry read once per sweep
-    achieved = bytes_per_sweep / (ms * 1e-3) / 1e9
-
+    ms = ctx.bench_sweep(costs[p0["cost"]]["desc"](), u, v, r0.gamma_final, precision=args.precision, iters=200)
+    if args.cost_storage == "points":
+        bound, unit, peak = "alu", "Gexp/s", None
+        achieved = n * n / (ms * 1e-3) / 1e9
+        per_launch = {"elements_per_launch": n * n}
+    else:
+        bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBPS
+        per_launch = {"bytes_per_launch": n * n * BYTES[args.cost_storage]}
+        achieved = per_launch["bytes_per_launch"] / (ms * 1e-3) / 1e9
+    roof = {"bound": bound, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4) if peak else None, "traffic": None,
+            "kernel": "k_sweep (fused two-sided LSE sweep)", **per_launch}
     out = {
-        "metric": "time-to-gap 1e-6 at n=4096",
+        "metric": f"time-to-gap {args.target:g} at n={n}",
         "value": round(mean_s, 6),
         "unit": "s",
         "n_gpus": 1,
@@ -145,33 +185,139 @@ def main() -> int:
         "dtype": args.precision,
         "data": "synthetic",
         "config": {
-            "workload": (f"n={n} ({args.grid}x{args.grid} grid), FP32 stored cost, sqeuclid and L1 x "
-                         f"{{uniform, smooth, blobs, cauchy}} marginals, certified gap {args.target:g}"),
+            "workload": (f"n={n} ({k}x{k} grid), {args.cost_storage} cost, {'/'.join(sorted(costs))} x "
+                         f"{{{', '.join(sorted({p['family'] for p in probs}))}}} marginals, certified gap "
+                         f"{args.target:g}"),
             "n": n,
             "target_gap": args.target,
             "problems": len(probs),
+            "cost_storage": args.cost_storage,
         },
         "time_to_gap_median_s": round(statistics.median(step_times), 6),
         "time_to_gap_max_s": round(max(step_times), 6),
         "certified_gap_max": max(r.gap for r in results),
         "all_certified": all(r.status == 0 and r.gap <= args.target for r in results),
         "sweeps_mean": statistics.mean(r.sweeps for r in results),
+        "us_per_sweep_in_solve": round(1e6 * sum(step_times) / sum(r.sweeps for r in results), 2),
         "lse_sweep_us": round(ms * 1e3, 3),
-        "lse_sweep_GBps": round(achieved, 1),
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": None,
-            "kernel": "k_sweep<F32> (fused two-sided LSE sweep)",
-            "bytes_per_launch": bytes_per_sweep,
-        },
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p0, r0.sweeps, r0.stages)
+        big = n > 8192
+        out["cpu_baseline"] = cpu_baseline(costs[p0["cost"]]["host64"](), p0, r0.sweeps, r0.stages,
+                                           n_sweeps_sample=6 if big else 20, n_cert_sample=1 if big else 3,
+                                           label=f"the first problem ({p0['family']}/{p0['cost']})")
     ctx.close()
+    return out
+
+
+def bench_serving(args) -> dict:
+    import numpy as np
+    import torch
+
+    from paper_2307_08507_amd import mdot as M
+    from paper_2307_08507_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    reqs = W.serving_stream(args.requests, 1.0, seed=args.seed, d=3)
+    for q in reqs:
+        q.XY = torch.tensor(np.concatenate([q.x, q.y]), dtype=torch.float32, device=dev)
+        q.rd = torch.tensor(q.r, dtype=torch.float64, device=dev)
+        q.cd = torch.tensor(q.c, dtype=torch.float64, device=dev)
+        q.u = torch.empty(q.n, dtype=torch.float64, device=dev)
+        q.v = torch.empty_like(q.u)
+    prm = M.default_params(precision=args.precision)
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        eng = M.Context(0)
+        order = sorted(range(len(reqs)), key=lambda i: arrivals[i])
+        nxt, tickets, done = 0, {}, {}
+        t0 = time.perf_counter()
+        while len(done) < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(order) and arrivals[order[nxt]] <= now:
+                q = reqs[order[nxt]]
+                t = eng.submit(M.point_cost(q.XY, q.n, 3, "sqeuclid"), q.rd, q.cd, q.target, prm, q.u, q.v)
+                if t is None:
+                    break
+                tickets[t] = order[nxt]
+                nxt += 1
+            if tickets:
+                eng.run(8)
+                now = time.perf_counter() - t0
+                for t in list(tickets):
+                    res = eng.poll(t)
+                    if res is not None:
+                        done[tickets.pop(t)] = (now, res)
+                        if len(done) % 16 == 0:
+                            print(f"served {len(done)}/{len(reqs)} at {now:.2f} s", file=sys.stderr, flush=True)
+            elif nxt < len(order):
+                time.sleep(max(0.0, min(1e-3, arrivals[order[nxt]] - now)))
+        eng.close()
+        lat = [done[i][0] - arrivals[i] for i in range(len(reqs))]
+        span = max(d[0] for d in done.values()) - min(arrivals)
+        return lat, span, [done[i][1] for i in range(len(reqs))]
+
+    # saturation: every request available at t = 0
+    _, span_sat, _ = run([0.0] * len(reqs))
+    sat = len(reqs) / span_sat
+    rate = args.load * sat
+    arrivals = [q.arrival for q in reqs]  # Poisson at rate 1: rescale to `rate`
+    arrivals = [a / rate for a in arrivals]
+    lat, span, res = run(arrivals)
+    # a sample of requests solved alone must give the same result bit for bit
+    ctx = M.Context(0)
+    same = True
+    for i in range(0, len(reqs), max(1, len(reqs) // 4)):
+        q = reqs[i]
+        u, v = torch.empty_like(q.u), torch.empty_like(q.v)
+        r1 = ctx.solve(M.point_cost(q.XY, q.n, 3, "sqeuclid"), q.rd, q.cd, q.target, prm, u, v)
+        same &= bool(torch.equal(u, q.u) and torch.equal(v, q.v) and r1.primal_cost == res[i].primal_cost)
+    ctx.close()
+    lat_s = sorted(lat)
+    return {
+        "metric": "serving throughput, point-cloud OT requests to certified gap",
+        "value": round(len(reqs) / span, 3),
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": (f"{len(reqs)} requests, Poisson arrivals at {rate:.2f}/s ({args.load:g} x "
+                                f"saturation), n log-uniform in [512, 8192], d=3 GMM point clouds, "
+                                f"Dirichlet(1) marginals, squared-Euclidean cost / max, target gap in "
+                                f"{{1e-4, 1e-5, 1e-6, 1e-7}}")},
+        "saturation_rps": round(sat, 3),
+        "latency_p50_s": round(lat_s[len(lat_s) // 2], 4),
+        "latency_p99_s": round(lat_s[min(len(lat_s) - 1, int(0.99 * len(lat_s)))], 4),
+        "latency_max_s": round(lat_s[-1], 4),
+        "all_certified": all(r.status == 0 and r.gap <= reqs[i].target for i, r in enumerate(res)),
+        "sample_bitwise_equal_to_alone": same,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--target", type=float, default=1e-6)
+    ap.add_argument("--grid", type=int, default=64, help="grid side k (n = k*k)")
+    ap.add_argument("--problems", type=int, default=8, help="problems cycled through (at most 8)")
+    ap.add_argument("--precision", default="f32", choices=("f32", "f64"))
+    ap.add_argument("--cost-storage", default="f32", choices=("f32", "f16", "bf16", "f64", "points"))
+    ap.add_argument("--workload", default="grid", choices=("grid", "serving"))
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--load", type=float, default=0.7, help="arrival rate as a fraction of saturation")
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is "
+              f"design-only in this build)", file=sys.stderr)
+        return 2
+    out = bench_serving(args) if args.workload == "serving" else bench_grid(args)
     print(json.dumps(out), flush=True)
     return 0
 

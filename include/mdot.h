@@ -107,6 +107,7 @@ typedef struct {
     int64_t pncg_iters, ls_trials, sweeps, cg_resets, ls_failures;
     int64_t fp64_retries; /* F32 sweeps re-run in F64 because of range */
     int64_t cert_sweeps;  /* Round/certificate sweeps */
+    int64_t prec_switches; /* F32 stages continued with FP64 exp after the gradient norm stalled */
 } mdot_result;
 
 typedef struct mdot_ctx mdot_ctx;

@@ -33,7 +33,7 @@
  * that does not change any value.
  *
  * Readings where the paper is silent (also listed in the design doc):
- *   - PNCG is called with tolerance eps_d/2 on the smoothed marginals (Alg. 1 L6).
+ *   - PNCG is called with tolerance eps_d/2 on the smoothed marginals (the inner solve of Alg. 1).
  *   - ||grad g||_1 = ||r(P) - r~||_1 + ||c(P) - c~||_1.
  *   - smoothing weight eps_d/4 is clamped at 1/2.
  *   - line search constants c1 = 0.1, c2 = 0.9 (Hager-Zhang defaults), first trial
@@ -562,7 +562,7 @@ int orc_round_certify(int n, const double* C, const double* u, const double* v, 
     return ORC_OK;
 }
 
-/* KL projection at fixed gamma from z (PNCG or Sinkhorn), as called by Alg. 1 L6. */
+/* KL projection at fixed gamma from z (PNCG or Sinkhorn), as called by the inner solve of Alg. 1. */
 int orc_project(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
                 double* z, const orc_params* prm, int64_t* counts /* [5] or NULL */, double* gnorm)
 {

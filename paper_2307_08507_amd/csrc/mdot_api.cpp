@@ -208,6 +208,10 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
                       &w.colmin, &w.tshift, &w.bdots};
     const int k = sizeof(vec) / sizeof(vec[0]);
     for (int i = 0; i < k; ++i) *vec[i] = (double*)(b + off[i]);
+    // standalone sweeps bind no marginals; point r and c at an n-vector of the workspace so
+    // that no kernel can ever dereference a null pointer (their values are unused there)
+    if (!w.r) w.r = w.xr;
+    if (!w.c) w.c = w.yc;
     w.st = (State*)((char*)pb.d_work + sizeof(Work));
     w.prm = pb.d_prm;
     HIPCHK(ctx, hipMemcpyAsync(pb.d_work, &w, sizeof w, hipMemcpyHostToDevice, ctx->stream));
@@ -336,7 +340,7 @@ static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
     P.c2 = prm.ls_c2;
     P.hmin = hmin;
     P.tol_floor = 1e-14;
-    P.f32_min_tol = 0.0;
+    P.f32_min_tol = 1e-7;  // about the L1 gradient resolution of FP32 exp sums
     P.max_sweeps = prm.max_sweeps;
     P.max_ls_trials = prm.max_ls_trials;
     P.max_pncg_iters = prm.max_pncg_iters;
@@ -369,6 +373,7 @@ static void fill_result(const State& S, double seconds, mdot_result* res)
     res->ls_failures = S.ls_failures;
     res->fp64_retries = S.fallbacks;
     res->cert_sweeps = S.cert_sweeps;
+    res->prec_switches = S.prec_switches;
 }
 
 static int ensure_graph(mdot_ctx* ctx, int n)

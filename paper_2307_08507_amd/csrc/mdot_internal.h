@@ -69,7 +69,7 @@ enum Dot : int {
 struct DevParams {
     double p, q, gamma_i, gamma_f, target, c1, c2, hmin;
     double tol_floor;     // lower limit of the PNCG tolerance eps_d / 2
-    double f32_min_tol;   // F32 sweeps while eps_d / 2 >= this, FP64 exp below it
+    double f32_min_tol;   // F32 sweeps while eps_d / 2 >= this, FP64 exp below it (initial floor)
     int64_t max_sweeps;
     int32_t max_ls_trials, max_pncg_iters;
     int32_t adaptive, exp64_default, warm_start, n;
@@ -88,7 +88,10 @@ struct State {
     double r1[4];   // R1 sums: c.g'(2), r.f''(2)
     double errc_sum;
     double best_ub, best_lb, best_gamma, best_me, last_ub, last_lb;
+    double f32_floor;   // FP64 exp for stages with tolerance below this (raised by the stall guard)
+    double stall_best;  // smallest ||grad||_1 of the stage when it last halved, at iteration stall_k
     int64_t k, sweeps, pncg_iters, ls_trials, cg_resets, ls_failures, fallbacks, cert_sweeps;
+    int64_t stall_k, prec_switches;
 };
 
 // Device buffers of one problem (all FP64 unless noted). 2n-vectors hold rows then columns.

@@ -43,24 +43,52 @@ namespace mdot {
 
 static_assert(kBR == 64, "a sweep tile has one row per lane of a wave64");
 
-__device__ __forceinline__ double wave_sum(double v)
+// ------------------------------------------------------------------ cross-lane reductions
+// DPP moves of an FP64 value (two 32-bit halves): lane i receives v from the lane the control
+// selects; lanes outside `ROW_MASK` or whose source lies outside the row receive `id`.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_d(double id, double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const uint64_t b = __builtin_bit_cast(uint64_t, v), o = __builtin_bit_cast(uint64_t, id);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(b >> 32), CTRL,
+                                                               ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
-__device__ __forceinline__ double wave_min(double v)
+__device__ __forceinline__ double readlane_d(double v, int lane)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
-__device__ __forceinline__ double wave_max(double v)
+
+template <int OP>  // 0: sum, 1: min, 2: max
+__device__ __forceinline__ double red_op(double a, double b)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    if constexpr (OP == 0) return a + b;
+    else if constexpr (OP == 1) return fmin(a, b);
+    else return fmax(a, b);
 }
+
+// Reduction over the 64 lanes of a wave in a fixed order: inclusive scans within each row of
+// 16 lanes (row_shr 1, 2, 4, 8), then row 0 into row 1 and row 2 into row 3 (row_bcast:15),
+// then rows 0-1 into rows 2-3 (row_bcast:31); lane 63 holds the result, returned to all lanes.
+template <int OP>
+__device__ __forceinline__ double wave_reduce(double v)
+{
+    const double id = (OP == 0) ? 0.0 : (OP == 1 ? INFINITY : -INFINITY);
+    v = red_op<OP>(v, dpp_d<0x111>(id, v));
+    v = red_op<OP>(v, dpp_d<0x112>(id, v));
+    v = red_op<OP>(v, dpp_d<0x114>(id, v));
+    v = red_op<OP>(v, dpp_d<0x118>(id, v));
+    v = red_op<OP>(v, dpp_d<0x142, 0xa>(id, v));
+    v = red_op<OP>(v, dpp_d<0x143, 0xc>(id, v));
+    return readlane_d(v, 63);
+}
+__device__ __forceinline__ double wave_sum(double v) { return wave_reduce<0>(v); }
+__device__ __forceinline__ double wave_min(double v) { return wave_reduce<1>(v); }
+__device__ __forceinline__ double wave_max(double v) { return wave_reduce<2>(v); }
 
 // ------------------------------------------------------------------ cost access
 // Dense costs are read with buffer loads through a resource descriptor based at the first
@@ -317,8 +345,8 @@ __device__ __forceinline__ double rows_reduce_f32(const float rp[kRPW], float* r
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) s += (double)src[k];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
+    s += dpp_d<0xb1>(0.0, s);  // quad_perm [1,0,3,2]
+    s += dpp_d<0x4e>(0.0, s);  // quad_perm [2,3,0,1]
     return s;
 }
 
@@ -382,6 +410,19 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     const int n = w.n;
     const double alpha = S.alpha;
     const double g2 = S.gamma * w.scale * LOG2E_D;
+    const int j0 = t.j0lane;
+    Cost cost(w, t.i0);
+    cost.cols(j0);
+    const int rbase = t.wave * kRPW;
+    const int nrows = min(kRPW, n - (t.i0 + rbase));  // rows of this wave (may be <= 0)
+    // loads of a batch of rows are issued before any compute on them (all 16 rows of the wave
+    // for <= 8 B per lane-row, 8 rows for wider ones); the first batch does not depend on the
+    // solver state and is issued before the per-row and per-column set-up, which it overlaps
+    constexpr int RB = sizeof(typename Cost::Raw) <= 8 ? kRPW : kRPW / 2;
+    typename Cost::Raw raw[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (r < nrows) raw[r] = cost.load(rbase + r, j0);
     // per-row values: shift s_i (predicted log row sum) and A_i = (u_i - lz_i) log2 e;
     // per-column V_j = (v_j + alpha p_j) log2 e, one column per thread, through LDS
     if (t.tid < kBR) {
@@ -407,7 +448,6 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     __syncthreads();
     const double SI = wave_max(sS[t.lane]);  // S_I = max_i s_i over the kBR (= 64) rows
     if (t.tid < kBR) sWt[t.tid] = exp(sS[t.tid] - SI);
-    const int j0 = t.j0lane;
     double V[4];
     bool ok[4];
 #pragma unroll
@@ -417,23 +457,17 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     }
     __syncthreads();
 
-    Cost cost(w, t.i0);
-    cost.cols(j0);
-    const int rbase = t.wave * kRPW;
-    const int nrows = min(kRPW, n - (t.i0 + rbase));  // rows of this wave (may be <= 0)
-    // issue the loads of a batch of rows before any compute on them (16 rows for <= 8 B per
-    // lane-row, 8 rows for wider ones)
-    constexpr int RB = sizeof(typename Cost::Raw) <= 8 ? kRPW : kRPW / 2;
     double col64[4] = {0, 0, 0, 0};
     if constexpr (!E64) {
         float col32[4] = {0, 0, 0, 0};
         float rp[kRPW];
 #pragma unroll
         for (int b = 0; b < kRPW; b += RB) {
-            typename Cost::Raw raw[RB];
+            if (b > 0) {
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
-                if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+                for (int r = 0; r < RB; ++r)
+                    if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+            }
 #pragma unroll
             for (int r0 = 0; r0 < RB; ++r0) {
                 const int r = b + r0;
@@ -466,10 +500,11 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     } else {
 #pragma unroll
         for (int b = 0; b < kRPW; b += RB) {
-            typename Cost::Raw raw[RB];
+            if (b > 0) {
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
-                if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+                for (int r = 0; r < RB; ++r)
+                    if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+            }
 #pragma unroll
             for (int r0 = 0; r0 < RB; ++r0) {
                 const int r = b + r0;
@@ -716,7 +751,7 @@ struct Comb {
     double a, b, c, d, e;
 };
 
-template <int OP>  // 0: fma(x, f, acc), 1: min, 2: max
+template <int OP>  // 0: fma(x, f, acc), 1: min, 2: max (red_op follows the same codes)
 __device__ __forceinline__ double fold_op(double acc, double x, double f)
 {
     if constexpr (OP == 0) return fma(x, f, acc);
@@ -750,12 +785,20 @@ __device__ __forceinline__ double lane_fold(const double* __restrict__ base, siz
     return acc;
 }
 
-// Xor butterfly over the L lanes of a group: every lane ends with the same value (each
-// pairwise step is commutative), and the order depends only on L. Called by whole waves.
+// Fold over the L lanes of a group (L a power of two, groups aligned to L): scans towards
+// lower lanes (row_shl 1, 2, 4, 8 within a row of 16, then lanes 16 and 32 further on), so
+// lane 0 of each group ends with the group's value; the order depends only on L. Called by
+// whole waves; the other lanes end with partial values.
 template <int OP>
 __device__ __forceinline__ double group_fold(double v, int L)
 {
-    for (int s = 1; s < L; s <<= 1) v = fold_op<OP>(v, __shfl_xor(v, s, 64), 1.0);
+    const double id = (OP == 0) ? 0.0 : (OP == 1 ? INFINITY : -INFINITY);
+    if (L >= 2) v = red_op<OP>(v, dpp_d<0x101>(id, v));
+    if (L >= 4) v = red_op<OP>(v, dpp_d<0x102>(id, v));
+    if (L >= 8) v = red_op<OP>(v, dpp_d<0x104>(id, v));
+    if (L >= 16) v = red_op<OP>(v, dpp_d<0x108>(id, v));
+    if (L >= 32) v = red_op<OP>(v, __shfl_down(v, 16, 64));
+    if (L >= 64) v = red_op<OP>(v, __shfl_down(v, 32, 64));
     return v;
 }
 
@@ -873,7 +916,7 @@ __device__ __forceinline__ void next_stage(State& S, const DevParams& P)
     S.w = fmin(S.eps_d / 4.0, 0.5);     // variable smoothing weight
     S.tol = fmax(S.eps_d / 2.0, P.tol_floor);
     // precision ladder: FP32 exp while the tolerance is far above FP32 resolution
-    S.exp64_stage = P.exp64_default || S.tol < P.f32_min_tol;
+    S.exp64_stage = P.exp64_default || S.tol < S.f32_floor;
     S.exp64 = S.exp64_stage;
     S.alpha_prev = 1.0;
     S.vec_action |= VA_STAGE_INIT;
@@ -912,6 +955,8 @@ __device__ __forceinline__ void start_line_search(State& S)
 
 // Scalar logic after a sweep: line search (App. B), PNCG bookkeeping (Alg. 2), stage
 // control (Alg. 1) and the certified-gap termination. `sum` holds the global dots.
+constexpr int kStallF32 = 256, kStallF64 = 4096;
+
 __device__ __forceinline__ void decide(State& S, const DevParams& P, const double* sum)
 {
     const int mode = S.sweep_mode;
@@ -952,6 +997,8 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
             S.vec_action = VA_ACCEPT;
             S.gnorm = gn;
             S.k = 1;
+            S.stall_best = gn;
+            S.stall_k = 1;
             S.dphi0 = sg;
             if (gn <= S.tol) end_stage(S, P, true);
             else if (!(sg < 0.0) || S.budget_stop) end_stage(S, P, false);
@@ -984,8 +1031,26 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
             S.k++;
             S.gnorm = gn;
             S.dphi0 = pg;
+            // precision ladder and stall guard: a stage whose gradient norm has not halved in
+            // kStallF32 iterations with FP32 exp continues with FP64 exp (and so do the later
+            // stages, whose tolerances are smaller); after kStallF64 more iterations without
+            // halving it ends unconverged
+            bool stalled = false;
+            if (gn <= 0.5 * S.stall_best) {
+                S.stall_best = gn;
+                S.stall_k = S.k;
+            } else if (!S.exp64_stage && S.k - S.stall_k >= kStallF32) {
+                S.exp64_stage = 1;
+                S.exp64 = 1;
+                S.f32_floor = fmax(S.f32_floor, 2.0 * S.tol);
+                S.prec_switches++;
+                S.stall_best = gn;
+                S.stall_k = S.k;
+            } else if (S.k - S.stall_k >= kStallF64) {
+                stalled = true;
+            }
             if (gn <= S.tol) end_stage(S, P, true);
-            else if (S.k > P.max_pncg_iters || S.budget_stop || !(pg < 0.0)) end_stage(S, P, false);
+            else if (S.k > P.max_pncg_iters || S.budget_stop || !(pg < 0.0) || stalled) end_stage(S, P, false);
             else start_line_search(S);
             return;
         }
@@ -1132,10 +1197,126 @@ struct FinShared {
     double red[kNDot * 4];
 };
 
+// Raw inputs of entry k for entry_after and the finalizer, loaded without data-dependent
+// branches (k is clamped into range by the caller) so that every load of an entry is in
+// flight at once. The marginal is read only when the update starts a stage: only solves do
+// that, and only solves bind r and c.
+struct EntryIn {
+    double z, p, lz, logt, rt, zprev, lzt, m, g;
+};
+__device__ __forceinline__ EntryIn entry_load(const Work& w, const SweepArgs& a, int k)
+{
+    const int n = w.n;
+    EntryIn in;
+    in.z = w.z[k];
+    in.p = w.p[k];
+    in.lz = w.lz[k];
+    in.logt = w.logt[k];
+    in.rt = w.rt[k];
+    in.zprev = w.zprev[k];
+    in.lzt = w.lzt[k];
+    in.m = (a.va & VA_STAGE_INIT) ? *((k < n) ? w.r + k : w.c + (k - n)) : 0.0;
+    in.g = w.g[k];
+    return in;
+}
+// entry_after from loaded inputs (same arithmetic, so bit-identical to the sweeps' copy)
+__device__ __forceinline__ Entry entry_from(const EntryIn& in, const SweepArgs& a, int n)
+{
+    Entry e;
+    e.z = in.z;
+    e.p = in.p;
+    e.lz = in.lz;
+    e.logt = in.logt;
+    e.rt = in.rt;
+    e.zprev = in.zprev;
+    if (a.va & VA_ACCEPT) {
+        e.z = fma(a.alpha_acc, e.p, e.z);
+        e.lz = in.lzt;
+        const double sdir = e.logt - e.lz;
+        e.p = a.reset ? sdir : fma(a.beta, e.p, sdir);
+    }
+    e.zacc = e.z;
+    if (a.va & VA_STAGE_INIT) {
+        e.rt = fma(1.0 - a.w, in.m, a.w / n);
+        e.logt = log(e.rt);
+        if (a.stage == 1) {
+            e.z = e.logt;
+            e.zprev = e.logt;
+        } else {
+            const double zp = e.zprev;
+            e.zprev = e.z;
+            e.z = fma(a.ws_ratio, e.z - zp, e.z);
+        }
+        e.p = 0.0;
+        e.lz = e.logt;
+    }
+    return e;
+}
+
+// Store the pending vector update of entry k and return the gradient entry at z.
+__device__ __forceinline__ double store_update(const Work& w, const SweepArgs& a, const Entry& e, double g_old, int k)
+{
+    const int va = a.va;
+    if (va & (VA_ACCEPT | VA_STAGE_INIT)) {
+        w.z[k] = e.z;
+        w.p[k] = e.p;
+        w.lz[k] = e.lz;
+    }
+    double g_cur = g_old;
+    if (va & VA_STAGE_INIT) {
+        w.rt[k] = e.rt;
+        w.logt[k] = e.logt;
+        w.zprev[k] = e.zprev;
+        g_cur = 0.0;
+        w.g[k] = g_cur;
+    } else if (va & VA_ACCEPT) {
+        g_cur = exp(e.lz) - e.rt;
+        w.g[k] = g_cur;
+    }
+    if (va & VA_SAVE_BEST) w.zbest[k] = e.zacc;
+    if ((va & VA_ROUND_PREP) && k < w.n) w.xr[k] = round_x(w.r[k], e.lz);
+    return g_cur;
+}
+
+// LSE finalize of one entry group when every partial fits one load per slot (m <= 8 L) and
+// nrt <= 256: all loads of the group (tile shifts, partials, entry inputs) are issued before
+// any arithmetic.
+__device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a, int k, bool valid, int l, int L,
+                                              bool e64, double v[kNDot])
+{
+    const int n = w.n, nrt = w.nrt;
+    const int kc = valid ? k : 0;
+    const bool row = kc < n;
+    const int m = row ? w.nct : nrt;
+    const int lane = threadIdx.x & 63;
+    const double* base = row ? w.rowpart + kc : w.colpart + (kc - n);
+    double ts[4], x[8], f[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ts[q] = w.tshift[min(lane + 64 * q, nrt - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int I = min(l + u * L, m - 1);
+        x[u] = base[(size_t)I * n];
+        f[u] = w.tshift[min(l + u * L, nrt - 1)];
+    }
+    const EntryIn in = entry_load(w, a, kc);
+    // M = max_I S_I, the same value in every lane
+    const double M = wave_max(fmax(fmax(ts[0], ts[1]), fmax(ts[2], ts[3])));
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (l + u * L < m) acc = fma(x[u], row ? 1.0 : exp(f[u] - M), acc);
+    Comb cb{};
+    cb.a = group_fold<0>(acc, L);
+    if (!valid || l != 0) return;
+    const Entry e = entry_from(in, a, n);
+    const double g_cur = store_update(w, a, e, in.g, k);
+    finalize_entry(w, a, e, g_cur, k, SM_LSE, e64, cb, M, v);
+}
+
 // Finalize workgroup `blk` of the problem's `nblk` (= fin_grid(n)) workgroups. Entry k is
 // handled by an L-lane group (L = fin_lanes(n)); the groups are laid out in virtual blocks of
-// kVecWG / L entries, which the workgroups take in a grid-stride loop. Every load of an
-// iteration is issued before its first use (the kernel is latency-bound).
+// kVecWG / L entries, which the workgroups take in a grid-stride loop.
 __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int nblk, FinShared& sh)
 {
     const State* Sp = w.st + parity;
@@ -1148,50 +1329,32 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     const int mode = Sp->sweep_mode;
     const bool active = !Sp->done && mode != SM_NONE;
     const bool e64 = Sp->exp64 != 0;
-    // M = max_I S_I (uniform loads); column partials are scaled by exp(S_I - M) when combined
-    double M = 0.0;
-    if (active && (mode == SM_LSE || mode == SM_R1)) {
-        double mx = -INFINITY;  // every wave forms the same maximum
-        for (int I = tid & 63; I < w.nrt; I += 64) mx = fmax(mx, w.tshift[I]);
-        M = wave_max(mx);
-    }
+    const bool fast = active && mode == SM_LSE && w.nrt <= 256 && w.nrt <= 8 * L && w.nct <= 8 * L;
     double v[kNDot];
 #pragma unroll
     for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
+    // M = max_I S_I (every wave forms the same maximum) for the general path
+    double M = 0.0;
+    if (!fast && active && (mode == SM_LSE || mode == SM_R1)) {
+        double mx = -INFINITY;
+        for (int I = tid & 63; I < w.nrt; I += 64) mx = fmax(mx, w.tshift[I]);
+        M = wave_max(mx);
+    }
     const int nvb = fin_vblocks(n);
     for (int vb = blk; vb < nvb; vb += nblk) {
         const int k = (vb * kVecWG + tid) >> lgL;
         const bool valid = k < 2 * n;
-        const bool lead = valid && l == 0;
-        Entry e{};
-        double g_old = 0.0;
-        if (lead) {
-            e = entry_after(w, a, k);
-            g_old = w.g[k];
+        if (fast) {
+            fin_lse_entry(w, a, k, valid, l, L, e64, v);
+            continue;
         }
+        const int kc = valid ? k : 0;
+        const EntryIn in = entry_load(w, a, kc);
         Comb cb{};
         if (active) cb = combine(w, mode, k, valid, l, L, M);
-        if (!lead) continue;
-        // store the pending vector update of this entry
-        const int va = a.va;
-        if (va & (VA_ACCEPT | VA_STAGE_INIT)) {
-            w.z[k] = e.z;
-            w.p[k] = e.p;
-            w.lz[k] = e.lz;
-        }
-        double g_cur = g_old;
-        if (va & VA_STAGE_INIT) {
-            w.rt[k] = e.rt;
-            w.logt[k] = e.logt;
-            w.zprev[k] = e.zprev;
-            g_cur = 0.0;
-            w.g[k] = g_cur;
-        } else if (va & VA_ACCEPT) {
-            g_cur = exp(e.lz) - e.rt;
-            w.g[k] = g_cur;
-        }
-        if (va & VA_SAVE_BEST) w.zbest[k] = e.zacc;
-        if ((va & VA_ROUND_PREP) && k < n) w.xr[k] = round_x(w.r[k], e.lz);
+        if (!valid || l != 0) continue;
+        const Entry e = entry_from(in, a, n);
+        const double g_cur = store_update(w, a, e, in.g, k);
         if (active) finalize_entry(w, a, e, g_cur, k, mode, e64, cb, M, v);
     }
     if (active) block_dots(v, w.bdots + (size_t)blk * kNDot, tid, sh.red);
@@ -1204,48 +1367,40 @@ __global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int
 }
 
 // ------------------------------------------------------------------ the decide kernel
-// One workgroup per problem: reduce the finalize kernel's per-workgroup dots in a fixed order,
-// run the scalar state machine on slot `parity` and write the next state into the other slot
-// (a finished or idle state is carried over with its vector update cleared).
-struct DecideShared {
-    double red[kNDot * 4];
-    double glob[kNDot];
-};
+// One wave per problem: reduce the finalize kernel's per-workgroup dots in a fixed order, run
+// the scalar state machine on slot `parity` (every lane holds the same values; lane 0 stores)
+// and write the next state into the other slot (a finished or idle state is carried over with
+// its vector update cleared).
+constexpr int kDecideWG = 64;
 
-__device__ __forceinline__ void decide_body(const Work& w, int parity, DecideShared& sh)
+__device__ __forceinline__ void decide_body(const Work& w, int parity)
 {
     const State* Sp = w.st + parity;
-    const int tid = threadIdx.x;
-    const bool active = !Sp->done && Sp->sweep_mode != SM_NONE;
+    const int lane = threadIdx.x;
+    State S = *Sp;
+    const DevParams P = *w.prm;
+    const bool active = !S.done && S.sweep_mode != SM_NONE;
     if (active) {
         const int nblk = fin_grid(w.n);
         double v[kNDot];
 #pragma unroll
         for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
-        for (int b = tid; b < nblk; b += kVecWG)
+        for (int b = lane; b < nblk; b += 64)
 #pragma unroll
             for (int d = 0; d < kNDot; ++d) v[d] += w.bdots[(size_t)b * kNDot + d];
-        block_dots(v, sh.glob, tid, sh.red);
-    }
-    if (tid == 0) {
-        State S = *Sp;
-        if (active) {
-            double sum[kNDot];
+        double sum[kNDot];
 #pragma unroll
-            for (int d = 0; d < kNDot; ++d) sum[d] = sh.glob[d];
-            const DevParams P = *w.prm;
-            decide(S, P, sum);
-        } else {
-            S.vec_action = 0;
-        }
-        w.st[parity ^ 1] = S;
+        for (int d = 0; d < kNDot; ++d) sum[d] = wave_sum(v[d]);
+        decide(S, P, sum);
+    } else {
+        S.vec_action = 0;
     }
+    if (lane == 0) w.st[parity ^ 1] = S;
 }
 
-__global__ void __launch_bounds__(kVecWG) k_decide(const Work* __restrict__ wp, int parity)
+__global__ void __launch_bounds__(kDecideWG) k_decide(const Work* __restrict__ wp, int parity)
 {
-    __shared__ DecideShared sh;
-    decide_body(*wp, parity, sh);
+    decide_body(*wp, parity);
 }
 
 // ------------------------------------------------------------------ batched kernels
@@ -1285,13 +1440,9 @@ __global__ void __launch_bounds__(kVecWG) k_fin_batch(const BatchDesc* __restric
     }
 }
 
-__global__ void __launch_bounds__(kVecWG) k_decide_batch(const BatchDesc* __restrict__ bd, int parity)
+__global__ void __launch_bounds__(kDecideWG) k_decide_batch(const BatchDesc* __restrict__ bd, int parity)
 {
-    __shared__ DecideShared sh;
-    for (int b = blockIdx.x; b < bd->nitems; b += gridDim.x) {
-        decide_body(*bd->items[b], parity, sh);
-        __syncthreads();
-    }
+    for (int b = blockIdx.x; b < bd->nitems; b += gridDim.x) decide_body(*bd->items[b], parity);
 }
 
 __global__ void k_gather_done(const BatchDesc* __restrict__ bd, int* out)
@@ -1314,7 +1465,8 @@ __global__ void k_init(const Work* __restrict__ wp)
     S.eps_d = P.hmin / pow(S.gamma, P.p);
     S.w = fmin(S.eps_d / 4.0, 0.5);
     S.tol = fmax(S.eps_d / 2.0, P.tol_floor);
-    S.exp64_stage = P.exp64_default || S.tol < P.f32_min_tol;
+    S.f32_floor = P.f32_min_tol;
+    S.exp64_stage = P.exp64_default || S.tol < S.f32_floor;
     S.exp64 = S.exp64_stage;
     S.alpha_prev = 1.0;
     S.vec_action = VA_STAGE_INIT;
@@ -1477,7 +1629,7 @@ int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
     MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
     hipLaunchKernelGGL(k_fin, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kVecWG), 0, s, wd, parity);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideWG), 0, s, wd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1497,7 +1649,7 @@ int launch_step_batch(int cc, const BatchDesc* bd, int parity, int sweep_grid, i
     MDOT_CC_SWITCH(cc, L_)
 #undef L_
     hipLaunchKernelGGL(k_fin_batch, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
-    hipLaunchKernelGGL(k_decide_batch, dim3(kMaxBatch), dim3(kVecWG), 0, s, bd, parity);
+    hipLaunchKernelGGL(k_decide_batch, dim3(kMaxBatch), dim3(kDecideWG), 0, s, bd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

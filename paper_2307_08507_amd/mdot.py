@@ -42,7 +42,7 @@ class Result(ct.Structure):
                 ("seconds", ct.c_double), ("stages", ct.c_int32), ("status", ct.c_int32),
                 ("pncg_iters", ct.c_int64), ("ls_trials", ct.c_int64), ("sweeps", ct.c_int64),
                 ("cg_resets", ct.c_int64), ("ls_failures", ct.c_int64), ("fp64_retries", ct.c_int64),
-                ("cert_sweeps", ct.c_int64)]
+                ("cert_sweeps", ct.c_int64), ("prec_switches", ct.c_int64)]
 
 
 class MdotError(RuntimeError):
@@ -149,6 +149,7 @@ class SolveResult:
     ls_failures: int
     fp64_retries: int
     cert_sweeps: int
+    prec_switches: int
 
 
 class Context:

@@ -150,6 +150,11 @@ def grid_problem(k: int, family: str, cost: str, seed: int, dtype=np.float64):
     return grid_cost(k, cost, dtype), r, c
 
 
+def grid_problem_marginals(k: int, family: str, seed: int) -> np.ndarray:
+    """The marginal `grid_problem` draws from `family` with `seed` (the cost is formed apart)."""
+    return FAMILIES[family](k, seed)
+
+
 def gmm_points(n: int, d: int, seed: int) -> np.ndarray:
     """n points in R^d from a K ~ U{1..8}-component Gaussian mixture: means N(0, 4 I),
     covariances A A^T / 3 + 0.1 I, equal component weights. float32 (n, d)."""
