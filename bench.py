@@ -88,6 +88,25 @@ def _grid_num(X, kind):
     return out
 
 
+def measured_traffic(n: int, storage: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it was taken
+    on this workload with the current kernel source (else None)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_sweep_n{n}_{storage}_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2307_08507_amd", "csrc", "mdot_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "|", "#")):
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(C64, prob, sweeps: int, stages: int, n_sweeps_sample: int, n_cert_sample: int, label: str):
     """Time the FP64 CPU oracle on a bounded sample and extrapolate to one full solve."""
     import numpy as np
@@ -169,7 +188,8 @@ def bench_grid(args) -> dict:
         per_launch = {"bytes_per_launch": n * n * BYTES[args.cost_storage]}
         achieved = per_launch["bytes_per_launch"] / (ms * 1e-3) / 1e9
     roof = {"bound": bound, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 4) if peak else None, "traffic": None,
+            "frac": round(achieved / peak, 4) if peak else None,
+            "traffic": measured_traffic(n, args.cost_storage) if args.precision == "f32" else None,
             "kernel": "k_sweep (fused two-sided LSE sweep)", **per_launch}
     out = {
         "metric": f"time-to-gap {args.target:g} at n={n}",
