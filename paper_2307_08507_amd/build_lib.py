@@ -34,8 +34,10 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(OUT_DIR, src + ".o")
         cmd = [hipcc(), *common, "-c", path, "-o", obj]
         if src.endswith(".hip"):
+            # kernel arguments (a few pointers and ints) are preloaded into SGPRs at dispatch, so a
+            # kernel's first dependent load does not wait for a kernarg-segment fetch
             cmd += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                    "-munsafe-fp-atomics"]
+                    "-munsafe-fp-atomics", "-mllvm", "-amdgpu-kernarg-preload-count=16"]
         else:
             pass
         if verbose:

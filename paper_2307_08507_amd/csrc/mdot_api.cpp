@@ -35,8 +35,8 @@ struct ProblemBufs {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     int cap_n = 0;
-    Work* d_work = nullptr;  // Work followed by State[2]
-    DevParams* d_prm = nullptr;
+    Work* d_work = nullptr;  // the Control block (Work, State[2], DevParams, dots)
+    DevParams* d_prm = nullptr;  // inside the Control block
     Work host_work{};
 };
 
@@ -114,7 +114,7 @@ static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
         2 * N, 2 * N,                                                 // gp fpp
         nct * N, nrt * N, nct * N, nct * N,                           // rowpart colpart rowpart2 rowpart3
         2 * nct * N, 2 * nrt * N,                                     // rowmin colmin
-        nrt, (size_t)fin_grid(n) * kNDot,                           // tshift bdots
+        nrt,                                                          // tshift
     };
     size_t off = 0;
     const int k = sizeof(counts) / sizeof(counts[0]);
@@ -128,14 +128,13 @@ static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
 
 static size_t problem_footprint(int n)
 {
-    return workspace_bytes(n) + sizeof(Work) + 2 * sizeof(State) + sizeof(DevParams);
+    return workspace_bytes(n) + sizeof(Control);
 }
 
 static void free_bufs(ProblemBufs& pb)
 {
     if (pb.ws) (void)hipFree(pb.ws);
     if (pb.d_work) (void)hipFree(pb.d_work);
-    if (pb.d_prm) (void)hipFree(pb.d_prm);
     pb = ProblemBufs{};
 }
 
@@ -158,8 +157,8 @@ static int ensure_scratch(mdot_ctx* ctx, int n)
 static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n)
 {
     if (!pb.d_work) {
-        HIPCHK(ctx, hipMalloc(&pb.d_work, sizeof(Work) + 2 * sizeof(State)));
-        HIPCHK(ctx, hipMalloc(&pb.d_prm, sizeof(DevParams)));
+        HIPCHK(ctx, hipMalloc(&pb.d_work, sizeof(Control)));
+        pb.d_prm = &reinterpret_cast<Control*>(pb.d_work)->prm;
     }
     if (n <= pb.cap_n && pb.ws) return ensure_scratch(ctx, n);
     const size_t need = workspace_bytes(n);
@@ -205,15 +204,17 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
     w.c = c;
     double** vec[] = {&w.rt, &w.logt, &w.z, &w.zprev, &w.zbest, &w.p, &w.g, &w.lz, &w.lzt, &w.xr, &w.yc,
                       &w.errc, &w.gp, &w.fpp, &w.rowpart, &w.colpart, &w.rowpart2, &w.rowpart3, &w.rowmin,
-                      &w.colmin, &w.tshift, &w.bdots};
+                      &w.colmin, &w.tshift};
     const int k = sizeof(vec) / sizeof(vec[0]);
     for (int i = 0; i < k; ++i) *vec[i] = (double*)(b + off[i]);
     // standalone sweeps bind no marginals; point r and c at an n-vector of the workspace so
     // that no kernel can ever dereference a null pointer (their values are unused there)
     if (!w.r) w.r = w.xr;
     if (!w.c) w.c = w.yc;
-    w.st = (State*)((char*)pb.d_work + sizeof(Work));
-    w.prm = pb.d_prm;
+    Control* ctl = reinterpret_cast<Control*>(pb.d_work);
+    w.st = ctl->st;
+    w.prm = &ctl->prm;
+    w.bdots = ctl->bdots;
     HIPCHK(ctx, hipMemcpyAsync(pb.d_work, &w, sizeof w, hipMemcpyHostToDevice, ctx->stream));
     return MDOT_OK;
 }

@@ -123,9 +123,20 @@ struct Work {
     double* rowmin;    // [2 * nct * n] per-tile row minima (two variants)
     double* colmin;    // [2 * nrt * n] per-tile column minima
     double* tshift;    // [nrt] per-row-tile column shift S_I
-    double* bdots;     // [fin_grid(n) * kNDot] per-workgroup dot products of the finalize kernel
+    double* bdots;     // [fin_grid(n) * kNDot] per-workgroup dot products (in the control block)
     State* st;         // [2] state slots: step k reads slot k % 2, its decide kernel writes the other
     DevParams* prm;
+};
+
+// Control block of one problem in device memory: the Work struct followed, at fixed offsets,
+// by the two state slots, the parameters and the finalize kernel's per-workgroup dots. Kernels
+// address these from the Work pointer itself, so their loads need not wait for the Work load.
+// Work::st, Work::prm and Work::bdots point at the same members.
+struct Control {
+    Work w;
+    State st[2];
+    DevParams prm;
+    double bdots[kFinMaxGrid * kNDot];
 };
 
 // Problems in flight in one batched launch: logical tile g of the step belongs to item b with

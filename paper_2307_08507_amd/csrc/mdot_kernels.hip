@@ -43,6 +43,13 @@ namespace mdot {
 
 static_assert(kBR == 64, "a sweep tile has one row per lane of a wave64");
 
+// Members of the control block that starts at a Work struct in device memory. `w` must be a
+// reference to that struct (not a copy): the addresses follow from &w without loading it.
+__device__ __forceinline__ Control& ctl_of(const Work& w) { return *reinterpret_cast<Control*>(const_cast<Work*>(&w)); }
+__device__ __forceinline__ State* state_slot(const Work& w, int s) { return ctl_of(w).st + s; }
+__device__ __forceinline__ const DevParams& params_of(const Work& w) { return ctl_of(w).prm; }
+__device__ __forceinline__ double* bdots_of(const Work& w) { return ctl_of(w).bdots; }
+
 // ------------------------------------------------------------------ cross-lane reductions
 // DPP moves of an FP64 value (two 32-bit halves): lane i receives v from the lane the control
 // selects; lanes outside `ROW_MASK` or whose source lies outside the row receive `id`.
@@ -157,6 +164,13 @@ struct DenseCost {
             }
         }
         return v;
+    }
+    // Direct-to-LDS load of row r (FP32, n % 4 == 0): lane l's 16 bytes land at lds + 16 l.
+    __device__ __forceinline__ void stage(int r, int j0, void* lds) const
+    {
+        static_assert(DT == MDOT_DT_F32, "staging is for FP32 rows");
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds, 16,
+                                                 (r * n + j0) * kBytes, 0, 0, 0);
     }
     __device__ __forceinline__ void decode(const Raw& v, double c[4]) const
     {
@@ -326,10 +340,33 @@ __device__ __forceinline__ void col_combine_store(double* sbuf, const double v[4
     __syncthreads();
 }
 
+// As col_combine_store, with wave w's values at sbuf + w * stride.
+__device__ __forceinline__ void col_combine_store_strided(double* sbuf, int stride, const double v[4], const TileCtx& t,
+                                                          double* dst, int n, int jt0)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sbuf[t.wave * stride + t.lane * 4 + k] = v[k];
+    __syncthreads();
+    const int col = t.tid;  // kWG == kBC
+    const double a = sbuf[col], b = sbuf[stride + col], c = sbuf[2 * stride + col], d = sbuf[3 * stride + col];
+    if (jt0 + col < n) dst[jt0 + col] = (a + b) + (c + d);
+    __syncthreads();
+}
+
 // LDS of one sweep workgroup: five per-row arrays, the per-wave column buffer, and the
 // per-wave row-partial transpose buffer (kRPW rows x 64 lanes, padded to 65, FP32).
 constexpr int kRowPad = 65;
-constexpr int kSmem = 5 * kBR + 4 * kBC + (4 * kRPW * kRowPad + 1) / 2;
+// The LSE tile lays its LDS out as: five per-row arrays (5 kBR doubles), the column values
+// (kBC doubles), then one region per wave (kWaveRegion doubles) that first receives the wave's
+// second batch of cost rows by direct-to-LDS loads and then, once the wave has read them, holds
+// its row-partial transpose buffer and its slice of the column combine. The other tile kinds
+// use the first 5 kBR + 4 kBC doubles.
+constexpr int kStageMinTiles = 2048;                    // staging pays with more tiles than this
+constexpr int kWaveRegion = 1024;                        // 8 KiB: 8 rows x 64 lanes x 16 B
+constexpr int kRowBufD = (kRPW * kRowPad + 1) / 2;      // transpose buffer, in doubles
+static_assert(kRowBufD + kBC <= kWaveRegion, "wave region too small");
+constexpr int kSmem = 5 * kBR + kBC + 4 * kWaveRegion;
+static_assert(kSmem >= 5 * kBR + 4 * kBC, "LDS for the Round tiles");
 
 // Sum the per-lane FP32 row partials rp[r] of the wave's kRPW rows across the 64 lanes:
 // a transpose through LDS, then 4 lanes per row each sum 16 values in FP64 and combine.
@@ -405,8 +442,11 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     double* sA = sm;
     double* sWt = sm + kBR;
     double* sS = sm + 2 * kBR;
-    double* sCol = sm + 5 * kBR;
-    float* sRow = (float*)(sm + 5 * kBR + 4 * kBC) + t.wave * kRPW * kRowPad;
+    double* sColV = sm + 5 * kBR;
+    double* region = sm + 5 * kBR + kBC;                   // the kWaveRegion per-wave regions
+    double* myRegion = region + t.wave * kWaveRegion;
+    float* sRow = (float*)myRegion;                         // after the staged rows are read
+    double* sColSlices = region + kRowBufD;                 // wave w's slice at + w kWaveRegion
     const int n = w.n;
     const double alpha = S.alpha;
     const double g2 = S.gamma * w.scale * LOG2E_D;
@@ -423,6 +463,20 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
 #pragma unroll
     for (int r = 0; r < RB; ++r)
         if (r < nrows) raw[r] = cost.load(rbase + r, j0);
+    // FP32 rows with n % 4 == 0 and more tiles than stay resident at once: the second batch
+    // goes straight to the wave's LDS region, so all 16 rows of the wave are in flight from the
+    // start without holding registers. With a single round of workgroups (n <= ~5800) the
+    // extra requests only delay the first batch, so it is not used there.
+    constexpr bool kCanStage = std::is_same<Cost, DenseCost<MDOT_DT_F32>>::value && RB < kRPW;
+    bool staged = false;
+    if constexpr (kCanStage) {
+        staged = cost.vec && w.nrt * w.nct > kStageMinTiles;
+        if (staged) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (RB + r < nrows) cost.stage(rbase + RB + r, j0, myRegion + r * (kWaveRegion / RB));
+        }
+    }
     // per-row values: shift s_i (predicted log row sum) and A_i = (u_i - lz_i) log2 e;
     // per-column V_j = (v_j + alpha p_j) log2 e, one column per thread, through LDS
     if (t.tid < kBR) {
@@ -443,7 +497,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
             const Entry e = entry_after(w, S, n + j);
             vv = fma(alpha, e.p, e.z) * LOG2E_D;
         }
-        sCol[t.tid] = vv;
+        sColV[t.tid] = vv;
     }
     __syncthreads();
     const double SI = wave_max(sS[t.lane]);  // S_I = max_i s_i over the kBR (= 64) rows
@@ -453,7 +507,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         ok[k] = j0 + k < n;
-        V[k] = sCol[t.lane * 4 + k];
+        V[k] = sColV[t.lane * 4 + k];
     }
     __syncthreads();
 
@@ -464,9 +518,22 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
 #pragma unroll
         for (int b = 0; b < kRPW; b += RB) {
             if (b > 0) {
+                if constexpr (kCanStage) {
+                    if (staged) {
+                        __builtin_amdgcn_s_waitcnt(0);  // the wave's direct-to-LDS loads have landed
+                        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+                        for (int r = 0; r < RB; ++r)
+                            if (b + r < nrows)
+                                raw[r] = reinterpret_cast<const typename Cost::Raw*>(myRegion + r * (kWaveRegion / RB))[t.lane];
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                if (!staged) {
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+                }
             }
 #pragma unroll
             for (int r0 = 0; r0 < RB; ++r0) {
@@ -501,9 +568,22 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
 #pragma unroll
         for (int b = 0; b < kRPW; b += RB) {
             if (b > 0) {
+                if constexpr (kCanStage) {
+                    if (staged) {
+                        __builtin_amdgcn_s_waitcnt(0);  // the wave's direct-to-LDS loads have landed
+                        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+                        for (int r = 0; r < RB; ++r)
+                            if (b + r < nrows)
+                                raw[r] = reinterpret_cast<const typename Cost::Raw*>(myRegion + r * (kWaveRegion / RB))[t.lane];
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                if (!staged) {
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+                }
             }
 #pragma unroll
             for (int r0 = 0; r0 < RB; ++r0) {
@@ -526,7 +606,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
             }
         }
     }
-    col_combine_store(sCol, col64, t, 0, w.colpart + (size_t)t.I * n, n, t.J * kBC);
+    col_combine_store_strided(sColSlices, kWaveRegion, col64, t, w.colpart + (size_t)t.I * n, n, t.J * kBC);
     // every tile of row block I writes the same S_I, so the finalizer of any column block
     // reads it from one of the tiles it waited for
     if (t.tid == 0) w.tshift[t.I] = SI;
@@ -1153,7 +1233,7 @@ __device__ __forceinline__ void sweep_tiles(const Work& w, const SweepArgs& a, c
 template <int CC, bool ROUND>
 __device__ __forceinline__ void sweep_kernel_body(const Work& w, int parity, int blk, double* smem)
 {
-    const State* Sp = w.st + parity;
+    const State* Sp = state_slot(w, parity);
     const int mode = Sp->sweep_mode;
     if (mode == SM_NONE || Sp->done) return;
     const bool e64 = Sp->exp64 != 0;
@@ -1176,7 +1256,7 @@ __device__ __forceinline__ void sweep_kernel_body(const Work& w, int parity, int
 template <int CC>
 __device__ __forceinline__ void sweep_any(const Work& w, int parity, int blk, double* smem)
 {
-    const int mode = w.st[parity].sweep_mode;
+    const int mode = state_slot(w, parity)->sweep_mode;
     if (mode == SM_R1 || mode == SM_R2) sweep_kernel_body<CC, true>(w, parity, blk, smem);
     else sweep_kernel_body<CC, false>(w, parity, blk, smem);
 }
@@ -1319,7 +1399,7 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
 // kVecWG / L entries, which the workgroups take in a grid-stride loop.
 __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int nblk, FinShared& sh)
 {
-    const State* Sp = w.st + parity;
+    const State* Sp = state_slot(w, parity);
     const int tid = threadIdx.x;
     const int n = w.n;
     const int L = fin_lanes(n);
@@ -1357,7 +1437,7 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         const double g_cur = store_update(w, a, e, in.g, k);
         if (active) finalize_entry(w, a, e, g_cur, k, mode, e64, cb, M, v);
     }
-    if (active) block_dots(v, w.bdots + (size_t)blk * kNDot, tid, sh.red);
+    if (active) block_dots(v, bdots_of(w) + (size_t)blk * kNDot, tid, sh.red);
 }
 
 __global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int parity)
@@ -1375,10 +1455,10 @@ constexpr int kDecideWG = 64;
 
 __device__ __forceinline__ void decide_body(const Work& w, int parity)
 {
-    const State* Sp = w.st + parity;
+    const State* Sp = state_slot(w, parity);
     const int lane = threadIdx.x;
     State S = *Sp;
-    const DevParams P = *w.prm;
+    const DevParams P = params_of(w);
     const bool active = !S.done && S.sweep_mode != SM_NONE;
     if (active) {
         const int nblk = fin_grid(w.n);
@@ -1387,7 +1467,7 @@ __device__ __forceinline__ void decide_body(const Work& w, int parity)
         for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
         for (int b = lane; b < nblk; b += 64)
 #pragma unroll
-            for (int d = 0; d < kNDot; ++d) v[d] += w.bdots[(size_t)b * kNDot + d];
+            for (int d = 0; d < kNDot; ++d) v[d] += bdots_of(w)[(size_t)b * kNDot + d];
         double sum[kNDot];
 #pragma unroll
         for (int d = 0; d < kNDot; ++d) sum[d] = wave_sum(v[d]);
@@ -1395,7 +1475,7 @@ __device__ __forceinline__ void decide_body(const Work& w, int parity)
     } else {
         S.vec_action = 0;
     }
-    if (lane == 0) w.st[parity ^ 1] = S;
+    if (lane == 0) *state_slot(w, parity ^ 1) = S;
 }
 
 __global__ void __launch_bounds__(kDecideWG) k_decide(const Work* __restrict__ wp, int parity)
