@@ -195,6 +195,11 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
     w.n = n;
     w.nrt = tiles_r(n);
     w.nct = tiles_c(n);
+    w.fin_L = fin_lanes(n);
+    w.fin_lgL = 0;
+    while ((1 << w.fin_lgL) < w.fin_L) ++w.fin_lgL;
+    w.fin_nvb = fin_vblocks(n);
+    w.fin_nblk = fin_grid(n);
     w.cost_kind = cost ? cost->kind : MDOT_COST_DENSE;
     w.dtype = cost ? cost->dtype : MDOT_DT_F32;
     w.d = cost ? cost->d : 0;

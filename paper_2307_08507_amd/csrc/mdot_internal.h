@@ -98,6 +98,7 @@ struct State {
 struct Work {
     int32_t n, nrt, nct;     // size, row tiles, column tiles
     int32_t cost_kind, dtype, d, pad;
+    int32_t fin_L, fin_lgL, fin_nvb, fin_nblk;  // fin_lanes(n), log2 of it, fin_vblocks(n), fin_grid(n)
     const void* cost;        // dense cost or coordinates X then Y
     double scale;            // C = scale * raw
     const double* r;         // original marginals

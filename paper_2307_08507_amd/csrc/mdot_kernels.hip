@@ -252,7 +252,8 @@ __device__ __forceinline__ SweepArgs args_of(const State* S)
 {
     SweepArgs a;
     const int mode = S->sweep_mode, ph = S->ls_phase;
-    a.alpha = (mode == SM_LSE && (ph == LS_TRIAL || ph == LS_FORCE)) ? S->alpha : 0.0;
+    const double alpha = S->alpha;  // read unconditionally: no branch between the state reads
+    a.alpha = ((mode == SM_LSE) & ((ph == LS_TRIAL) | (ph == LS_FORCE))) ? alpha : 0.0;
     a.gamma = S->gamma;
     a.gamma_prev = S->gamma_prev;
     a.alpha_acc = S->alpha_acc;
@@ -1399,17 +1400,26 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
 // kVecWG / L entries, which the workgroups take in a grid-stride loop.
 __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int nblk, FinShared& sh)
 {
-    const State* Sp = state_slot(w, parity);
-    const int tid = threadIdx.x;
-    const int n = w.n;
-    const int L = fin_lanes(n);
-    const int lgL = __ffs(L) - 1;
-    const int l = tid & (L - 1);
+    // Every control read (the Work fields and the state) is issued before the first branch,
+    // through a pointer held in a vector register (as scalar data these reads overflow the
+    // SGPRs and are issued in dependent groups), so the latency of the first access after
+    // the kernel boundary is paid once.
+    uint64_t cb = reinterpret_cast<uint64_t>(&ctl_of(w));
+    asm volatile("" : "+v"(cb));
+    const Control* C = reinterpret_cast<const Control*>(cb);
+    const Work wl = C->w;
+    const State* Sp = C->st + parity;
+    const int done = Sp->done, mode = Sp->sweep_mode, exp64 = Sp->exp64;
     const SweepArgs a = args_of(Sp);
-    const int mode = Sp->sweep_mode;
-    const bool active = !Sp->done && mode != SM_NONE;
-    const bool e64 = Sp->exp64 != 0;
-    const bool fast = active && mode == SM_LSE && w.nrt <= 256 && w.nrt <= 8 * L && w.nct <= 8 * L;
+    asm volatile("" ::: "memory");
+    const int tid = threadIdx.x;
+    const int n = wl.n;
+    const int L = wl.fin_L;
+    const int lgL = wl.fin_lgL;
+    const int l = tid & (L - 1);
+    const bool active = (done == 0) & (mode != SM_NONE);
+    const bool e64 = exp64 != 0;
+    const bool fast = active & (mode == SM_LSE) & (wl.nrt <= 256) & (wl.nrt <= 8 * L) & (wl.nct <= 8 * L);
     double v[kNDot];
 #pragma unroll
     for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
@@ -1417,25 +1427,25 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     double M = 0.0;
     if (!fast && active && (mode == SM_LSE || mode == SM_R1)) {
         double mx = -INFINITY;
-        for (int I = tid & 63; I < w.nrt; I += 64) mx = fmax(mx, w.tshift[I]);
+        for (int I = tid & 63; I < wl.nrt; I += 64) mx = fmax(mx, wl.tshift[I]);
         M = wave_max(mx);
     }
-    const int nvb = fin_vblocks(n);
+    const int nvb = wl.fin_nvb;
     for (int vb = blk; vb < nvb; vb += nblk) {
         const int k = (vb * kVecWG + tid) >> lgL;
         const bool valid = k < 2 * n;
         if (fast) {
-            fin_lse_entry(w, a, k, valid, l, L, e64, v);
+            fin_lse_entry(wl, a, k, valid, l, L, e64, v);
             continue;
         }
         const int kc = valid ? k : 0;
-        const EntryIn in = entry_load(w, a, kc);
+        const EntryIn in = entry_load(wl, a, kc);
         Comb cb{};
-        if (active) cb = combine(w, mode, k, valid, l, L, M);
+        if (active) cb = combine(wl, mode, k, valid, l, L, M);
         if (!valid || l != 0) continue;
         const Entry e = entry_from(in, a, n);
-        const double g_cur = store_update(w, a, e, in.g, k);
-        if (active) finalize_entry(w, a, e, g_cur, k, mode, e64, cb, M, v);
+        const double g_cur = store_update(wl, a, e, in.g, k);
+        if (active) finalize_entry(wl, a, e, g_cur, k, mode, e64, cb, M, v);
     }
     if (active) block_dots(v, bdots_of(w) + (size_t)blk * kNDot, tid, sh.red);
 }
@@ -1455,19 +1465,36 @@ constexpr int kDecideWG = 64;
 
 __device__ __forceinline__ void decide_body(const Work& w, int parity)
 {
-    const State* Sp = state_slot(w, parity);
     const int lane = threadIdx.x;
-    State S = *Sp;
-    const DevParams P = params_of(w);
+    // Every read of this kernel is issued together: the state, the parameters, n and the first
+    // 4 x 64 workgroups' dots (the dots array has kFinMaxGrid entries, so these loads are in
+    // bounds for any n; entries past fin_grid(n) are masked). The control block is read through
+    // a pointer held in a vector register, so the state is loaded into VGPRs (as scalar data it
+    // would overflow the SGPRs and be reloaded piecemeal).
+    uint64_t cb = reinterpret_cast<uint64_t>(&ctl_of(w));
+    asm volatile("" : "+v"(cb));
+    const Control* C = reinterpret_cast<const Control*>(cb);
+    State S = C->st[parity];
+    const DevParams P = C->prm;
+    const int n = C->w.n;
+    double x[4][kNDot];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int d = 0; d < kNDot; ++d) x[q][d] = C->bdots[(lane + 64 * q) * kNDot + d];
+    const int nblk = fin_grid(n);
+    double v[kNDot];
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int d = 0; d < kNDot; ++d) v[d] += (lane + 64 * q < nblk) ? x[q][d] : 0.0;
     const bool active = !S.done && S.sweep_mode != SM_NONE;
     if (active) {
-        const int nblk = fin_grid(w.n);
-        double v[kNDot];
+        for (int b = lane + 256; b < nblk; b += 64)
 #pragma unroll
-        for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
-        for (int b = lane; b < nblk; b += 64)
-#pragma unroll
-            for (int d = 0; d < kNDot; ++d) v[d] += bdots_of(w)[(size_t)b * kNDot + d];
+            for (int d = 0; d < kNDot; ++d) v[d] += C->bdots[b * kNDot + d];
         double sum[kNDot];
 #pragma unroll
         for (int d = 0; d < kNDot; ++d) sum[d] = wave_sum(v[d]);
