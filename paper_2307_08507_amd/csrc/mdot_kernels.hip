@@ -1232,13 +1232,9 @@ __device__ __forceinline__ void sweep_tiles(const Work& w, const SweepArgs& a, c
 // Body of the sweep kernel for one tile. ROUND = false: LSE and max sweeps (the hot path);
 // ROUND = true: the two Round/certificate sweeps (twice per stage).
 template <int CC, bool ROUND>
-__device__ __forceinline__ void sweep_kernel_body(const Work& w, int parity, int blk, double* smem)
+__device__ __forceinline__ void sweep_kernel_body(const Work& w, const SweepArgs& a, int mode, bool e64, int blk,
+                                                  double* smem)
 {
-    const State* Sp = state_slot(w, parity);
-    const int mode = Sp->sweep_mode;
-    if (mode == SM_NONE || Sp->done) return;
-    const bool e64 = Sp->exp64 != 0;
-    const SweepArgs a = args_of(Sp);
     TileCtx t;
     t.tid = threadIdx.x;
     t.lane = t.tid & 63;
@@ -1257,9 +1253,19 @@ __device__ __forceinline__ void sweep_kernel_body(const Work& w, int parity, int
 template <int CC>
 __device__ __forceinline__ void sweep_any(const Work& w, int parity, int blk, double* smem)
 {
-    const int mode = state_slot(w, parity)->sweep_mode;
-    if (mode == SM_R1 || mode == SM_R2) sweep_kernel_body<CC, true>(w, parity, blk, smem);
-    else sweep_kernel_body<CC, false>(w, parity, blk, smem);
+    // The state and the Work fields that locate the tile's cost rows are read in one group:
+    // the compiler barrier keeps every one of these loads ahead of the first branch.
+    const State* Sp = state_slot(w, parity);
+    const int mode = Sp->sweep_mode, done = Sp->done, exp64 = Sp->exp64;
+    const SweepArgs a = args_of(Sp);
+    const int n = w.n, nct = w.nct;
+    const void* cost = w.cost;
+    asm volatile("" ::"s"(mode), "s"(done), "s"(exp64), "s"(n), "s"(nct), "s"(cost), "s"(a.alpha), "s"(a.gamma),
+                 "s"(a.va)
+                 : "memory");
+    if ((mode == SM_NONE) | (done != 0)) return;
+    if ((mode == SM_R1) | (mode == SM_R2)) sweep_kernel_body<CC, true>(w, a, mode, exp64 != 0, blk, smem);
+    else sweep_kernel_body<CC, false>(w, a, mode, exp64 != 0, blk, smem);
 }
 
 template <int CC>
