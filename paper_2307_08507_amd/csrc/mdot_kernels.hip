@@ -189,6 +189,16 @@ struct DenseCost {
         }
     }
     __device__ __forceinline__ void row(int r, int j0, double c[4]) const { decode(load(r, j0), c); }
+    // LSE exponent arguments (log2 units) of one row for this lane's 4 columns:
+    // x_k = -g2 C_ik + V_k + A, with g2 = gamma * scale * log2(e).
+    __device__ __forceinline__ void prepare(double, const double*) {}
+    __device__ __forceinline__ void args(const Raw& raw, double g2, const double V[4], double A, double x[4]) const
+    {
+        double c[4];
+        decode(raw, c);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = fma(-g2, c[k], V[k]) + A;
+    }
 };
 
 // Point clouds: raw C_ij = sum_k (x_ik - y_jk)^2 (KIND 1) or sum_k |x_ik - y_jk| (KIND 2),
@@ -234,6 +244,37 @@ struct PointCost {
         }
     }
     __device__ __forceinline__ void row(int r, int j0, double c[4]) const { decode(load(r, j0), c); }
+    // LSE exponent arguments, as DenseCost::args. For squared distances the expansion
+    // |x - y|^2 = |x|^2 + |y|^2 - 2 <x, y> moves |y_k|^2 into W_k = V_k - g2 |y_k|^2 and |x|^2 into
+    // the row term, leaving 3 FMAs per element (prepare() turns y into 2 g2 y). The large
+    // terms cancel in FP64 to an absolute error ~1e-16 g2 |x|^2, far below the FP32 exp error.
+    double W[4];
+    __device__ __forceinline__ void prepare(double g2, const double V[4])
+    {
+        if constexpr (KIND == 1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double yy = fma(y[k][0], y[k][0], fma(y[k][1], y[k][1], y[k][2] * y[k][2]));
+                W[k] = fma(-g2, yy, V[k]);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) y[k][e] *= 2.0 * g2;
+            }
+        }
+    }
+    __device__ __forceinline__ void args(const Raw& raw, double g2, const double V[4], double A, double x[4]) const
+    {
+        if constexpr (KIND == 1) {
+            const double x0 = raw.x, x1 = raw.y, x2 = raw.z;
+            const double Ar = fma(-g2, fma(x0, x0, fma(x1, x1, x2 * x2)), A);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = fma(x0, y[k][0], fma(x1, y[k][1], fma(x2, y[k][2], W[k] + Ar)));
+        } else {
+            double c[4];
+            decode(raw, c);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = fma(-g2, c[k], V[k]) + A;
+        }
+    }
 };
 
 // ------------------------------------------------------------------ tile bodies
@@ -511,6 +552,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
         V[k] = sColV[t.lane * 4 + k];
     }
     __syncthreads();
+    cost.prepare(g2, V);
 
     double col64[4] = {0, 0, 0, 0};
     if constexpr (!E64) {
@@ -541,14 +583,12 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
                 const int r = b + r0;
                 rp[r] = 0.f;
                 if (r < nrows) {
-                    double c[4];
-                    cost.decode(raw[r0], c);
-                    const double A = sA[rbase + r];
+                    double xa[4];
+                    cost.args(raw[r0], g2, V, sA[rbase + r], xa);
                     const float wt = (float)sWt[rbase + r];
                     float e[4];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        e[k] = ok[k] ? __builtin_amdgcn_exp2f((float)(fma(-g2, c[k], V[k]) + A)) : 0.f;
+                    for (int k = 0; k < 4; ++k) e[k] = ok[k] ? __builtin_amdgcn_exp2f((float)xa[k]) : 0.f;
                     rp[r] = (e[0] + e[1]) + (e[2] + e[3]);
 #pragma unroll
                     for (int k = 0; k < 4; ++k) col32[k] = fmaf(wt, e[k], col32[k]);
@@ -590,14 +630,13 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
             for (int r0 = 0; r0 < RB; ++r0) {
                 const int r = b + r0;
                 if (r < nrows) {
-                    double c[4];
-                    cost.decode(raw[r0], c);
-                    const double A = sA[rbase + r];
+                    double xa[4];
+                    cost.args(raw[r0], g2, V, sA[rbase + r], xa);
                     const double wt = sWt[rbase + r];
                     double rs = 0.0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const double e = ok[k] ? exp2(fma(-g2, c[k], V[k]) + A) : 0.0;
+                        const double e = ok[k] ? exp2(xa[k]) : 0.0;
                         rs += e;
                         col64[k] = fma(wt, e, col64[k]);
                     }
