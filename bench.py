@@ -178,7 +178,8 @@ def bench_grid(args) -> dict:
     # roofline of the dominant kernel: the fused LSE sweep at the first problem's solution
     p0 = probs[0]
     r0 = solve(p0)
-    ms = ctx.bench_sweep(costs[p0["cost"]]["desc"](), u, v, r0.gamma_final, precision=args.precision, iters=200)
+    sweep_prec = "f64" if args.precision == "f64" else "f32"  # MIXED finishes on the exact cost in F32
+    ms = ctx.bench_sweep(costs[p0["cost"]]["desc"](), u, v, r0.gamma_final, precision=sweep_prec, iters=200)
     if args.cost_storage == "points":
         bound, unit, peak = "alu", "Gexp/s", None
         achieved = n * n / (ms * 1e-3) / 1e9
@@ -189,7 +190,7 @@ def bench_grid(args) -> dict:
         achieved = per_launch["bytes_per_launch"] / (ms * 1e-3) / 1e9
     roof = {"bound": bound, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4) if peak else None,
-            "traffic": measured_traffic(n, args.cost_storage) if args.precision == "f32" else None,
+            "traffic": measured_traffic(n, args.cost_storage) if sweep_prec == "f32" else None,
             "kernel": "k_sweep (fused two-sided LSE sweep)", **per_launch}
     out = {
         "metric": f"time-to-gap {args.target:g} at n={n}",
@@ -218,6 +219,8 @@ def bench_grid(args) -> dict:
         "certified_gap_max": max(r.gap for r in results),
         "all_certified": all(r.status == 0 and r.gap <= args.target for r in results),
         "sweeps_mean": statistics.mean(r.sweeps for r in results),
+        "proxy_stages_mean": statistics.mean(r.proxy_stages for r in results),
+        "fp64_stage_switches": sum(r.prec_switches for r in results),
         "us_per_sweep_in_solve": round(1e6 * sum(step_times) / sum(r.sweeps for r in results), 2),
         "lse_sweep_us": round(ms * 1e3, 3),
         "roofline": roof,
@@ -325,7 +328,7 @@ def main() -> int:
     ap.add_argument("--target", type=float, default=1e-6)
     ap.add_argument("--grid", type=int, default=64, help="grid side k (n = k*k)")
     ap.add_argument("--problems", type=int, default=8, help="problems cycled through (at most 8)")
-    ap.add_argument("--precision", default="f32", choices=("f32", "f64"))
+    ap.add_argument("--precision", default="f32", choices=("f32", "f64", "mixed"))
     ap.add_argument("--cost-storage", default="f32", choices=("f32", "f16", "bf16", "f64", "points"))
     ap.add_argument("--workload", default="grid", choices=("grid", "serving"))
     ap.add_argument("--requests", type=int, default=512)

@@ -67,7 +67,13 @@ typedef enum { MDOT_DT_F64 = 0, MDOT_DT_F32 = 1, MDOT_DT_F16 = 2, MDOT_DT_BF16 =
  * FP64 everything else (dual objective, marginals, dot products, line search, gap
  * certificate); rows or columns whose shifted sums fall outside the FP32 range are
  * re-evaluated in F64. Round and certificate sweeps always accumulate in FP64. */
-typedef enum { MDOT_PREC_F64 = 0, MDOT_PREC_F32 = 1 } mdot_precision;
+/* MIXED (mdot_solve with a DENSE FP32 or FP64 cost): the library keeps an FP16 copy of the cost
+ * in its workspace and runs the early stages (F32 arithmetic) on that copy while
+ * gamma * scale * delta <= mixed_switch, delta = max_ij |C16_ij - C_ij| (raw units); the
+ * remaining stages run on the exact cost. Any potentials start the next stage (Prop. 1.2),
+ * so the stages on the copy only provide warm starts: every Round / certificate sweep reads
+ * the exact cost, and the certified gap refers to it. */
+typedef enum { MDOT_PREC_F64 = 0, MDOT_PREC_F32 = 1, MDOT_PREC_MIXED = 2 } mdot_precision;
 
 typedef struct {
     int32_t n;            /* problem size, >= 1 */
@@ -92,6 +98,7 @@ typedef struct {
     int64_t max_sweeps;       /* LSE sweeps per solve, 0 = unlimited */
     mdot_precision precision; /* default MDOT_PREC_F32 */
     int32_t warm_start;       /* 1: Taylor warm start eq. (approx-znext); 0: reuse z^t */
+    double mixed_switch;      /* MIXED: largest gamma * scale * delta run on the FP16 copy (default 0.05) */
 } mdot_params;
 
 typedef struct {
@@ -108,6 +115,7 @@ typedef struct {
     int64_t fp64_retries; /* F32 sweeps re-run in F64 because of range */
     int64_t cert_sweeps;  /* Round/certificate sweeps */
     int64_t prec_switches; /* F32 stages continued with FP64 exp after the gradient norm stalled */
+    int64_t proxy_stages;  /* MIXED: stages run on the FP16 copy of the cost */
 } mdot_result;
 
 typedef struct mdot_ctx mdot_ctx;

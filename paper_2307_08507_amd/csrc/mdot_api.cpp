@@ -28,6 +28,7 @@ constexpr int kChunk = 32;       // solver steps per graph launch (even: the sta
 constexpr int kBatchChunk = 8;   // engine steps per graph launch (admission granularity, even)
 constexpr int kMaxN = 65536;     // the finalize kernel keeps n / 64 tile shifts in LDS
 constexpr int kSweepGrid = 2048; // engine: workgroups of the grid-stride sweep kernels
+constexpr int kConvBlocks = 1024; // workgroups of the FP16 conversion (MIXED)
 constexpr int kFinGrid = 512;    // engine: workgroups of the grid-stride finalize kernel
 
 // Device buffers of one problem: workspace, device copy of Work + 2 state slots, parameters.
@@ -38,6 +39,8 @@ struct ProblemBufs {
     Work* d_work = nullptr;  // the Control block (Work, State[2], DevParams, dots)
     DevParams* d_prm = nullptr;  // inside the Control block
     Work host_work{};
+    void* proxy = nullptr;  // MIXED: FP16 copy of the cost
+    size_t proxy_bytes = 0;
 };
 
 struct Slot {
@@ -135,12 +138,13 @@ static void free_bufs(ProblemBufs& pb)
 {
     if (pb.ws) (void)hipFree(pb.ws);
     if (pb.d_work) (void)hipFree(pb.d_work);
+    if (pb.proxy) (void)hipFree(pb.proxy);
     pb = ProblemBufs{};
 }
 
 static int ensure_scratch(mdot_ctx* ctx, int n)
 {
-    const size_t scr = std::max<size_t>(64, 2 * (size_t)tiles_r(n) * tiles_c(n));
+    const size_t scr = std::max<size_t>(kConvBlocks, 2 * (size_t)tiles_r(n) * tiles_c(n));
     if (scr <= ctx->scratch_doubles) return MDOT_OK;
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
     if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
@@ -238,6 +242,7 @@ static void fill_defaults(mdot_params* p)
     p->max_sweeps = 0;
     p->precision = MDOT_PREC_F32;
     p->warm_start = 1;
+    p->mixed_switch = 0.05;
 }
 
 static int check_cost_desc(mdot_ctx* ctx, const mdot_cost_desc* cost)
@@ -263,7 +268,8 @@ static int check_params(mdot_ctx* ctx, const mdot_params& prm, double target_gap
     if (!(prm.p >= 1.0) || !(prm.q > 1.0) || !(prm.gamma_i > 0.0) ||
         !(prm.ls_c1 > 0.0 && prm.ls_c1 < prm.ls_c2 && prm.ls_c2 < 1.0) || prm.max_ls_trials < 1 ||
         prm.max_pncg_iters < 1 || prm.max_sweeps < 0 ||
-        (prm.precision != MDOT_PREC_F32 && prm.precision != MDOT_PREC_F64))
+        (prm.precision != MDOT_PREC_F32 && prm.precision != MDOT_PREC_F64 && prm.precision != MDOT_PREC_MIXED) ||
+        (prm.precision == MDOT_PREC_MIXED && !(prm.mixed_switch > 0.0 && std::isfinite(prm.mixed_switch))))
         return fail(ctx, MDOT_E_ARG, "invalid parameters");
     return MDOT_OK;
 }
@@ -353,8 +359,40 @@ static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
     P.exp64_default = prm.precision == MDOT_PREC_F64;
     P.warm_start = prm.warm_start;
     P.n = n;
+    if (prm.precision == MDOT_PREC_MIXED) {
+        // FP16 copy of the cost and its largest rounding error delta; stages with
+        // gamma * scale * delta <= mixed_switch run on the copy, and at least the last stage
+        // before gamma_f runs on the exact cost
+        const size_t count = (size_t)n * n;
+        if (pb.proxy_bytes < count * 2) {
+            if (pb.proxy) (void)hipFree(pb.proxy);
+            pb.proxy = nullptr;
+            pb.proxy_bytes = 0;
+            HIPCHK(ctx, hipMalloc(&pb.proxy, count * 2));
+            pb.proxy_bytes = count * 2;
+        }
+        if (launch_to_f16(cost->data, cost->dtype, pb.proxy, count, ctx->d_scratch, kConvBlocks, ctx->stream))
+            return fail(ctx, MDOT_E_DEVICE, "conversion launch failed");
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, kConvBlocks * sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        double delta = 0.0;
+        for (int b = 0; b < kConvBlocks; ++b) delta = std::max(delta, ctx->h_scratch[b]);
+        const double scale = pb.host_work.scale;
+        double mg = delta > 0.0 ? prm.mixed_switch / (scale * delta) : P.gamma_f;
+        mg = std::min(mg, P.gamma_f / prm.q);
+        P.mix_gamma = (mg >= std::min(P.gamma_i, P.gamma_f)) ? mg : 0.0;
+    }
     HIPCHK(ctx, hipMemcpyAsync(pb.d_prm, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
     if (launch_init(pb.d_work, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "init launch failed");
+    if (P.mix_gamma > 0.0) {  // the first stages read the FP16 copy
+        mdot_cost_desc proxy = *cost;
+        proxy.dtype = MDOT_DT_F16;
+        proxy.data = pb.proxy;
+        const double scale = pb.host_work.scale;
+        rc = bind_work(ctx, pb, n, &proxy, scale, r, c);
+        if (rc) return rc;
+    }
     // the pinned parameter block is reused by the next intake: let this copy land first
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return MDOT_OK;
@@ -380,6 +418,7 @@ static void fill_result(const State& S, double seconds, mdot_result* res)
     res->fp64_retries = S.fallbacks;
     res->cert_sweeps = S.cert_sweeps;
     res->prec_switches = S.prec_switches;
+    res->proxy_stages = S.proxy_stages;
 }
 
 static int ensure_graph(mdot_ctx* ctx, int n)
@@ -601,13 +640,30 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
     if (ctx->budget && problem_footprint(n) > ctx->budget)
         return fail(ctx, MDOT_E_NOMEM, "workspace for n=%d needs %zu bytes > budget %zu", n, problem_footprint(n),
                     ctx->budget);
+    if (prm.precision == MDOT_PREC_MIXED &&
+        (cost->kind != MDOT_COST_DENSE || (cost->dtype != MDOT_DT_F32 && cost->dtype != MDOT_DT_F64)))
+        return fail(ctx, MDOT_E_ARG, "MIXED needs a dense FP32 or FP64 cost");
     rc = setup_problem(ctx, ctx->main, cost, r, c, target_gap, prm);
     if (rc) return rc;
     HIPCHK(ctx, hipEventRecord(ctx->t0, ctx->stream));
     // hard cap on steps: every LSE sweep is one step, each stage adds at most a few more
     const int64_t max_steps = prm.max_sweeps > 0 ? 4 * prm.max_sweeps + 4096 : (int64_t)1 << 22;
-    rc = run_steps(ctx, n, (int)std::min<int64_t>(max_steps / kChunk + 1, 1 << 30));
+    const int max_chunks = (int)std::min<int64_t>(max_steps / kChunk + 1, 1 << 30);
+    rc = run_steps(ctx, n, max_chunks);
     if (rc) return rc;
+    if (ctx->main.host_work.dtype != cost->dtype) {  // MIXED: paused at the switch to the exact cost
+        rc = read_state(ctx, ctx->main);
+        if (rc) return rc;
+        if (ctx->h_state->done == 2) {
+            rc = bind_work(ctx, ctx->main, n, cost, ctx->main.host_work.scale, r, c);
+            if (rc) return rc;
+            static const int32_t kResume = 0;
+            HIPCHK(ctx, hipMemcpyAsync(&ctx->main.host_work.st[0].done, &kResume, sizeof kResume,
+                                       hipMemcpyHostToDevice, ctx->stream));
+            rc = run_steps(ctx, n, max_chunks);
+            if (rc) return rc;
+        }
+    }
     if (launch_finish(ctx->main.d_work, u_out, v_out, ctx->stream))
         return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
     HIPCHK(ctx, hipEventRecord(ctx->t1, ctx->stream));
@@ -778,6 +834,7 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
     else fill_defaults(&prm);
     rc = check_params(ctx, prm, target_gap);
     if (rc) return rc;
+    if (prm.precision == MDOT_PREC_MIXED) return fail(ctx, MDOT_E_ARG, "MIXED is available through mdot_solve only");
     const int cc = cost_code_of(cost->kind, cost->dtype);
     int active = 0;
     for (const Slot& sl : ctx->slots) active += sl.used;

@@ -70,6 +70,7 @@ struct DevParams {
     double p, q, gamma_i, gamma_f, target, c1, c2, hmin;
     double tol_floor;     // lower limit of the PNCG tolerance eps_d / 2
     double f32_min_tol;   // F32 sweeps while eps_d / 2 >= this, FP64 exp below it (initial floor)
+    double mix_gamma;     // MIXED: stages with gamma <= this run on the FP16 copy (0: none)
     int64_t max_sweeps;
     int32_t max_ls_trials, max_pncg_iters;
     int32_t adaptive, exp64_default, warm_start, n;
@@ -82,6 +83,7 @@ struct State {
     int32_t exp64, ls_phase, stage, reset;
     int32_t save_best, inner_warn, ls_trials_cur, standalone;  // standalone: 0 solve, 1 LSE only, 2 round+certify
     int32_t budget_stop, exp64_stage;
+    int32_t on_proxy, pad_;  // on_proxy: the stage runs on the FP16 copy of the cost (MIXED)
     double gamma, gamma_prev, eps_d, w, ws_ratio, tol;
     double alpha, alpha_acc, alpha_prev, beta;
     double dphi0, alo, dlo, ahi, dhi, gnorm;
@@ -91,7 +93,7 @@ struct State {
     double f32_floor;   // FP64 exp for stages with tolerance below this (raised by the stall guard)
     double stall_best;  // smallest ||grad||_1 of the stage when it last halved, at iteration stall_k
     int64_t k, sweeps, pncg_iters, ls_trials, cg_resets, ls_failures, fallbacks, cert_sweeps;
-    int64_t stall_k, prec_switches;
+    int64_t stall_k, prec_switches, proxy_stages;
 };
 
 // Device buffers of one problem (all FP64 unless noted). 2n-vectors hold rows then columns.
@@ -159,6 +161,8 @@ int launch_init(const Work* wd, void* stream);                               // 
 int launch_intake(const Work* wd, double* out8, void* stream);
 int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream);
 int launch_finish(const Work* wd, double* u_out, double* v_out, void* stream);
+// FP16 copy of a dense FP32 (src_dtype MDOT_DT_F32) or FP64 cost; part[b] = max |C16 - C| of block b.
+int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, double* part, int nblocks, void* stream);
 // Batched step over a BatchDesc in device memory (cost type cost_code for every item), with
 // fixed grids (grid-stride over the descriptor), and a gather of the items' done flags.
 int cost_code_of(int cost_kind, int dtype);

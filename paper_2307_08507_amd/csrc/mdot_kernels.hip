@@ -1042,11 +1042,26 @@ __device__ __forceinline__ void next_stage(State& S, const DevParams& P)
     S.vec_action |= VA_STAGE_INIT;
     S.sweep_mode = SM_LSE;
     S.ls_phase = LS_INIT;
+    // MIXED: the first stage past the switch point runs on the exact cost; the host swaps the
+    // cost and resumes (done = 2 pauses the solve with this stage's start already stored)
+    if (S.on_proxy && S.gamma > P.mix_gamma) {
+        S.on_proxy = 0;
+        S.done = 2;
+    }
 }
 
 __device__ __forceinline__ void end_stage(State& S, const DevParams& P, bool converged)
 {
     if (!converged) S.inner_warn = 1;
+    if (S.on_proxy) {  // MIXED: stages on the FP16 copy only provide warm starts
+        S.proxy_stages++;
+        if (S.gamma < P.gamma_f && !S.budget_stop) {
+            next_stage(S, P);
+            return;
+        }
+        S.on_proxy = 0;  // certify on the exact cost: pause for the swap first
+        S.done = 2;
+    }
     if (P.adaptive || S.gamma >= P.gamma_f || S.budget_stop) {
         S.vec_action |= VA_ROUND_PREP;
         S.sweep_mode = SM_R1;
@@ -1618,6 +1633,7 @@ __global__ void k_init(const Work* __restrict__ wp)
     S.w = fmin(S.eps_d / 4.0, 0.5);
     S.tol = fmax(S.eps_d / 2.0, P.tol_floor);
     S.f32_floor = P.f32_min_tol;
+    S.on_proxy = P.mix_gamma > 0.0 && S.gamma <= P.mix_gamma;
     S.exp64_stage = P.exp64_default || S.tol < S.f32_floor;
     S.exp64 = S.exp64_stage;
     S.alpha_prev = 1.0;
@@ -1829,6 +1845,36 @@ int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream
 #define L_(CC) hipLaunchKernelGGL(k_cost_range<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, part)
     MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// FP16 copy of a dense cost (round to nearest) and the largest rounding error per block.
+template <class T>
+__global__ void __launch_bounds__(256) k_to_f16(const T* __restrict__ src, __half* __restrict__ dst, size_t count,
+                                                double* part)
+{
+    __shared__ double sm[4];
+    double mx = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
+        const double c = (double)src[i];
+        const _Float16 h = static_cast<_Float16>(c);  // the error is measured, so the rounding path does not matter
+        dst[i] = __half_raw{h};
+        mx = fmax(mx, fabs((double)h - c));
+    }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+}
+
+int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, double* part, int nblocks, void* stream)
+{
+    if (src_dtype == MDOT_DT_F32)
+        hipLaunchKernelGGL(k_to_f16<float>, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, (const float*)src,
+                           (__half*)dst, count, part);
+    else
+        hipLaunchKernelGGL(k_to_f16<double>, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, (const double*)src,
+                           (__half*)dst, count, part);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -21,7 +21,7 @@ ERRORS = {-1: "MDOT_E_ARG", -2: "MDOT_E_MARGINAL", -3: "MDOT_E_COST", -4: "MDOT_
 
 COST_DENSE, COST_POINTS_SQEUCLID, COST_POINTS_L1 = 0, 1, 2
 DT_F64, DT_F32, DT_F16, DT_BF16 = 0, 1, 2, 3
-PREC_F64, PREC_F32 = 0, 1
+PREC_F64, PREC_F32, PREC_MIXED = 0, 1, 2
 
 
 class CostDesc(ct.Structure):
@@ -33,7 +33,7 @@ class Params(ct.Structure):
     _fields_ = [("p", ct.c_double), ("q", ct.c_double), ("gamma_i", ct.c_double), ("gamma_f", ct.c_double),
                 ("gamma_cap", ct.c_double), ("ls_c1", ct.c_double), ("ls_c2", ct.c_double),
                 ("max_ls_trials", ct.c_int32), ("max_pncg_iters", ct.c_int32), ("max_sweeps", ct.c_int64),
-                ("precision", ct.c_int), ("warm_start", ct.c_int32)]
+                ("precision", ct.c_int), ("warm_start", ct.c_int32), ("mixed_switch", ct.c_double)]
 
 
 class Result(ct.Structure):
@@ -42,7 +42,7 @@ class Result(ct.Structure):
                 ("seconds", ct.c_double), ("stages", ct.c_int32), ("status", ct.c_int32),
                 ("pncg_iters", ct.c_int64), ("ls_trials", ct.c_int64), ("sweeps", ct.c_int64),
                 ("cg_resets", ct.c_int64), ("ls_failures", ct.c_int64), ("fp64_retries", ct.c_int64),
-                ("cert_sweeps", ct.c_int64), ("prec_switches", ct.c_int64)]
+                ("cert_sweeps", ct.c_int64), ("prec_switches", ct.c_int64), ("proxy_stages", ct.c_int64)]
 
 
 class MdotError(RuntimeError):
@@ -94,7 +94,7 @@ def default_params(**kw) -> Params:
     lib().mdot_default_params(ct.byref(p))
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
-            v = {"f32": PREC_F32, "f64": PREC_F64}[v]
+            v = {"f32": PREC_F32, "f64": PREC_F64, "mixed": PREC_MIXED}[v]
         setattr(p, k, v)
     return p
 
@@ -150,6 +150,7 @@ class SolveResult:
     fp64_retries: int
     cert_sweeps: int
     prec_switches: int
+    proxy_stages: int
 
 
 class Context:

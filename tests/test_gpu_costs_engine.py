@@ -237,3 +237,42 @@ def test_engine_admission_budget():
         assert eng.poll(t2, wait=True).primal_cost == res.primal_cost
     finally:
         eng.close()
+
+
+# ---------------------------------------------------------------- MIXED precision
+@pytest.mark.parametrize("cost", ["sqeuclid", "l1"])
+def test_mixed_precision_certifies_on_exact_cost(ctx, cost):
+    from tests.exact_ot import exact_lp
+
+    C, r, c = W.grid_problem(16, "blobs", cost, 11)
+    Cd = dev(C, torch.float32)
+    C64 = Cd.double().cpu().numpy()
+    u = torch.empty(r.size, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+    res = ctx.solve(M.dense_cost(Cd), dev(r), dev(c), 1e-5, M.default_params(precision="mixed"), u, v)
+    ref = ctx.solve(M.dense_cost(Cd), dev(r), dev(c), 1e-5, M.default_params(precision="f32"), u, v)
+    ot = exact_lp(C64, r, c)
+    print(f"mixed {cost}: proxy stages={res.proxy_stages} stages={res.stages} sweeps={res.sweeps} gap={res.gap:.3e} "
+          f"UB-OT={res.primal_cost - ot:.3e}; f32 sweeps={ref.sweeps}")
+    assert res.proxy_stages > 0
+    assert res.status == 0 and res.gap <= 1e-5
+    # the bound and the rounded plan refer to the exact (FP32-stored) cost
+    assert res.dual_bound <= ot + 1e-12 and res.primal_cost >= ot - 1e-12
+    assert res.marg_err_l1 <= 1e-12
+
+
+def test_mixed_precision_rejected_where_unsupported(ctx):
+    n, d = 64, 3
+    XY, _, scale = _points(n, d, 3, "sqeuclid")
+    r = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+    with pytest.raises(M.MdotError) as e:
+        ctx.solve(M.point_cost(XY, n, d, "sqeuclid", scale=scale), r, r, 1e-4, M.default_params(precision="mixed"))
+    assert e.value.code == -1
+    eng = M.Context(0)
+    try:
+        C = dev(np.random.default_rng(0).random((n, n)), torch.float32)
+        with pytest.raises(M.MdotError) as e:
+            eng.submit(M.dense_cost(C), r, r, 1e-4, M.default_params(precision="mixed"))
+        assert e.value.code == -1
+    finally:
+        eng.close()
