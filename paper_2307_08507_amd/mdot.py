@@ -118,7 +118,9 @@ def _dtype_code(t) -> int:
 def dense_cost(C, scale: float = 1.0) -> CostDesc:
     """Descriptor of a dense n x n cost tensor (device, contiguous, f64/f32/f16/bf16)."""
     assert C.is_cuda and C.dim() == 2 and C.shape[0] == C.shape[1] and C.is_contiguous()
-    return CostDesc(n=C.shape[0], d=0, kind=COST_DENSE, dtype=_dtype_code(C), data=C.data_ptr(), scale=scale)
+    desc = CostDesc(n=C.shape[0], d=0, kind=COST_DENSE, dtype=_dtype_code(C), data=C.data_ptr(), scale=scale)
+    desc._tensor = C  # the descriptor holds a raw pointer: keep the tensor alive with it
+    return desc
 
 
 def point_cost(XY, n: int, d: int, kind: str = "sqeuclid", scale: float = 0.0) -> CostDesc:
@@ -128,7 +130,9 @@ def point_cost(XY, n: int, d: int, kind: str = "sqeuclid", scale: float = 0.0) -
 
     assert XY.is_cuda and XY.dtype == torch.float32 and XY.is_contiguous() and XY.numel() == 2 * n * d
     k = COST_POINTS_SQEUCLID if kind == "sqeuclid" else COST_POINTS_L1
-    return CostDesc(n=n, d=d, kind=k, dtype=DT_F32, data=XY.data_ptr(), scale=scale)
+    desc = CostDesc(n=n, d=d, kind=k, dtype=DT_F32, data=XY.data_ptr(), scale=scale)
+    desc._tensor = XY  # the descriptor holds a raw pointer: keep the tensor alive with it
+    return desc
 
 
 @dataclass

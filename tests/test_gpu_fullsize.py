@@ -1,0 +1,141 @@
+"""Parity at the benchmark's size and in the degenerate cases.
+
+* Full size: the n = 4096 grid workload in the launch configuration bench.py times (FP32
+  stored cost, one workgroup per 64 x 256 tile). The oracle cannot run a whole solve there in
+  seconds, so the sweep is checked on sampled rows and columns (each log-sum recomputed in
+  FP64 by the oracle's definition), and the solve's output is checked by the oracle's own
+  Round + certificate on the returned potentials. A ragged size (n = 4097: no 16-byte rows,
+  ragged last tiles) covers the other load path at scale.
+* Degenerate cases with closed forms: n = 1, identical marginals on a cost with zero
+  diagonal (OT = 0), and a separable cost C_ij = a_i + b_j (every plan costs <a, r> + <b, c>).
+
+Inputs are seeded and synthetic (paper_2307_08507_amd.workloads); expected values come from
+the oracle or from the closed forms, never from the HIP path.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2307_08507_amd import mdot as M  # noqa: E402
+from paper_2307_08507_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _sampled_lse(C, u, v, gamma, rows, cols):
+    from scipy.special import logsumexp
+
+    lr = np.array([logsumexp(u[i] + v - gamma * C[i]) for i in rows])
+    lc = np.array([logsumexp(u + v[j] - gamma * C[:, j]) for j in cols])
+    return lr, lc
+
+
+@pytest.mark.parametrize("k,ragged", [(64, False), (64, True)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_lse2_fullsize_sampled(ctx, k, ragged, prec):
+    from scipy.special import logsumexp
+
+    C, r, c = W.grid_problem(k, "smooth", "sqeuclid", 1000)
+    if ragged:  # n = 4097: one extra point at the far corner
+        n0 = C.shape[0]
+        C = np.pad(C, ((0, 1), (0, 1)), constant_values=1.0)
+        C[n0, n0] = 0.0
+        r = np.append(r, 1e-6)
+        c = np.append(c, 1e-6)
+    n = C.shape[0]
+    print(f"full-size lse2 n={n} prec={prec}", flush=True)
+    Cd = dev(C, torch.float32)
+    C64 = Cd.double().cpu().numpy()
+    gamma = 300.0
+    rng = np.random.default_rng(n)
+    u = np.log(r) + rng.standard_normal(n) * 0.1
+    v = -logsumexp(u[:, None] - gamma * C64, axis=0) + np.log(c)
+    lr = torch.empty(n, dtype=torch.float64, device="cuda")
+    lc = torch.empty_like(lr)
+    assert ctx.lse2(M.dense_cost(Cd), dev(u), dev(v), gamma, lr, lc, precision=prec) == 0
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([rng.choice(n, 60, replace=False), [0, n - 1]]))
+    cols = np.unique(np.concatenate([rng.choice(n, 60, replace=False), [0, n - 1]]))
+    lr_o, lc_o = _sampled_lse(C64, u, v, gamma, rows, cols)
+    tol = 1e-12 * gamma if prec == "f64" else 2e-6
+    np.testing.assert_allclose(lr.cpu().numpy()[rows], lr_o, rtol=0, atol=tol)
+    np.testing.assert_allclose(lc.cpu().numpy()[cols], lc_o, rtol=0, atol=tol)
+
+
+def test_solve_fullsize_recertified_by_oracle(ctx):
+    # the benchmark's first problem (uniform marginals, squared-Euclidean grid cost, n = 4096)
+    k = 64
+    r = W.grid_problem_marginals(k, "uniform", 1000)
+    c = W.grid_problem_marginals(k, "uniform", 1001)
+    C = W.grid_cost(k, "sqeuclid")
+    Cd = dev(C, torch.float32)
+    C64 = Cd.double().cpu().numpy()
+    u = torch.empty(k * k, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+    res = ctx.solve(M.dense_cost(Cd), dev(r), dev(c), 1e-6, M.default_params(precision="f32"), u, v)
+    print(f"n=4096 solve: gap={res.gap:.3e} UB={res.primal_cost!r} LB={res.dual_bound!r} "
+          f"gamma=2^{np.log2(res.gamma_final):.2f} sweeps={res.sweeps}", flush=True)
+    assert res.status == 0 and 0 <= res.gap <= 1e-6
+    # the oracle rounds the plan of the returned potentials at gamma_final (Alg. 3) and bounds
+    # OT with their c-transforms: its UB is the GPU's UB up to FP32-exp rounding, and the
+    # GPU's certified bound cannot exceed a feasible plan's cost
+    ub_o, lb_o, me_o, _ = O.round_certify(C64, u.cpu().numpy(), v.cpu().numpy(), res.gamma_final, r, c)
+    print(f"oracle: UB={ub_o!r} LB(u/gamma)={lb_o!r} marg_err={me_o:.2e}")
+    assert res.primal_cost == pytest.approx(ub_o, rel=1e-5)
+    assert res.dual_bound <= ub_o + 1e-12
+    assert lb_o <= res.primal_cost + 1e-12
+    assert me_o <= 1e-12
+
+
+def test_single_point(ctx):
+    C = dev(np.array([[0.375]]), torch.float64)
+    one = dev(np.array([1.0]))
+    res = ctx.solve(M.dense_cost(C), one, one, 1e-6)
+    assert res.status == 0
+    assert res.primal_cost == pytest.approx(0.375, abs=1e-12)
+    assert res.dual_bound == pytest.approx(0.375, abs=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_identical_marginals_zero_diagonal(ctx, prec):
+    # r = c and C_ii = 0 <= C_ij: the identity coupling is optimal, OT = 0
+    C, r, _ = W.grid_problem(16, "blobs", "l1", 21)
+    Cd, rd = dev(C, torch.float32), dev(r)  # keep the device buffers alive during the call
+    res = ctx.solve(M.dense_cost(Cd), rd, rd, 1e-6, M.default_params(precision=prec))
+    assert res.status == 0 and res.gap <= 1e-6
+    assert res.dual_bound <= 1e-12
+    assert 0.0 <= res.primal_cost <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_separable_cost(ctx, prec):
+    # C_ij = a_i + b_j: every coupling costs <a, r> + <b, c>
+    n = 300
+    rng = np.random.default_rng(5)
+    a, b = rng.random(n) * 0.5, rng.random(n) * 0.5
+    C = a[:, None] + b[None, :]
+    r = W.dirichlet_marginal(n, 7)
+    c = W.dirichlet_marginal(n, 8)
+    exact = float(a @ r + b @ c)
+    Cd, rd, cd = dev(C, torch.float64), dev(r), dev(c)  # keep the device buffers alive during the call
+    res = ctx.solve(M.dense_cost(Cd), rd, cd, 1e-8, M.default_params(precision=prec))
+    assert res.status == 0
+    assert res.primal_cost == pytest.approx(exact, abs=1e-10)
+    assert res.dual_bound == pytest.approx(exact, abs=1e-8)
