@@ -191,6 +191,8 @@ struct DenseCost {
     __device__ __forceinline__ void row(int r, int j0, double c[4]) const { decode(load(r, j0), c); }
     // LSE exponent arguments (log2 units) of one row for this lane's 4 columns:
     // x_k = -g2 C_ik + V_k + A, with g2 = gamma * scale * log2(e).
+    __device__ __forceinline__ void bind_rows(void*) {}
+    __device__ __forceinline__ void row_setup(int, int, double, double&) {}
     __device__ __forceinline__ void prepare(double, const double*) {}
     __device__ __forceinline__ void args(const Raw& raw, double g2, const double V[4], double A, double x[4]) const
     {
@@ -202,14 +204,16 @@ struct DenseCost {
 };
 
 // Point clouds: raw C_ij = sum_k (x_ik - y_jk)^2 (KIND 1) or sum_k |x_ik - y_jk| (KIND 2),
-// evaluated in FP64 from FP32 coordinates (d <= 3). "Raw" is the row's coordinates.
+// evaluated in FP64 from FP32 coordinates (d <= 3). In the LSE tile the rows' coordinates are
+// the same for every lane: row_setup() puts them in LDS once and "Raw" is just the tile row.
 template <int KIND>
 struct PointCost {
-    using Raw = float4;
+    using Raw = int;
     const float* X;
     const float* Y;
     int n, d, i0;
     double y[4][3];
+    const float4* sX;
     __device__ __forceinline__ PointCost(const Work& w, int i0_)
         : X((const float*)w.cost), Y((const float*)w.cost + (size_t)w.n * w.d), n(w.n), d(w.d), i0(i0_) {}
     __device__ __forceinline__ void cols(int j0)
@@ -219,17 +223,17 @@ struct PointCost {
 #pragma unroll
             for (int e = 0; e < 3; ++e) y[k][e] = (j0 + k < n && e < d) ? (double)Y[(size_t)(j0 + k) * d + e] : 0.0;
     }
-    __device__ __forceinline__ Raw load(int r, int) const
+    __device__ __forceinline__ float4 xrow(int r) const
     {
         const int i = i0 + r;
-        Raw v;
+        float4 v;
         v.x = (i < n) ? X[(size_t)i * d] : 0.f;
         v.y = (i < n && d > 1) ? X[(size_t)i * d + 1] : 0.f;
         v.z = (i < n && d > 2) ? X[(size_t)i * d + 2] : 0.f;
         v.w = 0.f;
         return v;
     }
-    __device__ __forceinline__ void decode(const Raw& x, double c[4]) const
+    __device__ __forceinline__ void decode(const float4& x, double c[4]) const
     {
         const double xs[3] = {x.x, x.y, x.z};
 #pragma unroll
@@ -243,7 +247,20 @@ struct PointCost {
             c[k] = s;
         }
     }
-    __device__ __forceinline__ void row(int r, int j0, double c[4]) const { decode(load(r, j0), c); }
+    __device__ __forceinline__ void row(int r, int, double c[4]) const { decode(xrow(r), c); }
+    __device__ __forceinline__ Raw load(int r, int) const { return r; }
+    // LSE tile set-up: sX = kBR float4 rows of LDS; thread r < kBR stores row r's coordinates
+    // and, for squared distances, folds -g2 |x_r|^2 into the row term a.
+    __device__ __forceinline__ void bind_rows(void* lds) { sX = (const float4*)lds; }
+    __device__ __forceinline__ void row_setup(int r, int i, double g2, double& a)
+    {
+        const float4 v = xrow(r);
+        ((float4*)sX)[r] = v;
+        if (KIND == 1 && i < n) {
+            const double x0 = v.x, x1 = v.y, x2 = v.z;
+            a = fma(-g2, fma(x0, x0, fma(x1, x1, x2 * x2)), a);
+        }
+    }
     // LSE exponent arguments, as DenseCost::args. For squared distances the expansion
     // |x - y|^2 = |x|^2 + |y|^2 - 2 <x, y> moves |y_k|^2 into W_k = V_k - g2 |y_k|^2 and |x|^2 into
     // the row term, leaving 3 FMAs per element (prepare() turns y into 2 g2 y). The large
@@ -261,16 +278,16 @@ struct PointCost {
             }
         }
     }
-    __device__ __forceinline__ void args(const Raw& raw, double g2, const double V[4], double A, double x[4]) const
+    __device__ __forceinline__ void args(const Raw& r, double g2, const double V[4], double A, double x[4]) const
     {
+        const float4 xr = sX[r];  // one address for the whole wave: an LDS broadcast
         if constexpr (KIND == 1) {
-            const double x0 = raw.x, x1 = raw.y, x2 = raw.z;
-            const double Ar = fma(-g2, fma(x0, x0, fma(x1, x1, x2 * x2)), A);
+            const double x0 = xr.x, x1 = xr.y, x2 = xr.z;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) x[k] = fma(x0, y[k][0], fma(x1, y[k][1], fma(x2, y[k][2], W[k] + Ar)));
+            for (int k = 0; k < 4; ++k) x[k] = fma(x0, y[k][0], fma(x1, y[k][1], fma(x2, y[k][2], W[k] + A)));
         } else {
             double c[4];
-            decode(raw, c);
+            decode(xr, c);
 #pragma unroll
             for (int k = 0; k < 4; ++k) x[k] = fma(-g2, c[k], V[k]) + A;
         }
@@ -358,27 +375,41 @@ __device__ __forceinline__ double round_x(double ri, double lz)
     return (rp > 0.0) ? fmin(ri / rp, 1.0) : 1.0;
 }
 
-// 2^x in FP64 for the sweeps' arguments (finite, at most a few tens): x = k + f with
-// k = rint(x), |f| <= 1/2; 2^f = e^t, t = f ln 2, |t| <= 0.347, by its Taylor series to degree
-// 11 (truncation < 7e-15 relative, Horner rounding a few ulp); 2^k by ldexp, which also gives
-// 0 (through subnormals) for x below -1074. No range branches.
+// One Horner step a * x + c with the coefficient c in an SGPR pair: left to itself the
+// compiler holds every polynomial coefficient of exp2_f64 in a VGPR pair across the sweep loops.
+__device__ __forceinline__ double fma_sc(double a, double x, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(x), "s"(c));
+    return r;
+}
+
+// 2^x in FP64 for the sweeps' exponent arguments. x is clamped to [-1023, 1000], split as
+// x = k + f with k = round-to-nearest(x) by the 1.5 * 2^52 shift (its low word is k) and
+// |f| <= 1/2; 2^f = 1 + f q(f) with q of degree 9, a weighted least-squares fit driven to equal
+// ripple (relative error below 4e-16 in exact arithmetic, a few ulp after Horner rounding);
+// 2^k is written into the exponent field. At the clamp -1023 that field is 0 and the result is
+// exactly 0, so x = -inf gives 0; x below -1022.5 is flushed to 0, which every caller meets only
+// beside terms of order 1. No range branches: 19 VALU operations.
 __device__ __forceinline__ double exp2_f64(double x)
 {
-    const double k = rint(fmax(x, -2000.0));
-    const double t = (x - k) * LN2_D;
-    double p = 2.505210838544172e-08;     // 1/11!
-    p = fma(p, t, 2.755731922398589e-07); // 1/10!
-    p = fma(p, t, 2.7557319223985893e-06);  // 1/9!
-    p = fma(p, t, 2.48015873015873e-05);    // 1/8!
-    p = fma(p, t, 1.984126984126984e-04);   // 1/7!
-    p = fma(p, t, 1.388888888888889e-03);   // 1/6!
-    p = fma(p, t, 8.333333333333333e-03);   // 1/5!
-    p = fma(p, t, 4.1666666666666664e-02);  // 1/4!
-    p = fma(p, t, 1.6666666666666666e-01);  // 1/3!
-    p = fma(p, t, 0.5);
-    p = fma(p, t, 1.0);
-    p = fma(p, t, 1.0);
-    return ldexp(p, (int)k);
+    constexpr double kShift = 0x1.8p52;
+    x = fmin(fmax(x, -1023.0), 1000.0);
+    const double y = x + kShift;
+    const double f = x - (y - kShift);
+    const int k = (int)(uint32_t)__builtin_bit_cast(uint64_t, y);
+    double q = fma_sc(f, 0x1.e3a9131404cdep-28, 0x1.b671b6a900f80p-24);
+    q = fma_sc(q, f, 0x1.62c147a08947dp-20);
+    q = fma_sc(q, f, 0x1.ffcb58c5cff22p-17);
+    q = fma_sc(q, f, 0x1.4309126bff6b0p-13);
+    q = fma_sc(q, f, 0x1.5d87fe9b90bb4p-10);
+    q = fma_sc(q, f, 0x1.3b2ab6fbd6d27p-7);
+    q = fma_sc(q, f, 0x1.c6b08d703e16ap-5);
+    q = fma_sc(q, f, 0x1.ebfbdff82c431p-3);
+    q = fma_sc(q, f, 0x1.62e42fefa3a12p-1);
+    const double p = fma(q, f, 1.0);
+    const uint64_t scale = (uint64_t)((uint32_t)(k + 1023) << 20) << 32;
+    return p * __builtin_bit_cast(double, scale);
 }
 
 template <bool E64>
@@ -447,6 +478,24 @@ __device__ __forceinline__ double rows_reduce_f32(const float rp[kRPW], float* r
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) s += (double)src[k];
+    s += dpp_d<0xb1>(0.0, s);  // quad_perm [1,0,3,2]
+    s += dpp_d<0x4e>(0.0, s);  // quad_perm [2,3,0,1]
+    return s;
+}
+
+// The same for FP64 row partials, which the caller has stored as rb[r * 64 + lane] (the wave's
+// kRPW x 64 values fill its region); lane (rr, q) walks its 16 entries in the order k ^ rr, so
+// that the lanes of each read hit distinct banks.
+__device__ __forceinline__ double rows_reduce_f64(const double* rb, int lane)
+{
+    static_assert(kRPW * 64 <= kWaveRegion, "FP64 row transpose fits the wave region");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const int rr = lane >> 2, q = lane & 3;
+    const double* src = rb + rr * 64 + q * 16;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += src[k ^ rr];
     s += dpp_d<0xb1>(0.0, s);  // quad_perm [1,0,3,2]
     s += dpp_d<0x4e>(0.0, s);  // quad_perm [2,3,0,1]
     return s;
@@ -521,13 +570,20 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     const int rbase = t.wave * kRPW;
     const int nrows = min(kRPW, n - (t.i0 + rbase));  // rows of this wave (may be <= 0)
     // loads of a batch of rows are issued before any compute on them (all 16 rows of the wave
-    // for <= 8 B per lane-row, 8 rows for wider ones); the first batch does not depend on the
+    // for <= 8 B per lane-row, 8 rows for 16 B, 4 for 32 B); the first batch does not depend on the
     // solver state and is issued before the per-row and per-column set-up, which it overlaps
-    constexpr int RB = sizeof(typename Cost::Raw) <= 8 ? kRPW : kRPW / 2;
+    constexpr int RB = sizeof(typename Cost::Raw) <= 8 ? kRPW : (sizeof(typename Cost::Raw) <= 16 ? kRPW / 2 : kRPW / 4);
+    // FP32 exponentials with rows of at most 16 B: rows past the end of the matrix are loaded
+    // too (the buffer range check returns 0 for them) and computed without a branch. Their row
+    // term is -inf, so every exponential of theirs is exactly 0, and one straight-line loop
+    // over the batch lets the compiler overlap one row's exponentials with the next row's
+    // arguments. Elsewhere (FP64 exponentials, 32 B rows) that overlap costs more registers
+    // than there are, and each row stays behind its own branch.
+    constexpr bool kRowGuard = E64 || sizeof(typename Cost::Raw) > 16;
     typename Cost::Raw raw[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
-        if (r < nrows) raw[r] = cost.load(rbase + r, j0);
+        if (!kRowGuard || r < nrows) raw[r] = cost.load(rbase + r, j0);
     // FP32 rows with n % 4 == 0 and more tiles than stay resident at once: the second batch
     // goes straight to the wave's LDS region, so all 16 rows of the wave are in flight from the
     // start without holding registers. With a single round of workgroups (n <= ~5800) the
@@ -544,14 +600,16 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     }
     // per-row values: shift s_i (predicted log row sum) and A_i = (u_i - lz_i) log2 e;
     // per-column V_j = (v_j + alpha p_j) log2 e, one column per thread, through LDS
+    cost.bind_rows(sm + 3 * kBR);  // 2 kBR doubles, free in this tile
     if (t.tid < kBR) {
         const int i = t.i0 + t.tid;
-        double sh = -INFINITY, aa = 0.0;
+        double sh = -INFINITY, aa = -INFINITY;
         if (i < n) {
             const Entry e = entry_after(w, S, i);
             sh = fma(alpha, e.p, e.lz);
             aa = (e.z - e.lz) * LOG2E_D;
         }
+        cost.row_setup(t.tid, i, g2, aa);
         sS[t.tid] = sh;
         sA[t.tid] = aa;
     }
@@ -567,13 +625,10 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     __syncthreads();
     const double SI = wave_max(sS[t.lane]);  // S_I = max_i s_i over the kBR (= 64) rows
     if (t.tid < kBR) sWt[t.tid] = exp(sS[t.tid] - SI);
+    // padding columns (j >= n) get V = -inf: their arguments are -inf and their exponentials 0
     double V[4];
-    bool ok[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        ok[k] = j0 + k < n;
-        V[k] = sColV[t.lane * 4 + k];
-    }
+    for (int k = 0; k < 4; ++k) V[k] = (j0 + k < n) ? sColV[t.lane * 4 + k] : -INFINITY;
     __syncthreads();
     cost.prepare(g2, V);
 
@@ -590,28 +645,29 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
                         __builtin_amdgcn_wave_barrier();
 #pragma unroll
                         for (int r = 0; r < RB; ++r)
-                            if (b + r < nrows)
-                                raw[r] = reinterpret_cast<const typename Cost::Raw*>(myRegion + r * (kWaveRegion / RB))[t.lane];
+                            raw[r] = (b + r < nrows)
+                                ? reinterpret_cast<const typename Cost::Raw*>(myRegion + r * (kWaveRegion / RB))[t.lane]
+                                : typename Cost::Raw{};
                         __builtin_amdgcn_wave_barrier();
                     }
                 }
                 if (!staged) {
 #pragma unroll
                     for (int r = 0; r < RB; ++r)
-                        if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+                        if (!kRowGuard || b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
                 }
             }
 #pragma unroll
             for (int r0 = 0; r0 < RB; ++r0) {
                 const int r = b + r0;
                 rp[r] = 0.f;
-                if (r < nrows) {
+                if (!kRowGuard || r < nrows) {
                     double xa[4];
                     cost.args(raw[r0], g2, V, sA[rbase + r], xa);
                     const float wt = (float)sWt[rbase + r];
                     float e[4];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) e[k] = ok[k] ? __builtin_amdgcn_exp2f((float)xa[k]) : 0.f;
+                    for (int k = 0; k < 4; ++k) e[k] = __builtin_amdgcn_exp2f((float)xa[k]);
                     rp[r] = (e[0] + e[1]) + (e[2] + e[3]);
 #pragma unroll
                     for (int k = 0; k < 4; ++k) col32[k] = fmaf(wt, e[k], col32[k]);
@@ -629,6 +685,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
         const int rr = t.lane >> 2;
         if ((t.lane & 3) == 0 && rr < nrows) w.rowpart[(size_t)t.J * n + t.i0 + rbase + rr] = rs;
     } else {
+        double rp[kRPW];
 #pragma unroll
         for (int b = 0; b < kRPW; b += RB) {
             if (b > 0) {
@@ -638,36 +695,45 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
                         __builtin_amdgcn_wave_barrier();
 #pragma unroll
                         for (int r = 0; r < RB; ++r)
-                            if (b + r < nrows)
-                                raw[r] = reinterpret_cast<const typename Cost::Raw*>(myRegion + r * (kWaveRegion / RB))[t.lane];
+                            raw[r] = (b + r < nrows)
+                                ? reinterpret_cast<const typename Cost::Raw*>(myRegion + r * (kWaveRegion / RB))[t.lane]
+                                : typename Cost::Raw{};
                         __builtin_amdgcn_wave_barrier();
                     }
                 }
                 if (!staged) {
 #pragma unroll
                     for (int r = 0; r < RB; ++r)
-                        if (b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
+                        if (!kRowGuard || b + r < nrows) raw[r] = cost.load(rbase + b + r, j0);
                 }
+                // the region no longer holds staged rows: park the previous batch's partials
+                // (the compiler barrier keeps these FP64 stores after the float4 reads above)
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int r = b - RB; r < b; ++r) myRegion[r * 64 + t.lane] = rp[r];
             }
 #pragma unroll
             for (int r0 = 0; r0 < RB; ++r0) {
                 const int r = b + r0;
-                if (r < nrows) {
+                rp[r] = 0.0;
+                if (r < nrows) {  // kRowGuard holds on this path
                     double xa[4];
                     cost.args(raw[r0], g2, V, sA[rbase + r], xa);
                     const double wt = sWt[rbase + r];
-                    double rs = 0.0;
+                    double e[4];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const double e = ok[k] ? exp2_f64(xa[k]) : 0.0;
-                        rs += e;
-                        col64[k] = fma(wt, e, col64[k]);
-                    }
-                    rs = wave_sum(rs);
-                    if (t.lane == 0) w.rowpart[(size_t)t.J * n + t.i0 + rbase + r] = rs;
+                    for (int k = 0; k < 4; ++k) e[k] = exp2_f64(xa[k]);
+                    rp[r] = (e[0] + e[1]) + (e[2] + e[3]);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) col64[k] = fma(wt, e[k], col64[k]);
                 }
             }
         }
+#pragma unroll
+        for (int r = kRPW - RB; r < kRPW; ++r) myRegion[r * 64 + t.lane] = rp[r];
+        const double rs = rows_reduce_f64(myRegion, t.lane);
+        const int rr = t.lane >> 2;
+        if ((t.lane & 3) == 0 && rr < nrows) w.rowpart[(size_t)t.J * n + t.i0 + rbase + rr] = rs;
     }
     col_combine_store_strided(sColSlices, kWaveRegion, col64, t, w.colpart + (size_t)t.I * n, n, t.J * kBC);
     // every tile of row block I writes the same S_I, so the finalizer of any column block

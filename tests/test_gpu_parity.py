@@ -166,11 +166,14 @@ def test_adaptive_config1(ctx, prec):
               f"retries={res.fp64_retries} time={res.seconds * 1e3:.2f} ms; oracle stages={s.result['stages']} "
               f"sweeps={s.result['sweeps']} gap={s.result['gap']:.3e}")
         if prec == "f64":
-            # same decisions; the iterates agree up to rounding amplified by PNCG within the
-            # stopping ball, which moves UB by far less than the target
+            # same stage decisions. The inner solve stops anywhere in ||grad||_1 <= eps_d / 2, and a
+            # last-bit difference in exp can end it one line-search trial earlier or later: the
+            # oracle itself, with exp perturbed by at most 2 ulp, moves UB and the gap by up to
+            # 0.9 % of the target here (seed 0: one more trial, UB +8.9e-7). 2 % of the target
+            # bounds that spread and is still 50 times tighter than the certificate.
             assert res.stages == s.result["stages"]
-            assert abs(res.primal_cost - s.result["primal_cost"]) <= 1e-3 * 1e-4
-            assert abs(res.gap - s.result["gap"]) <= 1e-3 * 1e-4
+            assert abs(res.primal_cost - s.result["primal_cost"]) <= 2e-2 * 1e-4
+            assert abs(res.gap - s.result["gap"]) <= 2e-2 * 1e-4
 
 
 def test_invalid_inputs(ctx):
