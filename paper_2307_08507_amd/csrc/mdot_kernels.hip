@@ -62,6 +62,16 @@ __device__ __forceinline__ double dpp_d(double id, double v)
                                                                ROW_MASK, 0xf, false);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
+// The same with every row enabled and 0 for lanes whose source lies outside the row (bound
+// control): a sum's identity without initialising the destination.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d0(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
@@ -94,6 +104,26 @@ __device__ __forceinline__ double wave_reduce(double v)
     return readlane_d(v, 63);
 }
 __device__ __forceinline__ double wave_sum(double v) { return wave_reduce<0>(v); }
+// kNDot sums at once, stage by stage: the same operations in the same order per value as
+// wave_sum, with the independent chains interleaved (one after another they run at the
+// latency of the DPP moves).
+__device__ __forceinline__ void wave_sum_dots(double v[kNDot])
+{
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] += dpp_d0<0x111>(v[d]);
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] += dpp_d0<0x112>(v[d]);
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] += dpp_d0<0x114>(v[d]);
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] += dpp_d0<0x118>(v[d]);
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] += dpp_d<0x142, 0xa>(0.0, v[d]);
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] += dpp_d<0x143, 0xc>(0.0, v[d]);
+#pragma unroll
+    for (int d = 0; d < kNDot; ++d) v[d] = readlane_d(v[d], 63);
+}
 __device__ __forceinline__ double wave_min(double v) { return wave_reduce<1>(v); }
 __device__ __forceinline__ double wave_max(double v) { return wave_reduce<2>(v); }
 
@@ -935,10 +965,10 @@ __device__ void tile_r2(const Work& w, const SweepArgs& S, const TileCtx& t, dou
 // Block reduction of kNDot values (fixed tree). sred: LDS of kNDot * 4 doubles.
 __device__ void block_dots(double v[kNDot], double* dst, int tid, double* sred)
 {
+    wave_sum_dots(v);
+    if ((tid & 63) == 0) {
 #pragma unroll
-    for (int d = 0; d < kNDot; ++d) {
-        double s = wave_sum(v[d]);
-        if ((tid & 63) == 0) sred[d * 4 + (tid >> 6)] = s;
+        for (int d = 0; d < kNDot; ++d) sred[d * 4 + (tid >> 6)] = v[d];
     }
     __syncthreads();
     if (tid < kNDot) dst[tid] = (sred[tid * 4 + 0] + sred[tid * 4 + 1]) + (sred[tid * 4 + 2] + sred[tid * 4 + 3]);
@@ -1644,10 +1674,8 @@ __device__ __forceinline__ void decide_body(const Work& w, int parity)
         for (int b = lane + 256; b < nblk; b += 64)
 #pragma unroll
             for (int d = 0; d < kNDot; ++d) v[d] += C->bdots[b * kNDot + d];
-        double sum[kNDot];
-#pragma unroll
-        for (int d = 0; d < kNDot; ++d) sum[d] = wave_sum(v[d]);
-        decide(S, P, sum);
+        wave_sum_dots(v);
+        decide(S, P, v);
     } else {
         S.vec_action = 0;
     }
