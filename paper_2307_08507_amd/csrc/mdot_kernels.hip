@@ -1455,6 +1455,7 @@ k_sweep(const Work* __restrict__ wp, int parity)
 // dot products. The decide kernel that follows reduces them and writes the other slot.
 struct FinShared {
     double red[kNDot * 4];
+    double fac[256];  // exp(S_I - M) of the column partials (fast path, nrt <= 256)
 };
 
 // Raw inputs of entry k for entry_after and the finalizer, loaded without data-dependent
@@ -1542,7 +1543,7 @@ __device__ __forceinline__ double store_update(const Work& w, const SweepArgs& a
 // nrt <= 256: all loads of the group (tile shifts, partials, entry inputs) are issued before
 // any arithmetic.
 __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a, int k, bool valid, int l, int L,
-                                              bool e64, double v[kNDot])
+                                              bool e64, double v[kNDot], double* sfac, bool first)
 {
     const int n = w.n, nrt = w.nrt;
     const int kc = valid ? k : 0;
@@ -1550,22 +1551,29 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
     const int m = row ? w.nct : nrt;
     const int lane = threadIdx.x & 63;
     const double* base = row ? w.rowpart + kc : w.colpart + (kc - n);
-    double ts[4], x[8], f[8];
+    double ts[4], x[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) ts[q] = w.tshift[min(lane + 64 * q, nrt - 1)];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int I = min(l + u * L, m - 1);
         x[u] = base[(size_t)I * n];
-        f[u] = w.tshift[min(l + u * L, nrt - 1)];
     }
     const EntryIn in = entry_load(w, a, kc);
     // M = max_I S_I, the same value in every lane
     const double M = wave_max(fmax(fmax(ts[0], ts[1]), fmax(ts[2], ts[3])));
+    // the column partials' factors exp(S_I - M) depend on I alone: thread I of the workgroup
+    // forms factor I once (its wave holds S_I in ts[wave]), the entries read them from LDS
+    if (first) {
+        const int tid = threadIdx.x, wv = tid >> 6;
+        const double sI = wv == 0 ? ts[0] : (wv == 1 ? ts[1] : (wv == 2 ? ts[2] : ts[3]));
+        if (tid < nrt) sfac[tid] = exp(sI - M);
+        __syncthreads();
+    }
     double acc = 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-        if (l + u * L < m) acc = fma(x[u], row ? 1.0 : exp(f[u] - M), acc);
+        if (l + u * L < m) acc = fma(x[u], row ? 1.0 : sfac[min(l + u * L, 255)], acc);
     Comb cb{};
     cb.a = group_fold<0>(acc, L);
     if (!valid || l != 0) return;
@@ -1614,7 +1622,7 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         const int k = (vb * kVecWG + tid) >> lgL;
         const bool valid = k < 2 * n;
         if (fast) {
-            fin_lse_entry(wl, a, k, valid, l, L, e64, v);
+            fin_lse_entry(wl, a, k, valid, l, L, e64, v, sh.fac, vb == blk);
             continue;
         }
         const int kc = valid ? k : 0;
