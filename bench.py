@@ -37,6 +37,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# ALU roofline of the point-cost sweep (the cost is recomputed, nothing streams from HBM): the
+# chip issues 256 CUs x 4 SIMDs x 16 lanes of VALU work per clock at 2.4 GHz, and one element of
+# the FP32-exp loop takes about 11.6 lane-slots in the gfx950 code of its inner loop: 3 FP64 FMAs
+# and 1 FP64 add (the argument), 1 FP64->FP32 convert, 1 v_exp_f32 at quarter rate (4 slots),
+# 1.75 FP32 adds/FMAs (row and column sums) and 0.85 of per-row coordinate work.
+VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+POINT_SLOTS_PER_ELEMENT = 11.6
+POINTS_ALU_PEAK_GEXPS = VALU_LANE_SLOTS_PER_S / POINT_SLOTS_PER_ELEMENT / 1e9
 FAMILIES = ("uniform", "smooth", "blobs", "cauchy")
 COSTS = ("sqeuclid", "l1")
 BYTES = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}
@@ -181,7 +189,7 @@ def bench_grid(args) -> dict:
     sweep_prec = "f64" if args.precision == "f64" else "f32"  # MIXED finishes on the exact cost in F32
     ms = ctx.bench_sweep(costs[p0["cost"]]["desc"](), u, v, r0.gamma_final, precision=sweep_prec, iters=200)
     if args.cost_storage == "points":
-        bound, unit, peak = "alu", "Gexp/s", None
+        bound, unit, peak = "alu", "Gexp/s", round(POINTS_ALU_PEAK_GEXPS, 1)
         achieved = n * n / (ms * 1e-3) / 1e9
         per_launch = {"elements_per_launch": n * n}
     else:
