@@ -27,9 +27,7 @@ namespace {
 constexpr int kChunk = 32;       // solver steps per graph launch (even: the state slot alternates)
 constexpr int kBatchChunk = 8;   // engine steps per graph launch (admission granularity, even)
 constexpr int kMaxN = 65536;     // the finalize kernel keeps n / 64 tile shifts in LDS
-constexpr int kSweepGrid = 2048; // engine: workgroups of the grid-stride sweep kernels
 constexpr int kConvBlocks = 1024; // workgroups of the FP16 conversion (MIXED)
-constexpr int kFinGrid = 512;    // engine: workgroups of the grid-stride finalize kernel
 
 // Device buffers of one problem: workspace, device copy of Work + 2 state slots, parameters.
 struct ProblemBufs {
@@ -80,6 +78,7 @@ struct mdot_ctx {
     int engine_cc = -1;
     hipGraphExec_t bgraph = nullptr;
     int bgraph_cc = -1;
+    int bgraph_tiles = -1, bgraph_fin = -1;  // grids the batch graph was captured with
     uint64_t next_ticket = 1;
     size_t bytes_in_use = 0;
     std::map<uint64_t, mdot_result> finished;
@@ -512,9 +511,13 @@ static int rebuild_batch(mdot_ctx* ctx)
     return MDOT_OK;
 }
 
+// The batch graph launches exactly one workgroup per tile and per finalize block of the
+// problems in flight, so it is captured again whenever the batch's totals change (admissions
+// and completions, between chunks).
 static int ensure_batch_graph(mdot_ctx* ctx, int cc)
 {
-    if (ctx->bgraph && ctx->bgraph_cc == cc) return MDOT_OK;
+    const int tiles = std::max(1, ctx->h_batch->total_tiles), fin = std::max(1, ctx->h_batch->total_fin);
+    if (ctx->bgraph && ctx->bgraph_cc == cc && ctx->bgraph_tiles == tiles && ctx->bgraph_fin == fin) return MDOT_OK;
     if (ctx->bgraph) {
         (void)hipGraphExecDestroy(ctx->bgraph);
         ctx->bgraph = nullptr;
@@ -524,7 +527,7 @@ static int ensure_batch_graph(mdot_ctx* ctx, int cc)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(cc, ctx->d_batch, k & 1, kSweepGrid, kFinGrid, cap);
+        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(cc, ctx->d_batch, k & 1, tiles, fin, cap);
         launch_gather_done(ctx->d_batch, ctx->d_done, cap);
         e = hipStreamEndCapture(cap, &g);
     }
@@ -536,6 +539,8 @@ static int ensure_batch_graph(mdot_ctx* ctx, int cc)
         return fail(ctx, MDOT_E_DEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
     }
     ctx->bgraph_cc = cc;
+    ctx->bgraph_tiles = tiles;
+    ctx->bgraph_fin = fin;
     return MDOT_OK;
 }
 

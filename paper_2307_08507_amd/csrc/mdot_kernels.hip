@@ -1707,29 +1707,29 @@ __device__ __forceinline__ int batch_item(const int32_t* prefix, int nitems, int
     return lo;
 }
 
-// Batched sweep: a grid-stride loop over the tiles of every problem in flight. Its register
-// count is left to the compiler (capping it spills inside the tile loop).
+// Batched sweep: one workgroup per tile of every problem in flight (the engine launches
+// exactly total_tiles workgroups), under the same register cap as the single-problem sweep.
+// A grid-stride loop here would keep the loop-invariant values of the tile code live across
+// tiles and spill.
 template <int CC>
-__global__ void __launch_bounds__(kWG) k_sweep_batch(const BatchDesc* __restrict__ bd, int parity)
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
+k_sweep_batch(const BatchDesc* __restrict__ bd, int parity)
 {
     __shared__ double smem[kSmem];
-    const int total = bd->total_tiles, nitems = bd->nitems;
-    for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        const int b = batch_item(bd->tile_prefix, nitems, g);
-        sweep_any<CC>(*bd->items[b], parity, g - bd->tile_prefix[b], smem);
-        __syncthreads();
-    }
+    const int g = blockIdx.x;
+    if (g >= bd->total_tiles) return;
+    const int b = batch_item(bd->tile_prefix, bd->nitems, g);
+    sweep_any<CC>(*bd->items[b], parity, g - bd->tile_prefix[b], smem);
 }
 
+// Batched finalize: one workgroup per finalize block of every problem in flight.
 __global__ void __launch_bounds__(kVecWG) k_fin_batch(const BatchDesc* __restrict__ bd, int parity)
 {
     __shared__ FinShared sh;
-    const int total = bd->total_fin, nitems = bd->nitems;
-    for (int g = blockIdx.x; g < total; g += gridDim.x) {
-        const int b = batch_item(bd->fin_prefix, nitems, g);
-        fin_body(*bd->items[b], parity, g - bd->fin_prefix[b], bd->fin_prefix[b + 1] - bd->fin_prefix[b], sh);
-        __syncthreads();
-    }
+    const int g = blockIdx.x;
+    if (g >= bd->total_fin) return;
+    const int b = batch_item(bd->fin_prefix, bd->nitems, g);
+    fin_body(*bd->items[b], parity, g - bd->fin_prefix[b], bd->fin_prefix[b + 1] - bd->fin_prefix[b], sh);
 }
 
 __global__ void __launch_bounds__(kDecideWG) k_decide_batch(const BatchDesc* __restrict__ bd, int parity)
