@@ -488,23 +488,47 @@ static int rebuild_batch(mdot_ctx* ctx)
 {
     BatchDesc& B = *ctx->h_batch;
     memset(&B, 0, sizeof B);
-    int nt = 0, nf = 0, m = 0;
-    for (int s = 0; s < kMaxBatch; ++s) {
+    int nf = 0, m = 0;
+    const Work* hw[kMaxBatch];
+    for (int s = 0; s < kMaxBatch; ++s) {  // items in slot order (the done flags follow it)
         const Slot& sl = ctx->slots[s];
         if (!sl.used) continue;
-        const Work& w = sl.pb.host_work;
+        hw[m] = &sl.pb.host_work;
         B.items[m] = sl.pb.d_work;
-        B.tile_prefix[m] = nt;
         B.fin_prefix[m] = nf;
-        nt += w.nrt * w.nct;
-        nf += fin_grid(w.n);
+        nf += fin_grid(sl.pb.host_work.n);
         ++m;
     }
     B.nitems = m;
-    B.tile_prefix[m] = nt;
     B.fin_prefix[m] = nf;
-    B.total_tiles = nt;
     B.total_fin = nf;
+    // sweep groups: items with the same cost data, size and kind, in order of first appearance
+    bool taken[kMaxBatch] = {};
+    int ng = 0, ne = 0, nt = 0;
+    for (int a = 0; a < m; ++a) {
+        if (taken[a]) continue;
+        B.grp_first[ng] = ne;
+        B.grp_prefix[ng] = nt;
+        int K = 0;
+        for (int b = a; b < m; ++b) {
+            const Work& x = *hw[a];
+            const Work& y = *hw[b];
+            if (taken[b] || y.cost != x.cost || y.n != x.n || y.d != x.d || y.cost_kind != x.cost_kind ||
+                y.dtype != x.dtype)
+                continue;
+            taken[b] = true;
+            B.grp_items[ne++] = b;
+            ++K;
+        }
+        const int T = hw[a]->nrt * hw[a]->nct;
+        B.grp_size[ng] = K;
+        B.grp_tiles[ng] = T;
+        nt += K * ((T + 7) / 8) * 8;
+        ++ng;
+    }
+    B.ngroups = ng;
+    B.grp_prefix[ng] = nt;
+    B.total_tiles = nt;
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_batch, &B, sizeof B, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // h_batch is reused on the next rebuild
     ctx->batch_dirty = false;

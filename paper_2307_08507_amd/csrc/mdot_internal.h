@@ -142,14 +142,24 @@ struct Control {
     double bdots[kFinMaxGrid * kNDot];
 };
 
-// Problems in flight in one batched launch: logical tile g of the step belongs to item b with
-// tile_prefix[b] <= g < tile_prefix[b+1] (same for finalize blocks). Every item has its own
-// Work, state slots and counters, so its results do not depend on the rest of the batch.
+// Problems in flight in one batched launch. Every item has its own Work, state slots and
+// counters, so its results do not depend on the rest of the batch.
+// Finalize: workgroup g belongs to item b with fin_prefix[b] <= g < fin_prefix[b+1].
+// Sweep: the items are grouped by cost (same cost data, n and kind), and group q owns
+// workgroups grp_prefix[q] <= g < grp_prefix[q+1] (grp_prefix is a multiple of 8). Within a
+// group of K items with T tiles each, workgroup l = g - grp_prefix[q] sweeps tile
+// t = 8 (l / 8 / K) + l % 8 of the group's item (l / 8) % K (idle when t >= T): the K sweeps of
+// one cost tile land on the same XCD (workgroups go round-robin over the 8 XCDs) at nearly the
+// same time, so the cost is read from HBM once per group and from that XCD's L2 by the rest.
 constexpr int kMaxBatch = 64;
 struct BatchDesc {
-    int32_t nitems, total_tiles, total_fin, pad;
-    int32_t tile_prefix[kMaxBatch + 1];
+    int32_t nitems, total_tiles, total_fin, ngroups;
     int32_t fin_prefix[kMaxBatch + 1];
+    int32_t grp_prefix[kMaxBatch + 1];
+    int32_t grp_first[kMaxBatch];  // first entry of the group in grp_items
+    int32_t grp_size[kMaxBatch];   // K
+    int32_t grp_tiles[kMaxBatch];  // T
+    int32_t grp_items[kMaxBatch];  // item indices, group by group
     const Work* items[kMaxBatch];
 };
 

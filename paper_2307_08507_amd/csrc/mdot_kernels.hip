@@ -1707,10 +1707,10 @@ __device__ __forceinline__ int batch_item(const int32_t* prefix, int nitems, int
     return lo;
 }
 
-// Batched sweep: one workgroup per tile of every problem in flight (the engine launches
-// exactly total_tiles workgroups), under the same register cap as the single-problem sweep.
-// A grid-stride loop here would keep the loop-invariant values of the tile code live across
-// tiles and spill.
+// Batched sweep: one workgroup per tile of every problem in flight, tiles of problems that
+// share a cost interleaved so that they meet in one XCD's L2 (the engine launches exactly
+// total_tiles workgroups). Same register cap as the single-problem sweep; a grid-stride loop
+// here would keep the loop-invariant values of the tile code live across tiles and spill.
 template <int CC>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
 k_sweep_batch(const BatchDesc* __restrict__ bd, int parity)
@@ -1718,8 +1718,13 @@ k_sweep_batch(const BatchDesc* __restrict__ bd, int parity)
     __shared__ double smem[kSmem];
     const int g = blockIdx.x;
     if (g >= bd->total_tiles) return;
-    const int b = batch_item(bd->tile_prefix, bd->nitems, g);
-    sweep_any<CC>(*bd->items[b], parity, g - bd->tile_prefix[b], smem);
+    const int q = batch_item(bd->grp_prefix, bd->ngroups, g);
+    const int l = g - bd->grp_prefix[q];
+    const int K = bd->grp_size[q], T = bd->grp_tiles[q];
+    const int run = l >> 3, k = run % K;
+    const int t = (run / K) * 8 + (l & 7);
+    if (t >= T) return;
+    sweep_any<CC>(*bd->items[bd->grp_items[bd->grp_first[q] + k]], parity, t, smem);
 }
 
 // Batched finalize: one workgroup per finalize block of every problem in flight.

@@ -188,6 +188,49 @@ def test_engine_bitwise_equals_solve(ctx, prec):
         eng.close()
 
 
+@pytest.mark.parametrize("k", [16, 33])
+def test_engine_shared_cost_groups(ctx, k):
+    # problems that share a cost sweep their tiles interleaved (one group per cost); every
+    # result stays bit-identical to the solve alone. k = 33: n = 1089 has 18 x 5 = 90 tiles,
+    # not a multiple of 8, so the groups carry idle workgroups
+    print(f"engine shared-cost k={k}", flush=True)
+    costs = {kind: dev(W.grid_problem(k, "smooth", kind, 0)[0], torch.float32) for kind in ("sqeuclid", "l1")}
+    probs = []
+    for j, fam in enumerate(["smooth", "blobs", "uniform"]):
+        for kind in ("sqeuclid", "l1"):
+            _, r, c = W.grid_problem(k, fam, kind, 10 + j)
+            probs.append((costs[kind], dev(r), dev(c)))
+    prm = M.default_params(precision="f32")
+    alone = []
+    for C, r, c in probs:
+        u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+        res = ctx.solve(M.dense_cost(C), r, c, 1e-5, prm, u, v)
+        alone.append((res, u.cpu(), v.cpu()))
+    eng = M.Context(0)
+    try:
+        tickets, outs = [], []
+        for C, r, c in probs:
+            u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+            v = torch.empty_like(u)
+            tickets.append(eng.submit(M.dense_cost(C), r, c, 1e-5, prm, u, v))
+            outs.append((u, v))
+        assert all(t is not None for t in tickets)
+        for _ in range(100000):
+            if eng.inflight()[0] == 0:
+                break
+            eng.run(64)
+        assert eng.inflight() == (0, 0)
+        for t, (u, v), (ra, ua, va) in zip(tickets, outs, alone):
+            rb = eng.poll(t)
+            assert rb is not None and rb.status == 0
+            assert torch.equal(u.cpu(), ua) and torch.equal(v.cpu(), va)
+            for f in ("primal_cost", "dual_bound", "gap", "stages", "pncg_iters", "sweeps"):
+                assert getattr(rb, f) == getattr(ra, f), f
+    finally:
+        eng.close()
+
+
 def test_engine_staggered_submission(ctx):
     # a request admitted while others are half-way gets the same result as alone
     probs = _engine_problems()
