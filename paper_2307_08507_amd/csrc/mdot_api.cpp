@@ -25,7 +25,7 @@ using namespace mdot;
 namespace {
 
 constexpr int kChunk = 32;       // solver steps per graph launch (even: the state slot alternates)
-constexpr int kBatchChunk = 8;   // engine steps per graph launch (admission granularity, even)
+constexpr int kBatchChunk = 16;  // engine steps per graph launch (admission granularity, even)
 constexpr int kMaxN = 65536;     // the finalize kernel keeps n / 64 tile shifts in LDS
 constexpr int kConvBlocks = 1024; // workgroups of the FP16 conversion (MIXED)
 
@@ -59,7 +59,12 @@ struct mdot_ctx {
     std::string err;
     ProblemBufs main;             // single solves and the standalone entry points
     State* h_state = nullptr;     // pinned
-    int* h_done = nullptr;        // pinned, kMaxBatch + 2 slots
+    // done flags written by the last kernel of each graph chunk (pinned, mapped, fine-grained):
+    // 2 for the single solves, then 2 x kMaxBatch for the engine; d_hdone is the device alias
+    int* h_done = nullptr;
+    int* d_hdone = nullptr;
+    int* d_seq = nullptr;     // device chunk counters: [0] single solves, [1] engine
+    uint64_t solo_seq = 0;    // host mirror of d_seq[0]
     double* h_scratch = nullptr;  // pinned, intake results
     double* d_scratch = nullptr;  // device, intake results / cost range partials
     size_t scratch_doubles = 0;
@@ -73,12 +78,19 @@ struct mdot_ctx {
     std::vector<ProblemBufs> pool;  // released problem buffers kept for reuse
     BatchDesc* h_batch = nullptr;   // pinned
     BatchDesc* d_batch = nullptr;
-    int* d_done = nullptr;
     bool batch_dirty = true;
     int engine_cc = -1;
     hipGraphExec_t bgraph = nullptr;
     int bgraph_cc = -1;
     int bgraph_tiles = -1, bgraph_fin = -1;  // grids the batch graph was captured with
+    // engine chunks in flight: the next chunk is launched before the previous one's done flags
+    // are read; each remembers the slots and tickets it advanced, in descriptor order
+    hipEvent_t eng_ev[2] = {nullptr, nullptr};
+    int eng_pending = -1;  // buffer of the launched chunk not yet read back, or -1
+    int eng_next = 0;      // buffer of the next chunk
+    int chunk_m[2] = {0, 0};
+    int chunk_slot[2][kMaxBatch];
+    uint64_t chunk_ticket[2][kMaxBatch];
     uint64_t next_ticket = 1;
     size_t bytes_in_use = 0;
     std::map<uint64_t, mdot_result> finished;
@@ -435,6 +447,7 @@ static int ensure_graph(mdot_ctx* ctx, int n)
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         for (int k = 0; k < kChunk; ++k) launch_step(hw, ctx->main.d_work, k & 1, cap);
+        launch_chunk_done(ctx->main.d_work, ctx->d_hdone, ctx->d_seq, cap);
         e = hipStreamEndCapture(cap, &g);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
@@ -455,20 +468,20 @@ static int run_steps(mdot_ctx* ctx, int n, int max_chunks)
 {
     int rc = ensure_graph(ctx, n);
     if (rc) return rc;
-    State* st_dev = ctx->main.host_work.st;  // slot 0 holds the newest state after an even chunk
+    // slot 0 holds the newest state after an even chunk; the graph's last kernel copies its
+    // done flag to h_done[chunk number & 1]
+    const uint64_t base = ctx->solo_seq;
     int launched = 0, checked = 0;
-    ctx->h_done[0] = ctx->h_done[1] = 0;
     for (;;) {
         while (launched < checked + 2 && launched < max_chunks) {
             HIPCHK(ctx, hipGraphLaunch(ctx->graph, ctx->stream));
-            HIPCHK(ctx, hipMemcpyAsync(&ctx->h_done[launched & 1], &st_dev->done, sizeof(int), hipMemcpyDeviceToHost,
-                                       ctx->stream));
             HIPCHK(ctx, hipEventRecord(ctx->ev[launched & 1], ctx->stream));
             ++launched;
+            ++ctx->solo_seq;
         }
         if (checked == launched) break;
         HIPCHK(ctx, hipEventSynchronize(ctx->ev[checked & 1]));
-        const int done = ctx->h_done[checked & 1];
+        const int done = ctx->h_done[(base + checked) & 1];
         ++checked;
         if (done) break;
     }
@@ -552,7 +565,7 @@ static int ensure_batch_graph(mdot_ctx* ctx, int cc)
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(cc, ctx->d_batch, k & 1, tiles, fin, cap);
-        launch_gather_done(ctx->d_batch, ctx->d_done, cap);
+        launch_gather_done(ctx->d_batch, ctx->d_hdone + 2, ctx->d_seq + 1, cap);
         e = hipStreamEndCapture(cap, &g);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&ctx->bgraph, g, nullptr, nullptr, 0);
@@ -608,12 +621,16 @@ int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_
     ctx->budget = hbm_budget_bytes;
     bool ok = hipHostMalloc(&ctx->h_state, sizeof(State), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&ctx->h_prm, sizeof(DevParams), hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(&ctx->h_done, (kMaxBatch + 2) * sizeof(int), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_done, (2 * kMaxBatch + 2) * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) ==
+                  hipSuccess &&
+              hipHostGetDevicePointer((void**)&ctx->d_hdone, ctx->h_done, 0) == hipSuccess &&
+              hipMalloc(&ctx->d_seq, 2 * sizeof(int)) == hipSuccess && hipMemset(ctx->d_seq, 0, 2 * sizeof(int)) == hipSuccess &&
               hipHostMalloc(&ctx->h_batch, sizeof(BatchDesc), hipHostMallocDefault) == hipSuccess &&
               hipMalloc(&ctx->d_batch, sizeof(BatchDesc)) == hipSuccess &&
-              hipMalloc(&ctx->d_done, kMaxBatch * sizeof(int)) == hipSuccess &&
               hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->eng_ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->eng_ev[1], hipEventDisableTiming) == hipSuccess &&
               hipEventCreate(&ctx->t0) == hipSuccess && hipEventCreate(&ctx->t1) == hipSuccess;
     if (!ok) {
         mdot_ctx_destroy(ctx);
@@ -642,8 +659,10 @@ int mdot_ctx_destroy(mdot_ctx* ctx)
     if (ctx->h_done) (void)hipHostFree(ctx->h_done);
     if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
     if (ctx->d_batch) (void)hipFree(ctx->d_batch);
-    if (ctx->d_done) (void)hipFree(ctx->d_done);
+    if (ctx->d_seq) (void)hipFree(ctx->d_seq);
     for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->eng_ev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->t0) (void)hipEventDestroy(ctx->t0);
     if (ctx->t1) (void)hipEventDestroy(ctx->t1);
@@ -905,6 +924,28 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
     return MDOT_OK;
 }
 
+// Read back an engine chunk: retire the solves it finished (their slots may already hold newer
+// solves, admitted after the chunk was launched: those are told apart by the ticket).
+static int process_chunk(mdot_ctx* ctx, int buf, int* completed)
+{
+    HIPCHK(ctx, hipEventSynchronize(ctx->eng_ev[buf]));
+    const int* done = ctx->h_done + 2 + buf * kMaxBatch;
+    for (int m = 0; m < ctx->chunk_m[buf]; ++m) {
+        Slot& sl = ctx->slots[ctx->chunk_slot[buf][m]];
+        if (!done[m] || !sl.used || sl.ticket != ctx->chunk_ticket[buf][m]) continue;
+        if (launch_finish(sl.pb.d_work, sl.u_out, sl.v_out, ctx->stream))
+            return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
+        int rc = read_state(ctx, sl.pb);
+        if (rc) return rc;
+        mdot_result res;
+        fill_result(*ctx->h_state, 0.0, &res);
+        ctx->finished[sl.ticket] = res;
+        release_slot(ctx, sl);
+        ++*completed;
+    }
+    return MDOT_OK;
+}
+
 int mdot_run(mdot_ctx* ctx, int steps, int* n_done)
 {
     if (!ctx) return MDOT_E_ARG;
@@ -915,34 +956,38 @@ int mdot_run(mdot_ctx* ctx, int steps, int* n_done)
     for (int ch = 0; ch < chunks; ++ch) {
         int active = 0;
         for (const Slot& sl : ctx->slots) active += sl.used;
-        if (active == 0) break;
+        if (active == 0 && ctx->eng_pending < 0) break;
         int rc;
-        if (ctx->batch_dirty) {
-            rc = rebuild_batch(ctx);
+        if (active > 0) {  // launch the next chunk before reading the previous one back
+            if (ctx->batch_dirty) {
+                rc = rebuild_batch(ctx);
+                if (rc) return rc;
+            }
+            rc = ensure_batch_graph(ctx, ctx->engine_cc);
             if (rc) return rc;
-        }
-        rc = ensure_batch_graph(ctx, ctx->engine_cc);
-        if (rc) return rc;
-        HIPCHK(ctx, hipGraphLaunch(ctx->bgraph, ctx->stream));
-        HIPCHK(ctx, hipMemcpyAsync(ctx->h_done, ctx->d_done, kMaxBatch * sizeof(int), hipMemcpyDeviceToHost,
-                                   ctx->stream));
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        // items are in slot order in the descriptor
-        int m = 0;
-        for (int s = 0; s < kMaxBatch; ++s) {
-            Slot& sl = ctx->slots[s];
-            if (!sl.used) continue;
-            const int done = ctx->h_done[m++];
-            if (!done) continue;
-            if (launch_finish(sl.pb.d_work, sl.u_out, sl.v_out, ctx->stream))
-                return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
-            rc = read_state(ctx, sl.pb);
+            const int buf = ctx->eng_next;
+            int m = 0;
+            for (int s = 0; s < kMaxBatch; ++s) {  // descriptor order = slot order
+                if (!ctx->slots[s].used) continue;
+                ctx->chunk_slot[buf][m] = s;
+                ctx->chunk_ticket[buf][m] = ctx->slots[s].ticket;
+                ++m;
+            }
+            ctx->chunk_m[buf] = m;
+            // the graph's last kernel writes this chunk's done flags to host buffer `buf` (engine
+            // chunks alternate buffers in launch order, as the device counter does)
+            HIPCHK(ctx, hipGraphLaunch(ctx->bgraph, ctx->stream));
+            HIPCHK(ctx, hipEventRecord(ctx->eng_ev[buf], ctx->stream));
+            if (ctx->eng_pending >= 0) {
+                rc = process_chunk(ctx, ctx->eng_pending, &completed);
+                if (rc) return rc;
+            }
+            ctx->eng_pending = buf;
+            ctx->eng_next = buf ^ 1;
+        } else {  // nothing left to advance: read the last chunk back
+            rc = process_chunk(ctx, ctx->eng_pending, &completed);
             if (rc) return rc;
-            mdot_result res;
-            fill_result(*ctx->h_state, 0.0, &res);
-            ctx->finished[sl.ticket] = res;
-            release_slot(ctx, sl);
-            ++completed;
+            ctx->eng_pending = -1;
         }
     }
     if (n_done) *n_done = completed;

@@ -177,6 +177,9 @@ int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, doubl
 // fixed grids (grid-stride over the descriptor), and a gather of the items' done flags.
 int cost_code_of(int cost_kind, int dtype);
 int launch_step_batch(int cost_code, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, void* stream);
-int launch_gather_done(const BatchDesc* bd, int* out, void* stream);
+// End-of-chunk done flags into host-visible memory: chunk number *seq (a device counter, advanced
+// here) writes out[(seq & 1) * kMaxBatch + item] (batch) or out[seq & 1] (single problem).
+int launch_gather_done(const BatchDesc* bd, int* out, int* seq, void* stream);
+int launch_chunk_done(const Work* wd, int* out, int* seq, void* stream);
 
 }  // namespace mdot

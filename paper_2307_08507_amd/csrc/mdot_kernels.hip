@@ -1742,10 +1742,23 @@ __global__ void __launch_bounds__(kDecideWG) k_decide_batch(const BatchDesc* __r
     for (int b = blockIdx.x; b < bd->nitems; b += gridDim.x) decide_body(*bd->items[b], parity);
 }
 
-__global__ void k_gather_done(const BatchDesc* __restrict__ bd, int* out)
+// End-of-chunk done flags, written straight into pinned host memory (a stream-ordered copy
+// between chunks would stall the stream for tens of microseconds). The chunk counter *seq,
+// kept on the device, picks the host buffer: chunk s writes buffer s & 1, so the chunk queued
+// behind it never overwrites flags the host has not read yet.
+__global__ void k_gather_done(const BatchDesc* __restrict__ bd, int* out, int* seq)
 {
-    const int b = threadIdx.x;
-    if (b < bd->nitems) out[b] = bd->items[b]->st[0].done;
+    const int b = threadIdx.x;  // one wave: every lane reads the counter before lane 0 advances it
+    const int s = *seq;
+    if (b < bd->nitems) out[(s & 1) * kMaxBatch + b] = bd->items[b]->st[0].done;
+    if (b == 0) *seq = s + 1;
+}
+
+__global__ void k_chunk_done(const Work* __restrict__ wp, int* out, int* seq)
+{
+    const int s = *seq;
+    out[s & 1] = ctl_of(*wp).st[0].done;
+    *seq = s + 1;
 }
 
 // ------------------------------------------------------------------ set-up kernels
@@ -1951,9 +1964,15 @@ int launch_step_batch(int cc, const BatchDesc* bd, int parity, int sweep_grid, i
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_gather_done(const BatchDesc* bd, int* out, void* stream)
+int launch_gather_done(const BatchDesc* bd, int* out, int* seq, void* stream)
 {
-    hipLaunchKernelGGL(k_gather_done, dim3(1), dim3(kMaxBatch), 0, (hipStream_t)stream, bd, out);
+    hipLaunchKernelGGL(k_gather_done, dim3(1), dim3(kMaxBatch), 0, (hipStream_t)stream, bd, out, seq);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_chunk_done(const Work* wd, int* out, int* seq, void* stream)
+{
+    hipLaunchKernelGGL(k_chunk_done, dim3(1), dim3(1), 0, (hipStream_t)stream, wd, out, seq);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
