@@ -1679,7 +1679,20 @@ __device__ __forceinline__ void decide_body(const Work& w, int parity)
         for (int d = 0; d < kNDot; ++d) v[d] += (lane + 64 * q < nblk) ? x[q][d] : 0.0;
     const bool active = !S.done && S.sweep_mode != SM_NONE;
     if (active) {
-        for (int b = lane + 256; b < nblk; b += 64)
+        // the workgroups past the first 256, in the same order, four rounds' loads at a time
+        int b = lane + 256;
+        for (; b + 192 < nblk; b += 256) {
+            double y[4][kNDot];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int d = 0; d < kNDot; ++d) y[u][d] = C->bdots[(b + 64 * u) * kNDot + d];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int d = 0; d < kNDot; ++d) v[d] += y[u][d];
+        }
+        for (; b < nblk; b += 64)
 #pragma unroll
             for (int d = 0; d < kNDot; ++d) v[d] += C->bdots[b * kNDot + d];
         wave_sum_dots(v);
