@@ -83,6 +83,8 @@ struct mdot_ctx {
     hipGraphExec_t bgraph = nullptr;
     int bgraph_cc = -1;
     int bgraph_tiles = -1, bgraph_fin = -1;  // grids the batch graph was captured with
+    bool bgraph_big = false;                 // ... and whether a problem has n > 8192
+    bool batch_big = false;
     // engine chunks in flight: the next chunk is launched before the previous one's done flags
     // are read; each remembers the slots and tickets it advanced, in descriptor order
     hipEvent_t eng_ev[2] = {nullptr, nullptr};
@@ -211,6 +213,7 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
     w.nrt = tiles_r(n);
     w.nct = tiles_c(n);
     w.fin_L = fin_lanes(n);
+    w.fin_per = fin_per(n);
     w.fin_lgL = 0;
     while ((1 << w.fin_lgL) < w.fin_L) ++w.fin_lgL;
     w.fin_nvb = fin_vblocks(n);
@@ -515,6 +518,8 @@ static int rebuild_batch(mdot_ctx* ctx)
     B.nitems = m;
     B.fin_prefix[m] = nf;
     B.total_fin = nf;
+    ctx->batch_big = false;
+    for (int a = 0; a < m; ++a) ctx->batch_big |= hw[a]->fin_per > 8;
     // sweep groups: items with the same cost data, size and kind, in order of first appearance
     bool taken[kMaxBatch] = {};
     int ng = 0, ne = 0, nt = 0;
@@ -554,7 +559,10 @@ static int rebuild_batch(mdot_ctx* ctx)
 static int ensure_batch_graph(mdot_ctx* ctx, int cc)
 {
     const int tiles = std::max(1, ctx->h_batch->total_tiles), fin = std::max(1, ctx->h_batch->total_fin);
-    if (ctx->bgraph && ctx->bgraph_cc == cc && ctx->bgraph_tiles == tiles && ctx->bgraph_fin == fin) return MDOT_OK;
+    const bool big = ctx->batch_big;
+    if (ctx->bgraph && ctx->bgraph_cc == cc && ctx->bgraph_tiles == tiles && ctx->bgraph_fin == fin &&
+        ctx->bgraph_big == big)
+        return MDOT_OK;
     if (ctx->bgraph) {
         (void)hipGraphExecDestroy(ctx->bgraph);
         ctx->bgraph = nullptr;
@@ -564,7 +572,7 @@ static int ensure_batch_graph(mdot_ctx* ctx, int cc)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(cc, ctx->d_batch, k & 1, tiles, fin, cap);
+        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(cc, ctx->d_batch, k & 1, tiles, fin, big, cap);
         launch_gather_done(ctx->d_batch, ctx->d_hdone + 2, ctx->d_seq + 1, cap);
         e = hipStreamEndCapture(cap, &g);
     }
@@ -578,6 +586,7 @@ static int ensure_batch_graph(mdot_ctx* ctx, int cc)
     ctx->bgraph_cc = cc;
     ctx->bgraph_tiles = tiles;
     ctx->bgraph_fin = fin;
+    ctx->bgraph_big = big;
     return MDOT_OK;
 }
 

@@ -16,17 +16,19 @@ constexpr int kBR = 4 * kRPW;
 constexpr int kVecWG = 256;
 
 // Finalize kernel geometry: the tile partials of each 2n-vector entry are combined by a group of
-// L lanes (a power of two, at most 64) that each fold about kFinPer of them; the groups fill
+// L lanes (a power of two, at most 64) that each fold up to fin_per(n) of them; the groups fill
 // fin_vblocks(n) virtual workgroups, run on fin_grid(n) workgroups. Depends on n only, so the
-// summation order of every entry is fixed by n.
-constexpr int kFinPer = 8;
+// summation order of every entry is fixed by n. Past n = 8192 each lane takes 32 partials, so
+// that the groups fit in kFinMaxGrid workgroups without a second round (n = 16384: L = 8,
+// 1024 workgroups; with 8 per lane it would be L = 32 and four rounds).
 constexpr int kFinMaxGrid = 1024;
+constexpr int fin_per(int n) { return n > 8192 ? 32 : 8; }
 constexpr int fin_lanes(int n)
 {
     const int nrt = (n + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
     const int m = nrt > nct ? nrt : nct;
     int L = 1;
-    while (L < 64 && L * kFinPer < m) L <<= 1;
+    while (L < 64 && L * fin_per(n) < m) L <<= 1;
     return L;
 }
 constexpr int fin_vblocks(int n) { return (2 * n * fin_lanes(n) + kVecWG - 1) / kVecWG; }
@@ -99,7 +101,7 @@ struct State {
 // Device buffers of one problem (all FP64 unless noted). 2n-vectors hold rows then columns.
 struct Work {
     int32_t n, nrt, nct;     // size, row tiles, column tiles
-    int32_t cost_kind, dtype, d, pad;
+    int32_t cost_kind, dtype, d, fin_per;  // cost kind and dtype, point dimension, fin_per(n)
     int32_t fin_L, fin_lgL, fin_nvb, fin_nblk;  // fin_lanes(n), log2 of it, fin_vblocks(n), fin_grid(n)
     const void* cost;        // dense cost or coordinates X then Y
     double scale;            // C = scale * raw
@@ -176,7 +178,9 @@ int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, doubl
 // Batched step over a BatchDesc in device memory (cost type cost_code for every item), with
 // fixed grids (grid-stride over the descriptor), and a gather of the items' done flags.
 int cost_code_of(int cost_kind, int dtype);
-int launch_step_batch(int cost_code, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, void* stream);
+// big: some problem in flight has n > 8192 (the finalize instance for fin_per(n) = 32)
+int launch_step_batch(int cost_code, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, bool big,
+                      void* stream);
 // End-of-chunk done flags into host-visible memory: chunk number *seq (a device counter, advanced
 // here) writes out[(seq & 1) * kMaxBatch + item] (batch) or out[seq & 1] (single problem).
 int launch_gather_done(const BatchDesc* bd, int* out, int* seq, void* stream);

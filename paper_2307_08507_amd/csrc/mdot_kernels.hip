@@ -1542,6 +1542,7 @@ __device__ __forceinline__ double store_update(const Work& w, const SweepArgs& a
 // LSE finalize of one entry group when every partial fits one load per slot (m <= 8 L) and
 // nrt <= 256: all loads of the group (tile shifts, partials, entry inputs) are issued before
 // any arithmetic.
+template <int PER>
 __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a, int k, bool valid, int l, int L,
                                               bool e64, double v[kNDot], double* sfac, bool first)
 {
@@ -1551,11 +1552,11 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
     const int m = row ? w.nct : nrt;
     const int lane = threadIdx.x & 63;
     const double* base = row ? w.rowpart + kc : w.colpart + (kc - n);
-    double ts[4], x[8];
+    double ts[4], x[PER];
 #pragma unroll
     for (int q = 0; q < 4; ++q) ts[q] = w.tshift[min(lane + 64 * q, nrt - 1)];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < PER; ++u) {
         const int I = min(l + u * L, m - 1);
         x[u] = base[(size_t)I * n];
     }
@@ -1572,7 +1573,7 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
     }
     double acc = 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < PER; ++u)
         if (l + u * L < m) acc = fma(x[u], row ? 1.0 : sfac[min(l + u * L, 255)], acc);
     Comb cb{};
     cb.a = group_fold<0>(acc, L);
@@ -1585,6 +1586,9 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
 // Finalize workgroup `blk` of the problem's `nblk` (= fin_grid(n)) workgroups. Entry k is
 // handled by an L-lane group (L = fin_lanes(n)); the groups are laid out in virtual blocks of
 // kVecWG / L entries, which the workgroups take in a grid-stride loop.
+// BIG: the instance that also handles n > 8192 (32 partials per lane in the fast path); it needs
+// more registers, so the smaller sizes run the other instance.
+template <bool BIG>
 __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int nblk, FinShared& sh)
 {
     // Every control read (the Work fields and the state) is issued before the first branch,
@@ -1606,7 +1610,8 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     const int l = tid & (L - 1);
     const bool active = (done == 0) & (mode != SM_NONE);
     const bool e64 = exp64 != 0;
-    const bool fast = active & (mode == SM_LSE) & (wl.nrt <= 256) & (wl.nrt <= 8 * L) & (wl.nct <= 8 * L);
+    const int per = wl.fin_per;
+    const bool fast = active & (mode == SM_LSE) & (wl.nrt <= 256) & (wl.nrt <= per * L) & (wl.nct <= per * L);
     double v[kNDot];
 #pragma unroll
     for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
@@ -1622,7 +1627,8 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         const int k = (vb * kVecWG + tid) >> lgL;
         const bool valid = k < 2 * n;
         if (fast) {
-            fin_lse_entry(wl, a, k, valid, l, L, e64, v, sh.fac, vb == blk);
+            if (!BIG || per == 8) fin_lse_entry<8>(wl, a, k, valid, l, L, e64, v, sh.fac, vb == blk);
+            else fin_lse_entry<32>(wl, a, k, valid, l, L, e64, v, sh.fac, vb == blk);
             continue;
         }
         const int kc = valid ? k : 0;
@@ -1637,10 +1643,11 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     if (active) block_dots(v, bdots_of(w) + (size_t)blk * kNDot, tid, sh.red);
 }
 
+template <bool BIG>
 __global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int parity)
 {
     __shared__ FinShared sh;
-    fin_body(*wp, parity, blockIdx.x, gridDim.x, sh);
+    fin_body<BIG>(*wp, parity, blockIdx.x, gridDim.x, sh);
 }
 
 // ------------------------------------------------------------------ the decide kernel
@@ -1741,13 +1748,14 @@ k_sweep_batch(const BatchDesc* __restrict__ bd, int parity)
 }
 
 // Batched finalize: one workgroup per finalize block of every problem in flight.
+template <bool BIG>
 __global__ void __launch_bounds__(kVecWG) k_fin_batch(const BatchDesc* __restrict__ bd, int parity)
 {
     __shared__ FinShared sh;
     const int g = blockIdx.x;
     if (g >= bd->total_fin) return;
     const int b = batch_item(bd->fin_prefix, bd->nitems, g);
-    fin_body(*bd->items[b], parity, g - bd->fin_prefix[b], bd->fin_prefix[b + 1] - bd->fin_prefix[b], sh);
+    fin_body<BIG>(*bd->items[b], parity, g - bd->fin_prefix[b], bd->fin_prefix[b + 1] - bd->fin_prefix[b], sh);
 }
 
 __global__ void __launch_bounds__(kDecideWG) k_decide_batch(const BatchDesc* __restrict__ bd, int parity)
@@ -1952,7 +1960,8 @@ int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
 #define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity)
     MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
-    hipLaunchKernelGGL(k_fin, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
+    if (hw.fin_per > 8) hipLaunchKernelGGL(k_fin<true>, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
+    else hipLaunchKernelGGL(k_fin<false>, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideWG), 0, s, wd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1966,13 +1975,14 @@ int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_step_batch(int cc, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, void* stream)
+int launch_step_batch(int cc, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, bool big, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
 #define L_(CC) hipLaunchKernelGGL(k_sweep_batch<CC>, dim3(sweep_grid), dim3(kWG), 0, s, bd, parity)
     MDOT_CC_SWITCH(cc, L_)
 #undef L_
-    hipLaunchKernelGGL(k_fin_batch, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
+    if (big) hipLaunchKernelGGL(k_fin_batch<true>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
+    else hipLaunchKernelGGL(k_fin_batch<false>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
     hipLaunchKernelGGL(k_decide_batch, dim3(kMaxBatch), dim3(kDecideWG), 0, s, bd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
