@@ -183,9 +183,14 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
                 double target_gap, const mdot_params* params, double* u_out, double* v_out,
                 uint64_t* ticket);
 
-/* Advance every solve in flight by `steps` solver steps (rounded up to whole chunks of 8),
+/* Advance every solve in flight by `steps` solver steps (rounded up to whole chunks of 16) and
  * retire the finished ones (potentials written to their u_out/v_out, results kept for
- * mdot_poll). *n_done (host, may be NULL) receives the number retired. Synchronous. */
+ * mdot_poll). Chunks are pipelined: each chunk is launched before the previous one is read
+ * back, so a call retires the solves finished by the chunks read back during it, and the last
+ * chunk it launched is read back by the next call (or by mdot_poll with wait != 0). A solve
+ * that finished stays in flight, doing nothing, until its chunk is read back. *n_done (host,
+ * may be NULL) receives the number retired. Returns after the chunks it read back have
+ * completed; the last chunk launched may still be running. */
 int mdot_run(mdot_ctx* ctx, int steps, int* n_done);
 
 /* Result of a submitted solve. Returns MDOT_OK (res filled, ticket released) or 2 when still in
