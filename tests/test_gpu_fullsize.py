@@ -6,6 +6,8 @@
   FP64 by the oracle's definition), and the solve's output is checked by the oracle's own
   Round + certificate on the returned potentials. A ragged size (n = 4097: no 16-byte rows,
   ragged last tiles) covers the other load path at scale.
+* Past n = 8192 (the finalize's other instance): point-cost sweeps at n = 12000 on sampled rows
+  and columns, and an n = 9000 point-cost solve re-certified by the oracle.
 * Degenerate cases with closed forms: n = 1, identical marginals on a cost with zero
   diagonal (OT = 0), and a separable cost C_ij = a_i + b_j (every plan costs <a, r> + <b, c>).
 
@@ -96,6 +98,77 @@ def test_solve_fullsize_recertified_by_oracle(ctx):
     # the oracle rounds the plan of the returned potentials at gamma_final (Alg. 3) and bounds
     # OT with their c-transforms: its UB is the GPU's UB up to FP32-exp rounding, and the
     # GPU's certified bound cannot exceed a feasible plan's cost
+    ub_o, lb_o, me_o, _ = O.round_certify(C64, u.cpu().numpy(), v.cpu().numpy(), res.gamma_final, r, c)
+    print(f"oracle: UB={ub_o!r} LB(u/gamma)={lb_o!r} marg_err={me_o:.2e}")
+    assert res.primal_cost == pytest.approx(ub_o, rel=1e-5)
+    assert res.dual_bound <= ub_o + 1e-12
+    assert lb_o <= res.primal_cost + 1e-12
+    assert me_o <= 1e-12
+
+
+def _points_problem(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, 2)).astype(np.float32)
+    Y = rng.random((n, 2)).astype(np.float32)
+    r = rng.random(n) + 0.1
+    c = rng.random(n) + 0.1
+    return X, Y, r / r.sum(), c / c.sum()
+
+
+def _points_rows(X, Y, idx, scale, axis):
+    """Rows (axis 0) or columns (axis 1) idx of C = scale |x_i - y_j|^2 in FP64 from the FP32
+    coordinates."""
+    A, B = (X, Y) if axis == 0 else (Y, X)
+    A, B = A.astype(np.float64)[idx], B.astype(np.float64)
+    out = np.zeros((len(A), len(B)))
+    for e in range(A.shape[1]):
+        d = np.subtract.outer(A[:, e], B[:, e])
+        out += d * d
+    return scale * out
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_lse2_large_n_points_sampled(ctx, prec):
+    # past n = 8192 the finalize folds 32 partials per lane (its other kernel instance);
+    # n = 12000 also leaves ragged last tiles. Point costs, scale 1/2 (C in [0, 1])
+    from scipy.special import logsumexp
+
+    n, gamma, scale = 12000, 300.0, 0.5
+    print(f"large-n lse2 points n={n} prec={prec}", flush=True)
+    X, Y, _, _ = _points_problem(n, 77)
+    rng = np.random.default_rng(78)
+    u = rng.standard_normal(n) * 0.1
+    v = rng.standard_normal(n) * 0.1
+    XY = dev(np.concatenate([X, Y]).ravel(), torch.float32)
+    lr = torch.empty(n, dtype=torch.float64, device="cuda")
+    lc = torch.empty_like(lr)
+    assert ctx.lse2(M.point_cost(XY, n, 2, "sqeuclid", scale=scale), dev(u), dev(v), gamma, lr, lc,
+                    precision=prec) == 0
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([rng.choice(n, 40, replace=False), [0, n - 1]]))
+    cols = np.unique(np.concatenate([rng.choice(n, 40, replace=False), [0, n - 1]]))
+    Cr = _points_rows(X, Y, rows, scale, 0)
+    Cc = _points_rows(X, Y, cols, scale, 1)
+    lr_o = logsumexp(u[rows, None] + v[None, :] - gamma * Cr, axis=1)
+    lc_o = logsumexp(u[None, :] + v[cols, None] - gamma * Cc, axis=1)
+    tol = 1e-12 * gamma if prec == "f64" else 2e-6
+    np.testing.assert_allclose(lr.cpu().numpy()[rows], lr_o, rtol=0, atol=tol)
+    np.testing.assert_allclose(lc.cpu().numpy()[cols], lc_o, rtol=0, atol=tol)
+
+
+def test_solve_large_n_points_recertified_by_oracle(ctx):
+    # a solve past n = 8192 (n = 9000, ragged tiles), checked by the oracle's Round and
+    # certificate on the returned potentials
+    n, scale = 9000, 0.5
+    X, Y, r, c = _points_problem(n, 79)
+    XY = dev(np.concatenate([X, Y]).ravel(), torch.float32)
+    u = torch.empty(n, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+    res = ctx.solve(M.point_cost(XY, n, 2, "sqeuclid", scale=scale), dev(r), dev(c), 1e-4,
+                    M.default_params(precision="f32"), u, v)
+    print(f"n={n} points solve: gap={res.gap:.3e} UB={res.primal_cost!r} sweeps={res.sweeps}", flush=True)
+    assert res.status == 0 and 0 <= res.gap <= 1e-4
+    C64 = _points_rows(X, Y, np.arange(n), scale, 0)
     ub_o, lb_o, me_o, _ = O.round_certify(C64, u.cpu().numpy(), v.cpu().numpy(), res.gamma_final, r, c)
     print(f"oracle: UB={ub_o!r} LB(u/gamma)={lb_o!r} marg_err={me_o:.2e}")
     assert res.primal_cost == pytest.approx(ub_o, rel=1e-5)
