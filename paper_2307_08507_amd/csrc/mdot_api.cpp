@@ -4,9 +4,11 @@
 // keeping two chunks in flight so the GPU never waits for the host.
 //
 // The serving engine (mdot_submit / mdot_run / mdot_poll) keeps up to kMaxBatch solves in
-// flight. Every engine step advances all of them with one launch per kernel (grid-stride over
-// a device batch descriptor); a finished solve frees its slot and workspace at the next chunk
-// boundary, where new requests can be admitted if a slot and the HBM budget allow.
+// flight. Every engine step advances all of them with one launch per kernel, one workgroup per
+// tile and per finalize block of the solves in flight (a device batch descriptor maps
+// workgroups to solves; the graph is captured again when the batch changes). A finished solve
+// frees its slot and workspace when its chunk is read back, where new requests can be admitted
+// if a slot and the HBM budget allow.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -175,8 +175,8 @@ int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream
 int launch_finish(const Work* wd, double* u_out, double* v_out, void* stream);
 // FP16 copy of a dense FP32 (src_dtype MDOT_DT_F32) or FP64 cost; part[b] = max |C16 - C| of block b.
 int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, double* part, int nblocks, void* stream);
-// Batched step over a BatchDesc in device memory (cost type cost_code for every item), with
-// fixed grids (grid-stride over the descriptor), and a gather of the items' done flags.
+// Batched step over a BatchDesc in device memory (cost type cost_code for every item):
+// sweep_grid = total_tiles and fin_grid = total_fin workgroups of the descriptor.
 int cost_code_of(int cost_kind, int dtype);
 // big: some problem in flight has n > 8192 (the finalize instance for fin_per(n) = 32)
 int launch_step_batch(int cost_code, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, bool big,
