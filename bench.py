@@ -182,6 +182,20 @@ def bench_grid(args) -> dict:
         results.append(res)
     torch.cuda.synchronize()
     mean_s = (time.perf_counter() - t_start) / args.steps
+    # FP16/BF16 storage certifies the gap of the stored cost. Every plan's cost differs by at most
+    # delta = max |C_stored - C_exact| between the stored and the exact FP64 cost (total mass 1),
+    # so the returned plan is within gap + 2 delta of the exact problem's optimum.
+    error_vs_exact = None
+    if args.cost_storage in ("f16", "bf16"):
+        delta = {}
+        for kind, cd in costs.items():
+            exact = grid_cost_device(k, kind, "f64", dev)["keep"]
+            delta[kind] = float((cd["keep"].double() - exact).abs().max())
+            del exact
+        error_vs_exact = [{"problem": f"{probs[i % len(probs)]['family']}/{probs[i % len(probs)]['cost']}",
+                           "certified_gap_stored_cost": res.gap, "delta": delta[probs[i % len(probs)]["cost"]],
+                           "error_bound_exact_cost": res.gap + 2.0 * delta[probs[i % len(probs)]["cost"]]}
+                          for i, res in enumerate(results)]
 
     # roofline of the dominant kernel: the fused LSE sweep at the first problem's solution
     p0 = probs[0]
@@ -233,6 +247,9 @@ def bench_grid(args) -> dict:
         "lse_sweep_us": round(ms * 1e3, 3),
         "roofline": roof,
     }
+    if error_vs_exact is not None:
+        out["error_vs_exact_cost"] = error_vs_exact
+        out["error_bound_exact_cost_max"] = max(e["error_bound_exact_cost"] for e in error_vs_exact)
     if not args.no_cpu_baseline:
         big = n > 8192
         out["cpu_baseline"] = cpu_baseline(costs[p0["cost"]]["host64"](), p0, r0.sweeps, r0.stages,
