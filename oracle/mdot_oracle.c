@@ -32,7 +32,7 @@
  * index order. Independent rows (or columns) may run on different OpenMP threads;
  * that does not change any value.
  *
- * Readings where the paper is silent (also listed in the design doc):
+ * Readings where the paper is silent:
  *   - PNCG is called with tolerance eps_d/2 on the smoothed marginals (the inner solve of Alg. 1).
  *   - ||grad g||_1 = ||r(P) - r~||_1 + ||c(P) - c~||_1.
  *   - smoothing weight eps_d/4 is clamped at 1/2.
