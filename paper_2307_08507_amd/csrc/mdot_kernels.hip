@@ -414,21 +414,23 @@ __device__ __forceinline__ double fma_sc(double a, double x, double c)
     return r;
 }
 
-// 2^x in FP64 for the sweeps' exponent arguments. x is clamped to [-1023, 1000], split as
+// 2^x in FP64 for the sweeps' exponent arguments. x is clamped to [-1022, 1000], split as
 // x = k + f with k = round-to-nearest(x) by the 1.5 * 2^52 shift (its low word is k) and
 // |f| <= 1/2; 2^f = 1 + f q(f) with q of degree 9, a weighted least-squares fit driven to equal
-// ripple (relative error below 4e-16 in exact arithmetic, a few ulp after Horner rounding);
-// 2^k is written into the exponent field. At the clamp -1023 that field is 0 and the result is
-// exactly 0, so x = -inf gives 0; x below -1022.5 is flushed to 0, which every caller meets only
-// beside terms of order 1. No range branches: 19 VALU operations.
-__device__ __forceinline__ double exp2_f64(double x)
+// ripple (relative error below 4e-16 in exact arithmetic, a few ulp after Horner rounding).
+// 2^f lies in [0.707, 1.414], so 2^k is applied by adding k to its exponent field: exact for
+// normal results, and at the clamp -1022 (which x = -inf meets) the result is a positive
+// subnormal or 2^-1022, below any sum the sweeps accept. No range branches: 16 VALU
+// operations. c9 is q's leading coefficient (kExp2C9), which the caller keeps in a VGPR.
+constexpr double kExp2C9 = 0x1.e3a9131404cdep-28;
+__device__ __forceinline__ double exp2_f64(double x, double c9)
 {
     constexpr double kShift = 0x1.8p52;
-    x = fmin(fmax(x, -1023.0), 1000.0);
+    x = fmin(fmax(x, -1022.0), 1000.0);
     const double y = x + kShift;
     const double f = x - (y - kShift);
-    const int k = (int)(uint32_t)__builtin_bit_cast(uint64_t, y);
-    double q = fma_sc(f, 0x1.e3a9131404cdep-28, 0x1.b671b6a900f80p-24);
+    const uint32_t k = (uint32_t)__builtin_bit_cast(uint64_t, y);
+    double q = fma_sc(f, c9, 0x1.b671b6a900f80p-24);
     q = fma_sc(q, f, 0x1.62c147a08947dp-20);
     q = fma_sc(q, f, 0x1.ffcb58c5cff22p-17);
     q = fma_sc(q, f, 0x1.4309126bff6b0p-13);
@@ -438,14 +440,58 @@ __device__ __forceinline__ double exp2_f64(double x)
     q = fma_sc(q, f, 0x1.ebfbdff82c431p-3);
     q = fma_sc(q, f, 0x1.62e42fefa3a12p-1);
     const double p = fma(q, f, 1.0);
-    const uint64_t scale = (uint64_t)((uint32_t)(k + 1023) << 20) << 32;
-    return p * __builtin_bit_cast(double, scale);
+    return __hiloint2double(__double2hiint(p) + (int)(k << 20), __double2loint(p));
+}
+
+// Four Horner steps q_k = q_k f_k + c of independent exponentials in one block (one SGPR
+// coefficient): the steps of the four chains stay interleaved, so no step waits on the one
+// before it.
+__device__ __forceinline__ void fma4_sc(double q[4], const double f[4], double c)
+{
+    double r0, r1, r2, r3;
+    asm("v_fma_f64 %0, %4, %8, %12\n\t"
+        "v_fma_f64 %1, %5, %9, %12\n\t"
+        "v_fma_f64 %2, %6, %10, %12\n\t"
+        "v_fma_f64 %3, %7, %11, %12"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+        : "v"(q[0]), "v"(q[1]), "v"(q[2]), "v"(q[3]), "v"(f[0]), "v"(f[1]), "v"(f[2]), "v"(f[3]), "s"(c));
+    q[0] = r0; q[1] = r1; q[2] = r2; q[3] = r3;
+}
+
+// exp2_f64 of four arguments at once (the same operations in the same order per value).
+__device__ __forceinline__ void exp2_f64x4(const double x[4], double e[4], double c9)
+{
+    constexpr double kShift = 0x1.8p52;
+    double f[4], q[4];
+    uint32_t k[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double xc = fmin(fmax(x[i], -1022.0), 1000.0);
+        const double y = xc + kShift;
+        f[i] = xc - (y - kShift);
+        k[i] = (uint32_t)__builtin_bit_cast(uint64_t, y);
+        q[i] = c9;
+    }
+    fma4_sc(q, f, 0x1.b671b6a900f80p-24);
+    fma4_sc(q, f, 0x1.62c147a08947dp-20);
+    fma4_sc(q, f, 0x1.ffcb58c5cff22p-17);
+    fma4_sc(q, f, 0x1.4309126bff6b0p-13);
+    fma4_sc(q, f, 0x1.5d87fe9b90bb4p-10);
+    fma4_sc(q, f, 0x1.3b2ab6fbd6d27p-7);
+    fma4_sc(q, f, 0x1.c6b08d703e16ap-5);
+    fma4_sc(q, f, 0x1.ebfbdff82c431p-3);
+    fma4_sc(q, f, 0x1.62e42fefa3a12p-1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double p = fma(q[i], f[i], 1.0);
+        e[i] = __hiloint2double(__double2hiint(p) + (int)(k[i] << 20), __double2loint(p));
+    }
 }
 
 template <bool E64>
 __device__ __forceinline__ double exp2_sel(double x)
 {
-    if constexpr (E64) return exp2_f64(x);
+    if constexpr (E64) return exp2_f64(x, kExp2C9);
     else return (double)__builtin_amdgcn_exp2f((float)x);
 }
 
@@ -716,6 +762,8 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
         if ((t.lane & 3) == 0 && rr < nrows) w.rowpart[(size_t)t.J * n + t.i0 + rbase + rr] = rs;
     } else {
         double rp[kRPW];
+        double c9 = kExp2C9;
+        asm volatile("" : "+v"(c9));  // one VGPR pair for the whole tile instead of a move per exp
 #pragma unroll
         for (int b = 0; b < kRPW; b += RB) {
             if (b > 0) {
@@ -751,8 +799,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
                     cost.args(raw[r0], g2, V, sA[rbase + r], xa);
                     const double wt = sWt[rbase + r];
                     double e[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) e[k] = exp2_f64(xa[k]);
+                    exp2_f64x4(xa, e, c9);
                     rp[r] = (e[0] + e[1]) + (e[2] + e[3]);
 #pragma unroll
                     for (int k = 0; k < 4; ++k) col64[k] = fma(wt, e[k], col64[k]);
