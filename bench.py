@@ -38,13 +38,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 # ALU roofline of the point-cost sweep (the cost is recomputed, nothing streams from HBM): the
-# chip issues 256 CUs x 4 SIMDs x 16 lanes of VALU work per clock at 2.4 GHz, and one element of
-# the FP32-exp loop takes about 11.6 lane-slots in the gfx950 code of its inner loop: 3 FP64 FMAs
-# and 1 FP64 add (the argument), 1 FP64->FP32 convert, 1 v_exp_f32 at quarter rate (4 slots),
-# 1.75 FP32 adds/FMAs (row and column sums) and 0.85 of per-row coordinate work.
+# chip issues 256 CUs x 4 SIMDs x 16 lanes of VALU work per clock at 2.4 GHz. The peak takes the
+# least work one element needs in this formulation, in lane-slots: d FP64 FMAs and one FP64 add
+# (the argument, with |x|^2 and |y|^2 folded into the row and column terms), one FP64->FP32
+# conversion, one v_exp_f32 at quarter rate (4 slots), one FP32 add (row sum) and one FP32 FMA
+# (column sum): 8 + d. The compiled loop issues about 12.2 slots per element for d <= 2 and 13.5
+# for d = 3 (per-row coordinate work, accumulator flushes, addressing).
 VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-POINT_SLOTS_PER_ELEMENT = 11.6
-POINTS_ALU_PEAK_GEXPS = VALU_LANE_SLOTS_PER_S / POINT_SLOTS_PER_ELEMENT / 1e9
+
+
+POINT_DIM = 2  # grid workloads recompute the cost from 2-D pixel coordinates
+
+
+def points_alu_peak_gexps(d: int) -> float:
+    return VALU_LANE_SLOTS_PER_S / (8 + d) / 1e9
+
+
 FAMILIES = ("uniform", "smooth", "blobs", "cauchy")
 COSTS = ("sqeuclid", "l1")
 BYTES = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}
@@ -77,7 +86,7 @@ def grid_cost_device(k: int, kind: str, storage: str, dev):
     if storage == "points":
         XY = torch.cat([X, X]).float().contiguous()
         n = k * k
-        return {"desc": lambda: M.point_cost(XY, n, 2, kind, scale=1.0 / mx), "keep": XY,
+        return {"desc": lambda: M.point_cost(XY, n, POINT_DIM, kind, scale=1.0 / mx), "keep": XY,
                 "host64": lambda: _grid_num(X, kind).div_(mx).cpu().numpy()}
     dt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16, "f64": torch.float64}[storage]
     C = _grid_num(X, kind).div_(mx).to(dt).contiguous()
@@ -203,7 +212,7 @@ def bench_grid(args) -> dict:
     sweep_prec = "f64" if args.precision == "f64" else "f32"  # MIXED finishes on the exact cost in F32
     ms = ctx.bench_sweep(costs[p0["cost"]]["desc"](), u, v, r0.gamma_final, precision=sweep_prec, iters=200)
     if args.cost_storage == "points":
-        bound, unit, peak = "alu", "Gexp/s", round(POINTS_ALU_PEAK_GEXPS, 1)
+        bound, unit, peak = "alu", "Gexp/s", round(points_alu_peak_gexps(POINT_DIM), 1)
         achieved = n * n / (ms * 1e-3) / 1e9
         per_launch = {"elements_per_launch": n * n}
     else:

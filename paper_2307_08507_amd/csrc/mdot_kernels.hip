@@ -236,13 +236,16 @@ struct DenseCost {
 // Point clouds: raw C_ij = sum_k (x_ik - y_jk)^2 (KIND 1) or sum_k |x_ik - y_jk| (KIND 2),
 // evaluated in FP64 from FP32 coordinates (d <= 3). In the LSE tile the rows' coordinates are
 // the same for every lane: row_setup() puts them in LDS once and "Raw" is just the tile row.
-template <int KIND>
+// D is the number of coordinates the arithmetic carries: D = 3 serves every d <= 3; D = 2
+// (planar clouds, d <= 2) leaves out the third coordinate's operations. Coordinates past d are
+// zero in both, so every term D = 2 leaves out is an exact zero and the results are identical.
+template <int KIND, int D = 3>
 struct PointCost {
     using Raw = int;
     const float* X;
     const float* Y;
     int n, d, i0;
-    double y[4][3];
+    double y[4][D];
     const float4* sX;
     __device__ __forceinline__ PointCost(const Work& w, int i0_)
         : X((const float*)w.cost), Y((const float*)w.cost + (size_t)w.n * w.d), n(w.n), d(w.d), i0(i0_) {}
@@ -251,7 +254,7 @@ struct PointCost {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int e = 0; e < 3; ++e) y[k][e] = (j0 + k < n && e < d) ? (double)Y[(size_t)(j0 + k) * d + e] : 0.0;
+            for (int e = 0; e < D; ++e) y[k][e] = (j0 + k < n && e < d) ? (double)Y[(size_t)(j0 + k) * d + e] : 0.0;
     }
     __device__ __forceinline__ float4 xrow(int r) const
     {
@@ -259,7 +262,7 @@ struct PointCost {
         float4 v;
         v.x = (i < n) ? X[(size_t)i * d] : 0.f;
         v.y = (i < n && d > 1) ? X[(size_t)i * d + 1] : 0.f;
-        v.z = (i < n && d > 2) ? X[(size_t)i * d + 2] : 0.f;
+        v.z = (D > 2 && i < n && d > 2) ? X[(size_t)i * d + 2] : 0.f;
         v.w = 0.f;
         return v;
     }
@@ -270,7 +273,7 @@ struct PointCost {
         for (int k = 0; k < 4; ++k) {
             double s = 0.0;
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
+            for (int e = 0; e < D; ++e) {
                 double t = xs[e] - y[k][e];
                 s = (KIND == 1) ? fma(t, t, s) : s + fabs(t);
             }
@@ -288,7 +291,7 @@ struct PointCost {
         ((float4*)sX)[r] = v;
         if (KIND == 1 && i < n) {
             const double x0 = v.x, x1 = v.y, x2 = v.z;
-            a = fma(-g2, fma(x0, x0, fma(x1, x1, x2 * x2)), a);
+            a = fma(-g2, fma(x0, x0, fma(x1, x1, D > 2 ? x2 * x2 : 0.0)), a);
         }
     }
     // LSE exponent arguments, as DenseCost::args. For squared distances the expansion
@@ -301,10 +304,11 @@ struct PointCost {
         if constexpr (KIND == 1) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const double yy = fma(y[k][0], y[k][0], fma(y[k][1], y[k][1], y[k][2] * y[k][2]));
+                const double y2 = D > 2 ? y[k][D - 1] * y[k][D - 1] : 0.0;
+                const double yy = fma(y[k][0], y[k][0], fma(y[k][1], y[k][1], y2));
                 W[k] = fma(-g2, yy, V[k]);
 #pragma unroll
-                for (int e = 0; e < 3; ++e) y[k][e] *= 2.0 * g2;
+                for (int e = 0; e < D; ++e) y[k][e] *= 2.0 * g2;
             }
         }
     }
@@ -314,7 +318,10 @@ struct PointCost {
         if constexpr (KIND == 1) {
             const double x0 = xr.x, x1 = xr.y, x2 = xr.z;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) x[k] = fma(x0, y[k][0], fma(x1, y[k][1], fma(x2, y[k][2], W[k] + A)));
+            for (int k = 0; k < 4; ++k) {
+                const double b = W[k] + A;
+                x[k] = fma(x0, y[k][0], fma(x1, y[k][1], D > 2 ? fma(x2, y[k][D - 1], b) : b));
+            }
         } else {
             double c[4];
             decode(xr, c);
@@ -1427,7 +1434,10 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
 
 // ------------------------------------------------------------------ the sweep kernel
 // Cost types of a kernel instance (one per stored dtype / point metric).
-enum CostCode { CC_F64 = 0, CC_F32 = 1, CC_F16 = 2, CC_BF16 = 3, CC_PTS_SQ = 4, CC_PTS_L1 = 5 };
+// CC_PTS_SQ2 / CC_PTS_L12 are the planar (d <= 2) point instances. Only single-problem launches
+// take them; their results are identical to the general instances', which the engine runs.
+enum CostCode { CC_F64 = 0, CC_F32 = 1, CC_F16 = 2, CC_BF16 = 3, CC_PTS_SQ = 4, CC_PTS_L1 = 5, CC_PTS_SQ2 = 6,
+                CC_PTS_L12 = 7 };
 template <int CC> struct CostOf;
 template <> struct CostOf<CC_F64> { using T = DenseCost<MDOT_DT_F64>; };
 template <> struct CostOf<CC_F32> { using T = DenseCost<MDOT_DT_F32>; };
@@ -1435,6 +1445,8 @@ template <> struct CostOf<CC_F16> { using T = DenseCost<MDOT_DT_F16>; };
 template <> struct CostOf<CC_BF16> { using T = DenseCost<MDOT_DT_BF16>; };
 template <> struct CostOf<CC_PTS_SQ> { using T = PointCost<1>; };
 template <> struct CostOf<CC_PTS_L1> { using T = PointCost<2>; };
+template <> struct CostOf<CC_PTS_SQ2> { using T = PointCost<1, 2>; };
+template <> struct CostOf<CC_PTS_L12> { using T = PointCost<2, 2>; };
 
 template <int CC, bool E64, bool ROUND>
 __device__ __forceinline__ void sweep_tiles(const Work& w, const SweepArgs& a, const TileCtx& t, int mode, double* smem)
@@ -1988,7 +2000,14 @@ int cost_code_of(int cost_kind, int dtype)
     }
 }
 
-static int cost_code(const Work& w) { return cost_code_of(w.cost_kind, w.dtype); }
+// Kernel instance of a single-problem launch: planar point clouds take the planar instance.
+static int cost_code(const Work& w)
+{
+    const int cc = cost_code_of(w.cost_kind, w.dtype);
+    if (w.d <= 2 && cc == CC_PTS_SQ) return CC_PTS_SQ2;
+    if (w.d <= 2 && cc == CC_PTS_L1) return CC_PTS_L12;
+    return cc;
+}
 
 #define MDOT_CC_SWITCH(cc, F)         \
     switch (cc) {                     \
@@ -1999,13 +2018,19 @@ static int cost_code(const Work& w) { return cost_code_of(w.cost_kind, w.dtype);
         case CC_PTS_SQ: F(CC_PTS_SQ); break; \
         default: F(CC_PTS_L1); break;        \
     }
+#define MDOT_CC_SWITCH_SOLO(cc, F)                 \
+    switch (cc) {                                  \
+        case CC_PTS_SQ2: F(CC_PTS_SQ2); break;     \
+        case CC_PTS_L12: F(CC_PTS_L12); break;     \
+        default: MDOT_CC_SWITCH(cc, F) break;      \
+    }
 
 int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     const int tiles = hw.nrt * hw.nct;
 #define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity)
-    MDOT_CC_SWITCH(cost_code(hw), L_)
+    MDOT_CC_SWITCH_SOLO(cost_code(hw), L_)
 #undef L_
     if (hw.fin_per > 8) hipLaunchKernelGGL(k_fin<true>, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
     else hipLaunchKernelGGL(k_fin<false>, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
@@ -2017,7 +2042,7 @@ int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream)
 {
     const int tiles = hw.nrt * hw.nct;
 #define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, parity)
-    MDOT_CC_SWITCH(cost_code(hw), L_)
+    MDOT_CC_SWITCH_SOLO(cost_code(hw), L_)
 #undef L_
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -2062,7 +2087,7 @@ int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream
 {
     const int tiles = hw.nrt * hw.nct;
 #define L_(CC) hipLaunchKernelGGL(k_cost_range<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, part)
-    MDOT_CC_SWITCH(cost_code(hw), L_)
+    MDOT_CC_SWITCH_SOLO(cost_code(hw), L_)
 #undef L_
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -80,7 +80,8 @@ def _points(n, d, seed, kind):
     return XY, raw * scale, scale
 
 
-@pytest.mark.parametrize("n,d,kind", [(300, 3, "sqeuclid"), (512, 2, "l1"), (257, 1, "sqeuclid")])
+@pytest.mark.parametrize("n,d,kind", [(300, 3, "sqeuclid"), (600, 2, "sqeuclid"), (512, 2, "l1"),
+                                      (257, 1, "sqeuclid")])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_lse2_point_costs(ctx, n, d, kind, prec):
     print(f"lse2 points n={n} d={d} {kind} prec={prec}", flush=True)
@@ -92,6 +93,24 @@ def test_lse2_point_costs(ctx, n, d, kind, prec):
     tol = 1e-11 * gamma if prec == "f64" else 2e-6
     np.testing.assert_allclose(lr, lr_o, rtol=0, atol=tol)
     np.testing.assert_allclose(lc, lc_o, rtol=0, atol=tol)
+
+
+@pytest.mark.parametrize("kind", ["sqeuclid", "l1"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_planar_points_match_padded_3d(ctx, kind, prec):
+    # Clouds with d <= 2 take a kernel instance without the third coordinate's arithmetic. The
+    # same points with an explicit zero third coordinate take the general one; every term the
+    # planar instance leaves out is an exact zero, so the sweeps must agree bit for bit.
+    n = 700
+    print(f"planar vs padded points n={n} {kind} prec={prec}", flush=True)
+    XY2, C64, scale = _points(n, 2, 31, kind)
+    XY3 = torch.cat([XY2.view(2 * n, 2), torch.zeros(2 * n, 1, device="cuda")], 1).contiguous().view(-1)
+    gamma = 300.0
+    u, v = _potentials(n, 4, C64, gamma)
+    lr2, lc2 = _lse2(ctx, M.point_cost(XY2, n, 2, kind, scale=scale), u, v, gamma, prec)
+    lr3, lc3 = _lse2(ctx, M.point_cost(XY3, n, 3, kind, scale=scale), u, v, gamma, prec)
+    np.testing.assert_array_equal(lr2, lr3)
+    np.testing.assert_array_equal(lc2, lc3)
 
 
 def test_point_cost_default_scale(ctx):
