@@ -168,16 +168,16 @@ int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* 
 
 /* ---- Serving: continuous batching ----
  * A context keeps up to 64 solves in flight. Each engine step advances every admitted solve by
- * one solver step (one sweep each) in shared kernel launches; a solve that finishes frees its
- * slot and workspace at the next chunk boundary (8 steps), where further requests can be
- * admitted. Every solve in flight on one context must use the same cost kind and dtype. Each
+ * one solver step (one sweep each) in shared kernel launches, in chunks of 16 steps; a solve
+ * that finishes frees its slot and workspace when its chunk is read back (see mdot_run), where
+ * further requests can be admitted. Every solve in flight on one context must use the same cost kind and dtype. Each
  * solve's arithmetic is independent of the others in flight (own workspace, state and
  * fixed-order reductions), so its result is the same alone and in any mix.
  *
  * mdot_submit: admit one solve (arguments as mdot_solve). The inputs and u_out/v_out are
  * borrowed until mdot_poll reports the ticket done. Returns MDOT_OK with *ticket set,
  * MDOT_E_BUSY when no slot is free or the context's HBM budget (hbm_budget_bytes of
- * mdot_ctx_create; workspace of n ~ 27 n^2 / 64 + 200 n bytes) would be exceeded -- retry after
+ * mdot_ctx_create; workspace of n ~ 17 n^2 / 32 + 200 n bytes) would be exceeded -- retry after
  * mdot_run -- or an error (intake validation as in mdot_solve). Synchronous intake. */
 int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c,
                 double target_gap, const mdot_params* params, double* u_out, double* v_out,
