@@ -87,6 +87,7 @@ struct mdot_ctx {
     int bgraph_tiles = -1, bgraph_fin = -1;  // grids the batch graph was captured with
     bool bgraph_big = false;                 // ... and whether a problem has n > 8192
     bool batch_big = false;
+    bool batch_planar = false;  // every problem in flight is a planar (d <= 2) point cloud or dense
     // engine chunks in flight: the next chunk is launched before the previous one's done flags
     // are read; each remembers the slots and tickets it advanced, in descriptor order
     hipEvent_t eng_ev[2] = {nullptr, nullptr};
@@ -521,7 +522,11 @@ static int rebuild_batch(mdot_ctx* ctx)
     B.fin_prefix[m] = nf;
     B.total_fin = nf;
     ctx->batch_big = false;
-    for (int a = 0; a < m; ++a) ctx->batch_big |= hw[a]->fin_per > 8;
+    ctx->batch_planar = m > 0;
+    for (int a = 0; a < m; ++a) {
+        ctx->batch_big |= hw[a]->fin_per > 8;
+        ctx->batch_planar &= hw[a]->d <= 2;
+    }
     // sweep groups: items with the same cost data, size and kind, in order of first appearance
     bool taken[kMaxBatch] = {};
     int ng = 0, ne = 0, nt = 0;
@@ -974,7 +979,8 @@ int mdot_run(mdot_ctx* ctx, int steps, int* n_done)
                 rc = rebuild_batch(ctx);
                 if (rc) return rc;
             }
-            rc = ensure_batch_graph(ctx, ctx->engine_cc);
+            // a batch of planar clouds runs the planar point instance (identical results)
+            rc = ensure_batch_graph(ctx, ctx->batch_planar ? cost_code_planar(ctx->engine_cc) : ctx->engine_cc);
             if (rc) return rc;
             const int buf = ctx->eng_next;
             int m = 0;

@@ -178,6 +178,8 @@ int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, doubl
 // Batched step over a BatchDesc in device memory (cost type cost_code for every item):
 // sweep_grid = total_tiles and fin_grid = total_fin workgroups of the descriptor.
 int cost_code_of(int cost_kind, int dtype);
+// The planar (d <= 2) instance of a point cost code; other codes are returned unchanged.
+int cost_code_planar(int cost_code);
 // big: some problem in flight has n > 8192 (the finalize instance for fin_per(n) = 32)
 int launch_step_batch(int cost_code, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, bool big,
                       void* stream);

@@ -1434,8 +1434,9 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
 
 // ------------------------------------------------------------------ the sweep kernel
 // Cost types of a kernel instance (one per stored dtype / point metric).
-// CC_PTS_SQ2 / CC_PTS_L12 are the planar (d <= 2) point instances. Only single-problem launches
-// take them; their results are identical to the general instances', which the engine runs.
+// CC_PTS_SQ2 / CC_PTS_L12 are the planar (d <= 2) point instances: single-problem launches of
+// planar clouds take them, and so does the engine when every problem in flight is planar. Their
+// results are identical to the general instances'.
 enum CostCode { CC_F64 = 0, CC_F32 = 1, CC_F16 = 2, CC_BF16 = 3, CC_PTS_SQ = 4, CC_PTS_L1 = 5, CC_PTS_SQ2 = 6,
                 CC_PTS_L12 = 7 };
 template <int CC> struct CostOf;
@@ -2000,13 +2001,18 @@ int cost_code_of(int cost_kind, int dtype)
     }
 }
 
+int cost_code_planar(int cc)
+{
+    if (cc == CC_PTS_SQ) return CC_PTS_SQ2;
+    if (cc == CC_PTS_L1) return CC_PTS_L12;
+    return cc;
+}
+
 // Kernel instance of a single-problem launch: planar point clouds take the planar instance.
 static int cost_code(const Work& w)
 {
     const int cc = cost_code_of(w.cost_kind, w.dtype);
-    if (w.d <= 2 && cc == CC_PTS_SQ) return CC_PTS_SQ2;
-    if (w.d <= 2 && cc == CC_PTS_L1) return CC_PTS_L12;
-    return cc;
+    return w.d <= 2 ? cost_code_planar(cc) : cc;
 }
 
 #define MDOT_CC_SWITCH(cc, F)         \
@@ -2016,13 +2022,9 @@ static int cost_code(const Work& w)
         case CC_F16: F(CC_F16); break;       \
         case CC_BF16: F(CC_BF16); break;     \
         case CC_PTS_SQ: F(CC_PTS_SQ); break; \
+        case CC_PTS_SQ2: F(CC_PTS_SQ2); break; \
+        case CC_PTS_L12: F(CC_PTS_L12); break; \
         default: F(CC_PTS_L1); break;        \
-    }
-#define MDOT_CC_SWITCH_SOLO(cc, F)                 \
-    switch (cc) {                                  \
-        case CC_PTS_SQ2: F(CC_PTS_SQ2); break;     \
-        case CC_PTS_L12: F(CC_PTS_L12); break;     \
-        default: MDOT_CC_SWITCH(cc, F) break;      \
     }
 
 int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
@@ -2030,7 +2032,7 @@ int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
     hipStream_t s = (hipStream_t)stream;
     const int tiles = hw.nrt * hw.nct;
 #define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity)
-    MDOT_CC_SWITCH_SOLO(cost_code(hw), L_)
+    MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
     if (hw.fin_per > 8) hipLaunchKernelGGL(k_fin<true>, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
     else hipLaunchKernelGGL(k_fin<false>, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
@@ -2042,7 +2044,7 @@ int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream)
 {
     const int tiles = hw.nrt * hw.nct;
 #define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, parity)
-    MDOT_CC_SWITCH_SOLO(cost_code(hw), L_)
+    MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -2087,7 +2089,7 @@ int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream
 {
     const int tiles = hw.nrt * hw.nct;
 #define L_(CC) hipLaunchKernelGGL(k_cost_range<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, part)
-    MDOT_CC_SWITCH_SOLO(cost_code(hw), L_)
+    MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

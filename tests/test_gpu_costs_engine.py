@@ -207,6 +207,49 @@ def test_engine_bitwise_equals_solve(ctx, prec):
         eng.close()
 
 
+@pytest.mark.parametrize("mix", ["planar", "mixed"])
+def test_engine_point_clouds_bitwise_equals_solve(ctx, mix):
+    # A batch of planar clouds runs the planar point instance; a batch that also holds a d = 3
+    # cloud runs the general one for every problem. Solves alone take the instance of their own
+    # d, so the mixed batch compares the two instances over whole solves.
+    dims = [2, 2, 2] if mix == "planar" else [2, 3, 2]
+    print(f"engine point clouds {mix} d={dims}", flush=True)
+    probs = []
+    for j, (n, d) in enumerate(zip([300, 520, 260], dims)):
+        XY, _, scale = _points(n, d, 40 + j, "sqeuclid")
+        probs.append((M.point_cost(XY, n, d, "sqeuclid", scale=scale), XY, dev(W.dirichlet_marginal(n, 2 * j + 1)),
+                      dev(W.dirichlet_marginal(n, 2 * j + 2))))
+    prm = M.default_params(precision="f32")
+    alone = []
+    for cost, _, r, c in probs:
+        u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+        res = ctx.solve(cost, r, c, 1e-5, prm, u, v)
+        assert res.status == 0 and res.gap <= 1e-5
+        alone.append((res, u.cpu(), v.cpu()))
+    eng = M.Context(0)
+    try:
+        tickets, outs = [], []
+        for cost, _, r, c in probs:
+            u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+            v = torch.empty_like(u)
+            tickets.append(eng.submit(cost, r, c, 1e-5, prm, u, v))
+            outs.append((u, v))
+        assert all(t is not None for t in tickets)
+        for _ in range(100000):
+            if eng.inflight()[0] == 0:
+                break
+            eng.run(64)
+        assert eng.inflight() == (0, 0)
+        for t, (u, v), (ra, ua, va) in zip(tickets, outs, alone):
+            rb = eng.poll(t)
+            assert torch.equal(u.cpu(), ua) and torch.equal(v.cpu(), va)
+            for f in ("status", "primal_cost", "dual_bound", "gap", "sweeps"):
+                assert getattr(rb, f) == getattr(ra, f), f
+    finally:
+        eng.close()
+
+
 @pytest.mark.parametrize("k", [16, 33])
 def test_engine_shared_cost_groups(ctx, k):
     # problems that share a cost sweep their tiles interleaved (one group per cost); every
