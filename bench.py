@@ -290,32 +290,23 @@ def bench_grid_batched(args) -> dict:
     prm = M.default_params(precision=args.precision)
     eng = M.Context(0)
 
-    # The engine holds one cost kind at a time. Dense L1 and squared-Euclidean costs are both
-    # dense FP32 (one batch); the two point-cost kinds are not, so they run as consecutive batches.
-    if args.cost_storage == "points":
-        groups = [[i for i, p in enumerate(probs) if p["cost"] == kind] for kind in sorted(costs)]
-    else:
-        groups = [list(range(len(probs)))]
-
     def batch():
         t0 = time.perf_counter()
         res, lat = [None] * len(probs), [0.0] * len(probs)
-        for grp in groups:
-            tickets = {}
-            for i in grp:
-                p = probs[i]
-                t = eng.submit(costs[p["cost"]]["desc"](), p["rd"], p["cd"], args.target, prm, p["u"], p["v"])
-                if t is None:
-                    raise RuntimeError("the engine did not admit the whole batch")
-                tickets[i] = t
-            while tickets:
-                eng.run(8)
-                for i, t in list(tickets.items()):
-                    r = eng.poll(t)
-                    if r is not None:
-                        res[i] = r
-                        lat[i] = time.perf_counter() - t0
-                        del tickets[i]
+        tickets = {}
+        for i, p in enumerate(probs):
+            t = eng.submit(costs[p["cost"]]["desc"](), p["rd"], p["cd"], args.target, prm, p["u"], p["v"])
+            if t is None:
+                raise RuntimeError("the engine did not admit the whole batch")
+            tickets[i] = t
+        while tickets:
+            eng.run(8)
+            for i, t in list(tickets.items()):
+                r = eng.poll(t)
+                if r is not None:
+                    res[i] = r
+                    lat[i] = time.perf_counter() - t0
+                    del tickets[i]
         torch.cuda.synchronize()
         return time.perf_counter() - t0, res, lat
 
@@ -352,9 +343,7 @@ def bench_grid_batched(args) -> dict:
         "config": {
             "workload": (f"n={n} ({k}x{k} grid), {args.cost_storage} cost, {len(probs)} problems "
                          f"({'/'.join(sorted(costs))} x {{{', '.join(sorted({p['family'] for p in probs}))}}} "
-                         f"marginals) submitted together to the batched engine"
-                         f"{' (one batch per point-cost kind, one after the other)' if len(groups) > 1 else ''}"
-                         f", certified gap {args.target:g}"),
+                         f"marginals) submitted together to the batched engine, certified gap {args.target:g}"),
             "n": n,
             "target_gap": args.target,
             "problems": len(probs),

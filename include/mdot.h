@@ -170,9 +170,11 @@ int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* 
  * A context keeps up to 64 solves in flight. Each engine step advances every admitted solve by
  * one solver step (one sweep each) in shared kernel launches, in chunks of 16 steps; a solve
  * that finishes frees its slot and workspace when its chunk is read back (see mdot_run), where
- * further requests can be admitted. Every solve in flight on one context must use the same cost kind and dtype. Each
- * solve's arithmetic is independent of the others in flight (own workspace, state and
- * fixed-order reductions), so its result is the same alone and in any mix.
+ * further requests can be admitted. Solves of any cost kinds and dtypes can be in flight
+ * together: a step launches one sweep kernel per cost type present (and one finalize and one
+ * decision kernel for all). Each solve's arithmetic is independent of the others in flight
+ * (own workspace, state and fixed-order reductions), so its result is the same alone and in
+ * any mix.
  *
  * mdot_submit: admit one solve (arguments as mdot_solve). The inputs and u_out/v_out are
  * borrowed until mdot_poll reports the ticket done. Returns MDOT_OK with *ticket set,

@@ -81,13 +81,13 @@ struct mdot_ctx {
     BatchDesc* h_batch = nullptr;   // pinned
     BatchDesc* d_batch = nullptr;
     bool batch_dirty = true;
-    int engine_cc = -1;
     hipGraphExec_t bgraph = nullptr;
-    int bgraph_cc = -1;
-    int bgraph_tiles = -1, bgraph_fin = -1;  // grids the batch graph was captured with
-    bool bgraph_big = false;                 // ... and whether a problem has n > 8192
+    // what the batch graph was captured with: its sweep instances and their tile ranges, the
+    // finalize grid, and whether a problem has n > 8192
+    int bgraph_ncodes = 0, bgraph_code[kMaxCodes] = {}, bgraph_begin[kMaxCodes + 1] = {};
+    int bgraph_fin = -1;
+    bool bgraph_big = false;
     bool batch_big = false;
-    bool batch_planar = false;  // every problem in flight is a planar (d <= 2) point cloud or dense
     // engine chunks in flight: the next chunk is launched before the previous one's done flags
     // are read; each remembers the slots and tickets it advanced, in descriptor order
     hipEvent_t eng_ev[2] = {nullptr, nullptr};
@@ -522,35 +522,54 @@ static int rebuild_batch(mdot_ctx* ctx)
     B.fin_prefix[m] = nf;
     B.total_fin = nf;
     ctx->batch_big = false;
-    ctx->batch_planar = m > 0;
-    for (int a = 0; a < m; ++a) {
-        ctx->batch_big |= hw[a]->fin_per > 8;
-        ctx->batch_planar &= hw[a]->d <= 2;
-    }
-    // sweep groups: items with the same cost data, size and kind, in order of first appearance
+    for (int a = 0; a < m; ++a) ctx->batch_big |= hw[a]->fin_per > 8;
+    // sweep groups: items with the same cost data, size, point dimension, kind and dtype, in
+    // order of first appearance; each needs one sweep kernel instance (planar for d <= 2 clouds)
     bool taken[kMaxBatch] = {};
-    int ng = 0, ne = 0, nt = 0;
+    int gfirst[kMaxBatch], gcode[kMaxBatch], ngr = 0;
     for (int a = 0; a < m; ++a) {
         if (taken[a]) continue;
-        B.grp_first[ng] = ne;
-        B.grp_prefix[ng] = nt;
-        int K = 0;
         for (int b = a; b < m; ++b) {
             const Work& x = *hw[a];
             const Work& y = *hw[b];
-            if (taken[b] || y.cost != x.cost || y.n != x.n || y.d != x.d || y.cost_kind != x.cost_kind ||
-                y.dtype != x.dtype)
-                continue;
-            taken[b] = true;
-            B.grp_items[ne++] = b;
-            ++K;
+            if (y.cost == x.cost && y.n == x.n && y.d == x.d && y.cost_kind == x.cost_kind && y.dtype == x.dtype)
+                taken[b] = true;
         }
-        const int T = hw[a]->nrt * hw[a]->nct;
-        B.grp_size[ng] = K;
-        B.grp_tiles[ng] = T;
-        nt += K * ((T + 7) / 8) * 8;
-        ++ng;
+        const int cc = cost_code_of(hw[a]->cost_kind, hw[a]->dtype);
+        gfirst[ngr] = a;
+        gcode[ngr++] = hw[a]->d <= 2 ? cost_code_planar(cc) : cc;
     }
+    // lay the groups out instance by instance (one sweep launch per instance present)
+    int ng = 0, ne = 0, nt = 0;
+    B.ncodes = 0;
+    for (int code = 0; code < kMaxCodes; ++code) {
+        bool any = false;
+        for (int q = 0; q < ngr; ++q) {
+            if (gcode[q] != code) continue;
+            if (!any) {
+                B.code[B.ncodes] = code;
+                B.code_begin[B.ncodes++] = nt;
+                any = true;
+            }
+            const Work& x = *hw[gfirst[q]];
+            B.grp_first[ng] = ne;
+            B.grp_prefix[ng] = nt;
+            int K = 0;
+            for (int b = gfirst[q]; b < m; ++b) {
+                const Work& y = *hw[b];
+                if (y.cost != x.cost || y.n != x.n || y.d != x.d || y.cost_kind != x.cost_kind || y.dtype != x.dtype)
+                    continue;
+                B.grp_items[ne++] = b;
+                ++K;
+            }
+            const int T = x.nrt * x.nct;
+            B.grp_size[ng] = K;
+            B.grp_tiles[ng] = T;
+            nt += K * ((T + 7) / 8) * 8;
+            ++ng;
+        }
+    }
+    B.code_begin[B.ncodes] = nt;
     B.ngroups = ng;
     B.grp_prefix[ng] = nt;
     B.total_tiles = nt;
@@ -561,15 +580,18 @@ static int rebuild_batch(mdot_ctx* ctx)
 }
 
 // The batch graph launches exactly one workgroup per tile and per finalize block of the
-// problems in flight, so it is captured again whenever the batch's totals change (admissions
-// and completions, between chunks).
-static int ensure_batch_graph(mdot_ctx* ctx, int cc)
+// problems in flight, one sweep launch per kernel instance, so it is captured again whenever
+// the instances, their tile ranges or the totals change (admissions and completions, between
+// chunks).
+static int ensure_batch_graph(mdot_ctx* ctx)
 {
-    const int tiles = std::max(1, ctx->h_batch->total_tiles), fin = std::max(1, ctx->h_batch->total_fin);
+    const BatchDesc& hb = *ctx->h_batch;
+    const int fin = std::max(1, hb.total_fin);
     const bool big = ctx->batch_big;
-    if (ctx->bgraph && ctx->bgraph_cc == cc && ctx->bgraph_tiles == tiles && ctx->bgraph_fin == fin &&
-        ctx->bgraph_big == big)
-        return MDOT_OK;
+    bool same = ctx->bgraph && ctx->bgraph_ncodes == hb.ncodes && ctx->bgraph_fin == fin && ctx->bgraph_big == big;
+    for (int c = 0; same && c < hb.ncodes; ++c)
+        same = ctx->bgraph_code[c] == hb.code[c] && ctx->bgraph_begin[c + 1] == hb.code_begin[c + 1];
+    if (same) return MDOT_OK;
     if (ctx->bgraph) {
         (void)hipGraphExecDestroy(ctx->bgraph);
         ctx->bgraph = nullptr;
@@ -579,7 +601,7 @@ static int ensure_batch_graph(mdot_ctx* ctx, int cc)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(cc, ctx->d_batch, k & 1, tiles, fin, big, cap);
+        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(hb, ctx->d_batch, k & 1, fin, big, cap);
         launch_gather_done(ctx->d_batch, ctx->d_hdone + 2, ctx->d_seq + 1, cap);
         e = hipStreamEndCapture(cap, &g);
     }
@@ -590,8 +612,11 @@ static int ensure_batch_graph(mdot_ctx* ctx, int cc)
         ctx->bgraph = nullptr;
         return fail(ctx, MDOT_E_DEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
     }
-    ctx->bgraph_cc = cc;
-    ctx->bgraph_tiles = tiles;
+    ctx->bgraph_ncodes = hb.ncodes;
+    for (int c = 0; c < hb.ncodes; ++c) {
+        ctx->bgraph_code[c] = hb.code[c];
+        ctx->bgraph_begin[c + 1] = hb.code_begin[c + 1];
+    }
     ctx->bgraph_fin = fin;
     ctx->bgraph_big = big;
     return MDOT_OK;
@@ -899,12 +924,8 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
     rc = check_params(ctx, prm, target_gap);
     if (rc) return rc;
     if (prm.precision == MDOT_PREC_MIXED) return fail(ctx, MDOT_E_ARG, "MIXED is available through mdot_solve only");
-    const int cc = cost_code_of(cost->kind, cost->dtype);
     int active = 0;
     for (const Slot& sl : ctx->slots) active += sl.used;
-    if (active == 0) ctx->engine_cc = cc;
-    if (cc != ctx->engine_cc)
-        return fail(ctx, MDOT_E_ARG, "every solve in flight must use the same cost kind and dtype");
     const size_t fp = problem_footprint(cost->n);
     if (ctx->budget && fp > ctx->budget)
         return fail(ctx, MDOT_E_NOMEM, "n=%d needs %zu bytes > budget %zu", cost->n, fp, ctx->budget);
@@ -979,8 +1000,7 @@ int mdot_run(mdot_ctx* ctx, int steps, int* n_done)
                 rc = rebuild_batch(ctx);
                 if (rc) return rc;
             }
-            // a batch of planar clouds runs the planar point instance (identical results)
-            rc = ensure_batch_graph(ctx, ctx->batch_planar ? cost_code_planar(ctx->engine_cc) : ctx->engine_cc);
+            rc = ensure_batch_graph(ctx);
             if (rc) return rc;
             const int buf = ctx->eng_next;
             int m = 0;

@@ -154,6 +154,7 @@ struct Control {
 // one cost tile land on the same XCD (workgroups go round-robin over the 8 XCDs) at nearly the
 // same time, so the cost is read from HBM once per group and from that XCD's L2 by the rest.
 constexpr int kMaxBatch = 64;
+constexpr int kMaxCodes = 8;  // sweep kernel instances (cost codes)
 struct BatchDesc {
     int32_t nitems, total_tiles, total_fin, ngroups;
     int32_t fin_prefix[kMaxBatch + 1];
@@ -163,6 +164,11 @@ struct BatchDesc {
     int32_t grp_tiles[kMaxBatch];  // T
     int32_t grp_items[kMaxBatch];  // item indices, group by group
     const Work* items[kMaxBatch];
+    // Groups are ordered by the sweep kernel instance they need (cost code, planar when d <= 2):
+    // instance code[c] sweeps the tiles [code_begin[c], code_begin[c + 1]).
+    int32_t ncodes;
+    int32_t code[kMaxCodes];
+    int32_t code_begin[kMaxCodes + 1];
 };
 
 // Host-side launchers (mdot_kernels.hip). `hw` is the host copy of the Work struct (sizes
@@ -175,14 +181,14 @@ int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream
 int launch_finish(const Work* wd, double* u_out, double* v_out, void* stream);
 // FP16 copy of a dense FP32 (src_dtype MDOT_DT_F32) or FP64 cost; part[b] = max |C16 - C| of block b.
 int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, double* part, int nblocks, void* stream);
-// Batched step over a BatchDesc in device memory (cost type cost_code for every item):
-// sweep_grid = total_tiles and fin_grid = total_fin workgroups of the descriptor.
+// Batched step over a BatchDesc in device memory: one sweep launch per kernel instance of the
+// host copy hb (instance hb.code[c] over its tile range), then fin_grid = total_fin finalize
+// workgroups and the decisions.
 int cost_code_of(int cost_kind, int dtype);
 // The planar (d <= 2) instance of a point cost code; other codes are returned unchanged.
 int cost_code_planar(int cost_code);
 // big: some problem in flight has n > 8192 (the finalize instance for fin_per(n) = 32)
-int launch_step_batch(int cost_code, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, bool big,
-                      void* stream);
+int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, bool big, void* stream);
 // End-of-chunk done flags into host-visible memory: chunk number *seq (a device counter, advanced
 // here) writes out[(seq & 1) * kMaxBatch + item] (batch) or out[seq & 1] (single problem).
 int launch_gather_done(const BatchDesc* bd, int* out, int* seq, void* stream);

@@ -1787,17 +1787,18 @@ __device__ __forceinline__ int batch_item(const int32_t* prefix, int nitems, int
     return lo;
 }
 
-// Batched sweep: one workgroup per tile of every problem in flight, tiles of problems that
-// share a cost interleaved so that they meet in one XCD's L2 (the engine launches exactly
-// total_tiles workgroups). Same register cap as the single-problem sweep; a grid-stride loop
-// here would keep the loop-invariant values of the tile code live across tiles and spill.
+// Batched sweep: one workgroup per tile of the problems in flight that need this kernel
+// instance (the descriptor's tiles [tile_begin, tile_end), launched exactly), tiles of problems
+// that share a cost interleaved so that they meet in one XCD's L2 (ranges start at multiples of
+// 8). Same register cap as the single-problem sweep; a grid-stride loop here would keep the
+// loop-invariant values of the tile code live across tiles and spill.
 template <int CC>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
-k_sweep_batch(const BatchDesc* __restrict__ bd, int parity)
+k_sweep_batch(const BatchDesc* __restrict__ bd, int parity, int tile_begin, int tile_end)
 {
     __shared__ double smem[kSmem];
-    const int g = blockIdx.x;
-    if (g >= bd->total_tiles) return;
+    const int g = tile_begin + (int)blockIdx.x;
+    if (g >= tile_end) return;
     const int q = batch_item(bd->grp_prefix, bd->ngroups, g);
     const int l = g - bd->grp_prefix[q];
     const int K = bd->grp_size[q], T = bd->grp_tiles[q];
@@ -2049,12 +2050,16 @@ int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_step_batch(int cc, const BatchDesc* bd, int parity, int sweep_grid, int fin_grid, bool big, void* stream)
+int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, bool big, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-#define L_(CC) hipLaunchKernelGGL(k_sweep_batch<CC>, dim3(sweep_grid), dim3(kWG), 0, s, bd, parity)
-    MDOT_CC_SWITCH(cc, L_)
+    for (int c = 0; c < hb.ncodes; ++c) {
+        const int b = hb.code_begin[c], e = hb.code_begin[c + 1];
+        if (e <= b) continue;
+#define L_(CC) hipLaunchKernelGGL(k_sweep_batch<CC>, dim3(e - b), dim3(kWG), 0, s, bd, parity, b, e)
+        MDOT_CC_SWITCH(hb.code[c], L_)
 #undef L_
+    }
     if (big) hipLaunchKernelGGL(k_fin_batch<true>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
     else hipLaunchKernelGGL(k_fin_batch<false>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
     hipLaunchKernelGGL(k_decide_batch, dim3(kMaxBatch), dim3(kDecideWG), 0, s, bd, parity);

@@ -209,9 +209,8 @@ def test_engine_bitwise_equals_solve(ctx, prec):
 
 @pytest.mark.parametrize("mix", ["planar", "mixed"])
 def test_engine_point_clouds_bitwise_equals_solve(ctx, mix):
-    # A batch of planar clouds runs the planar point instance; a batch that also holds a d = 3
-    # cloud runs the general one for every problem. Solves alone take the instance of their own
-    # d, so the mixed batch compares the two instances over whole solves.
+    # Planar clouds run the planar point instance, d = 3 clouds the general one: a mixed batch
+    # launches both sweeps in every step. Each result must equal its solve alone bit for bit.
     dims = [2, 2, 2] if mix == "planar" else [2, 3, 2]
     print(f"engine point clouds {mix} d={dims}", flush=True)
     probs = []
@@ -236,6 +235,53 @@ def test_engine_point_clouds_bitwise_equals_solve(ctx, mix):
             tickets.append(eng.submit(cost, r, c, 1e-5, prm, u, v))
             outs.append((u, v))
         assert all(t is not None for t in tickets)
+        for _ in range(100000):
+            if eng.inflight()[0] == 0:
+                break
+            eng.run(64)
+        assert eng.inflight() == (0, 0)
+        for t, (u, v), (ra, ua, va) in zip(tickets, outs, alone):
+            rb = eng.poll(t)
+            assert torch.equal(u.cpu(), ua) and torch.equal(v.cpu(), va)
+            for f in ("status", "primal_cost", "dual_bound", "gap", "sweeps"):
+                assert getattr(rb, f) == getattr(ra, f), f
+    finally:
+        eng.close()
+
+
+def test_engine_mixed_cost_types_bitwise_equals_solve(ctx):
+    # One batch holding every cost type: dense FP64 / FP32 / FP16 / BF16 and point clouds of
+    # both metrics, planar and not. Each step launches one sweep per type; finalize and decide
+    # are shared. Every result must equal the same solve alone bit for bit.
+    print("engine mixed cost types", flush=True)
+    probs = []
+    for k, cost, dt in [(14, "sqeuclid", torch.float64), (16, "l1", torch.float32), (18, "sqeuclid", torch.float16),
+                        (15, "l1", torch.bfloat16)]:
+        C, r, c = W.grid_problem(k, "blobs", cost, k)
+        Cd = dev(C, dt)
+        probs.append((M.dense_cost(Cd), Cd, dev(r), dev(c)))
+    for n, d, kind in [(300, 3, "sqeuclid"), (280, 2, "l1"), (260, 2, "sqeuclid")]:
+        XY, _, scale = _points(n, d, 60 + n, kind)
+        probs.append((M.point_cost(XY, n, d, kind, scale=scale), XY, dev(W.dirichlet_marginal(n, n)),
+                      dev(W.dirichlet_marginal(n, n + 1))))
+    prm = M.default_params(precision="f32")
+    alone = []
+    for cost, _, r, c in probs:
+        u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+        res = ctx.solve(cost, r, c, 1e-5, prm, u, v)
+        assert res.status == 0 and res.gap <= 1e-5
+        alone.append((res, u.cpu(), v.cpu()))
+    eng = M.Context(0)
+    try:
+        tickets, outs = [], []
+        for cost, _, r, c in probs:
+            u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+            v = torch.empty_like(u)
+            tickets.append(eng.submit(cost, r, c, 1e-5, prm, u, v))
+            outs.append((u, v))
+        assert all(t is not None for t in tickets)
+        assert eng.inflight()[0] == len(probs)
         for _ in range(100000):
             if eng.inflight()[0] == 0:
                 break
