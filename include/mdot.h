@@ -75,8 +75,10 @@ typedef enum { MDOT_DT_F64 = 0, MDOT_DT_F32 = 1, MDOT_DT_F16 = 2, MDOT_DT_BF16 =
  * the exact cost, and the certified gap refers to it. */
 typedef enum { MDOT_PREC_F64 = 0, MDOT_PREC_F32 = 1, MDOT_PREC_MIXED = 2 } mdot_precision;
 
+#define MDOT_MAX_N 65536 /* largest n; larger sizes return MDOT_E_ARG */
+
 typedef struct {
-    int32_t n;            /* problem size, >= 1 */
+    int32_t n;            /* problem size, 1..MDOT_MAX_N */
     int32_t d;            /* point dimension for POINTS_* (1..3), ignored for DENSE */
     mdot_cost_kind kind;
     mdot_dtype dtype;     /* DENSE only: element type of data (POINTS_* use FP32 coordinates) */

@@ -28,7 +28,7 @@ namespace {
 
 constexpr int kChunk = 32;       // solver steps per graph launch (even: the state slot alternates)
 constexpr int kBatchChunk = 16;  // engine steps per graph launch (admission granularity, even)
-constexpr int kMaxN = 65536;     // the finalize kernel keeps n / 64 tile shifts in LDS
+constexpr int kMaxN = MDOT_MAX_N;
 constexpr int kConvBlocks = 1024; // workgroups of the FP16 conversion (MIXED)
 
 // Device buffers of one problem: workspace, device copy of Work + 2 state slots, parameters.

@@ -8,6 +8,8 @@
   ragged last tiles) covers the other load path at scale.
 * Past n = 8192 (the finalize's other instance): point-cost sweeps at n = 12000 on sampled rows
   and columns, and an n = 9000 point-cost solve re-certified by the oracle.
+* The largest size (MDOT_MAX_N = 65536): point-cost sweeps in both precisions and a 16 GiB
+  stored FP32 cost, on sampled rows and columns; one more is rejected.
 * Degenerate cases with closed forms: n = 1, identical marginals on a cost with zero
   diagonal (OT = 0), and a separable cost C_ij = a_i + b_j (every plan costs <a, r> + <b, c>).
 
@@ -154,6 +156,75 @@ def test_lse2_large_n_points_sampled(ctx, prec):
     tol = 1e-12 * gamma if prec == "f64" else 2e-6
     np.testing.assert_allclose(lr.cpu().numpy()[rows], lr_o, rtol=0, atol=tol)
     np.testing.assert_allclose(lc.cpu().numpy()[cols], lc_o, rtol=0, atol=tol)
+
+
+MAX_N = 65536  # MDOT_MAX_N of include/mdot.h
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_lse2_max_n_points_sampled(ctx, prec):
+    # the largest size the library takes: 1024 x 256 tiles, partial arrays past 2^31 bytes in
+    # total, and the finalize's general path (more row tiles than its fast path holds)
+    from scipy.special import logsumexp
+
+    n, gamma, scale = MAX_N, 200.0, 0.5
+    print(f"max-n lse2 points n={n} prec={prec}", flush=True)
+    X, Y, _, _ = _points_problem(n, 81)
+    rng = np.random.default_rng(82)
+    u = rng.standard_normal(n) * 0.1
+    v = rng.standard_normal(n) * 0.1
+    XY = dev(np.concatenate([X, Y]).ravel(), torch.float32)
+    lr = torch.empty(n, dtype=torch.float64, device="cuda")
+    lc = torch.empty_like(lr)
+    assert ctx.lse2(M.point_cost(XY, n, 2, "sqeuclid", scale=scale), dev(u), dev(v), gamma, lr, lc,
+                    precision=prec) == 0
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([rng.choice(n, 24, replace=False), [0, n - 1]]))
+    cols = np.unique(np.concatenate([rng.choice(n, 24, replace=False), [0, n - 1]]))
+    lr_o = logsumexp(u[rows, None] + v[None, :] - gamma * _points_rows(X, Y, rows, scale, 0), axis=1)
+    lc_o = logsumexp(u[None, :] + v[cols, None] - gamma * _points_rows(X, Y, cols, scale, 1), axis=1)
+    tol = 1e-12 * gamma if prec == "f64" else 2e-6
+    np.testing.assert_allclose(lr.cpu().numpy()[rows], lr_o, rtol=0, atol=tol)
+    np.testing.assert_allclose(lc.cpu().numpy()[cols], lc_o, rtol=0, atol=tol)
+
+
+def test_lse2_max_n_dense_sampled(ctx):
+    # a stored FP32 cost at the largest size (16 GiB): row offsets past 2^32 bytes, each tile's
+    # buffer range clamped below 2 GiB. Seeded uniform costs; the sampled rows and columns are
+    # copied back as inputs and the log-sums formed from them by their definition.
+    from scipy.special import logsumexp
+
+    n, gamma = MAX_N, 50.0
+    print(f"max-n lse2 dense f32 n={n}", flush=True)
+    g = torch.Generator(device="cuda").manual_seed(83)
+    C = torch.rand((n, n), generator=g, device="cuda", dtype=torch.float32)
+    rng = np.random.default_rng(84)
+    u = rng.standard_normal(n) * 0.1 - np.log(n)
+    v = rng.standard_normal(n) * 0.1
+    lr = torch.empty(n, dtype=torch.float64, device="cuda")
+    lc = torch.empty_like(lr)
+    assert ctx.lse2(M.dense_cost(C), dev(u), dev(v), gamma, lr, lc, precision="f32") == 0
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([rng.choice(n, 16, replace=False), [0, n - 1]]))
+    cols = np.unique(np.concatenate([rng.choice(n, 16, replace=False), [0, n - 1]]))
+    Cr = C[torch.as_tensor(rows, device="cuda")].double().cpu().numpy()
+    Cc = C[:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy().T
+    del C
+    torch.cuda.empty_cache()
+    lr_o = logsumexp(u[rows, None] + v[None, :] - gamma * Cr, axis=1)
+    lc_o = logsumexp(u[None, :] + v[cols, None] - gamma * Cc, axis=1)
+    np.testing.assert_allclose(lr.cpu().numpy()[rows], lr_o, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(lc.cpu().numpy()[cols], lc_o, rtol=0, atol=2e-6)
+
+
+def test_size_past_max_rejected(ctx):
+    # a descriptor claiming MAX_N + 1 points over a small buffer: rejected before any access
+    XY = torch.zeros(16, dtype=torch.float32, device="cuda")
+    u = torch.zeros(4, dtype=torch.float64, device="cuda")
+    desc = M.CostDesc(n=MAX_N + 1, d=2, kind=M.COST_POINTS_SQEUCLID, dtype=0, data=XY.data_ptr(), scale=1.0)
+    with pytest.raises(M.MdotError) as e:
+        ctx.lse2(desc, u, u, 1.0, u, u)
+    assert e.value.code == -1
 
 
 def test_solve_large_n_points_recertified_by_oracle(ctx):
