@@ -67,7 +67,7 @@ typedef enum { MDOT_DT_F64 = 0, MDOT_DT_F32 = 1, MDOT_DT_F16 = 2, MDOT_DT_BF16 =
  * FP64 everything else (dual objective, marginals, dot products, line search, gap
  * certificate); rows or columns whose shifted sums fall outside the FP32 range are
  * re-evaluated in F64. Round and certificate sweeps always accumulate in FP64. */
-/* MIXED (mdot_solve with a DENSE FP32 or FP64 cost): the library keeps an FP16 copy of the cost
+/* MIXED (a DENSE FP32 or FP64 cost; mdot_solve or mdot_submit): the library keeps an FP16 copy of the cost
  * in its workspace and runs the early stages (F32 arithmetic) on that copy while
  * gamma * scale * delta <= mixed_switch, delta = max_ij |C16_ij - C_ij| (raw units); the
  * remaining stages run on the exact cost. Any potentials start the next stage (Prop. 1.2),
@@ -181,8 +181,10 @@ int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* 
  * mdot_submit: admit one solve (arguments as mdot_solve). The inputs and u_out/v_out are
  * borrowed until mdot_poll reports the ticket done. Returns MDOT_OK with *ticket set,
  * MDOT_E_BUSY when no slot is free or the context's HBM budget (hbm_budget_bytes of
- * mdot_ctx_create; workspace of n ~ 17 n^2 / 32 + 200 n bytes) would be exceeded -- retry after
- * mdot_run -- or an error (intake validation as in mdot_solve). Synchronous intake. */
+ * mdot_ctx_create; workspace of n ~ 17 n^2 / 32 + 200 n bytes, plus 2 n^2 for MIXED's FP16
+ * copy) would be exceeded -- retry after mdot_run -- or an error (intake validation as in
+ * mdot_solve). Synchronous intake. A MIXED solve switches to the exact cost at the chunk
+ * boundary after it reaches the switch point; its result equals mdot_solve's. */
 int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c,
                 double target_gap, const mdot_params* params, double* u_out, double* v_out,
                 uint64_t* ticket);

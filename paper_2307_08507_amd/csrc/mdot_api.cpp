@@ -50,6 +50,11 @@ struct Slot {
     double* u_out = nullptr;
     double* v_out = nullptr;
     size_t footprint = 0;
+    // MIXED: the exact cost and the marginals, bound again when the solve pauses at the switch
+    mdot_cost_desc exact{};
+    const double* r = nullptr;
+    const double* c = nullptr;
+    int64_t resumed_at = -1;  // engine chunks up to this sequence number ran the paused state
 };
 
 }  // namespace
@@ -93,6 +98,8 @@ struct mdot_ctx {
     hipEvent_t eng_ev[2] = {nullptr, nullptr};
     int eng_pending = -1;  // buffer of the launched chunk not yet read back, or -1
     int eng_next = 0;      // buffer of the next chunk
+    int64_t eng_seq = 0;              // engine chunks launched so far
+    int64_t chunk_seq[2] = {0, 0};    // sequence number of the chunk in each buffer
     int chunk_m[2] = {0, 0};
     int chunk_slot[2][kMaxBatch];
     uint64_t chunk_ticket[2][kMaxBatch];
@@ -923,10 +930,14 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
     else fill_defaults(&prm);
     rc = check_params(ctx, prm, target_gap);
     if (rc) return rc;
-    if (prm.precision == MDOT_PREC_MIXED) return fail(ctx, MDOT_E_ARG, "MIXED is available through mdot_solve only");
+    if (prm.precision == MDOT_PREC_MIXED &&
+        (cost->kind != MDOT_COST_DENSE || (cost->dtype != MDOT_DT_F32 && cost->dtype != MDOT_DT_F64)))
+        return fail(ctx, MDOT_E_ARG, "MIXED needs a dense FP32 or FP64 cost");
     int active = 0;
     for (const Slot& sl : ctx->slots) active += sl.used;
-    const size_t fp = problem_footprint(cost->n);
+    // MIXED also holds an FP16 copy of the cost
+    const size_t fp = problem_footprint(cost->n) +
+                      (prm.precision == MDOT_PREC_MIXED ? (size_t)cost->n * cost->n * 2 : 0);
     if (ctx->budget && fp > ctx->budget)
         return fail(ctx, MDOT_E_NOMEM, "n=%d needs %zu bytes > budget %zu", cost->n, fp, ctx->budget);
     if (active == kMaxBatch || (ctx->budget && ctx->bytes_in_use + fp > ctx->budget))
@@ -955,6 +966,10 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
     sl.u_out = u_out;
     sl.v_out = v_out;
     sl.footprint = fp;
+    sl.exact = *cost;
+    sl.r = r;
+    sl.c = c;
+    sl.resumed_at = -1;
     ctx->bytes_in_use += fp;
     ctx->batch_dirty = true;
     *ticket = sl.ticket;
@@ -970,6 +985,19 @@ static int process_chunk(mdot_ctx* ctx, int buf, int* completed)
     for (int m = 0; m < ctx->chunk_m[buf]; ++m) {
         Slot& sl = ctx->slots[ctx->chunk_slot[buf][m]];
         if (!done[m] || !sl.used || sl.ticket != ctx->chunk_ticket[buf][m]) continue;
+        if (done[m] == 2) {  // MIXED: paused at the switch to the exact cost
+            // the chunk launched before the resume below still reports the pause: skip it
+            if (ctx->chunk_seq[buf] <= sl.resumed_at) continue;
+            int rc = bind_work(ctx, sl.pb, sl.exact.n, &sl.exact, sl.pb.host_work.scale, sl.r, sl.c);
+            if (rc) return rc;
+            // chunks have an even number of steps, so the next step reads state slot 0
+            static const int32_t kResume = 0;
+            HIPCHK(ctx, hipMemcpyAsync(&sl.pb.host_work.st[0].done, &kResume, sizeof kResume, hipMemcpyHostToDevice,
+                                       ctx->stream));
+            sl.resumed_at = ctx->eng_seq;
+            ctx->batch_dirty = true;  // its sweep group now needs the exact cost's kernel instance
+            continue;
+        }
         if (launch_finish(sl.pb.d_work, sl.u_out, sl.v_out, ctx->stream))
             return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
         int rc = read_state(ctx, sl.pb);
@@ -1011,6 +1039,7 @@ int mdot_run(mdot_ctx* ctx, int steps, int* n_done)
                 ++m;
             }
             ctx->chunk_m[buf] = m;
+            ctx->chunk_seq[buf] = ++ctx->eng_seq;
             // the graph's last kernel writes this chunk's done flags to host buffer `buf` (engine
             // chunks alternate buffers in launch order, as the device counter does)
             HIPCHK(ctx, hipGraphLaunch(ctx->bgraph, ctx->stream));

@@ -421,9 +421,53 @@ def test_mixed_precision_rejected_where_unsupported(ctx):
     assert e.value.code == -1
     eng = M.Context(0)
     try:
-        C = dev(np.random.default_rng(0).random((n, n)), torch.float32)
         with pytest.raises(M.MdotError) as e:
-            eng.submit(M.dense_cost(C), r, r, 1e-4, M.default_params(precision="mixed"))
+            eng.submit(M.point_cost(XY, n, d, "sqeuclid", scale=scale), r, r, 1e-4, M.default_params(precision="mixed"))
         assert e.value.code == -1
+        C16 = dev(np.random.default_rng(0).random((n, n)), torch.float16)
+        with pytest.raises(M.MdotError) as e:
+            eng.submit(M.dense_cost(C16), r, r, 1e-4, M.default_params(precision="mixed"))
+        assert e.value.code == -1
+    finally:
+        eng.close()
+
+
+def test_engine_mixed_precision_bitwise_equals_solve(ctx):
+    # MIXED solves in the engine pause at the switch to the exact cost; the engine binds the
+    # exact cost at the next chunk boundary and the problem's sweeps move to the FP32 kernel
+    # instance. Alongside a plain FP32 solve, each result must equal its solve alone bit for bit.
+    print("engine MIXED", flush=True)
+    probs = []
+    for k, fam, cost, seed, prec in [(16, "blobs", "sqeuclid", 11, "mixed"), (20, "smooth", "l1", 12, "mixed"),
+                                     (18, "cauchy", "sqeuclid", 13, "f32"), (24, "uniform", "sqeuclid", 14, "mixed")]:
+        C, r, c = W.grid_problem(k, fam, cost, seed)
+        probs.append((dev(C, torch.float32), dev(r), dev(c), prec))
+    alone = []
+    for C, r, c, prec in probs:
+        u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+        res = ctx.solve(M.dense_cost(C), r, c, 1e-5, M.default_params(precision=prec), u, v)
+        assert res.status == 0 and res.gap <= 1e-5
+        assert (res.proxy_stages > 0) == (prec == "mixed")
+        alone.append((res, u.cpu(), v.cpu()))
+    eng = M.Context(0)
+    try:
+        tickets, outs = [], []
+        for C, r, c, prec in probs:
+            u = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+            v = torch.empty_like(u)
+            tickets.append(eng.submit(M.dense_cost(C), r, c, 1e-5, M.default_params(precision=prec), u, v))
+            outs.append((u, v))
+        assert all(t is not None for t in tickets)
+        for _ in range(100000):
+            if eng.inflight()[0] == 0:
+                break
+            eng.run(64)
+        assert eng.inflight() == (0, 0)
+        for t, (u, v), (ra, ua, va) in zip(tickets, outs, alone):
+            rb = eng.poll(t)
+            assert torch.equal(u.cpu(), ua) and torch.equal(v.cpu(), va)
+            for f in ("status", "primal_cost", "dual_bound", "gap", "sweeps", "stages", "proxy_stages"):
+                assert getattr(rb, f) == getattr(ra, f), f
     finally:
         eng.close()
