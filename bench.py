@@ -463,11 +463,8 @@ def main() -> int:
                     help="grid workload: submit the problems together to the batched engine")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU sharding is "
-              f"design-only in this build)", file=sys.stderr)
-        return 2
-    if args.batched and args.precision == "mixed":
-        print("--batched: the engine takes F32 and F64 solves (MIXED pauses to swap the cost)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on one GPU; "
+              f"row sharding across GPUs is a design, not an implementation)", file=sys.stderr)
         return 2
     if args.workload == "serving":
         out = bench_serving(args)
