@@ -543,8 +543,11 @@ static int rebuild_batch(mdot_ctx* ctx)
                 taken[b] = true;
         }
         const int cc = cost_code_of(hw[a]->cost_kind, hw[a]->dtype);
+        const int code = hw[a]->d <= 2 ? cost_code_planar(cc) : cc;
+        if (code < 0 || code >= kMaxCodes)  // every code must get a tile range below
+            return fail(ctx, MDOT_E_DEVICE, "cost code %d has no batched sweep range", code);
         gfirst[ngr] = a;
-        gcode[ngr++] = hw[a]->d <= 2 ? cost_code_planar(cc) : cc;
+        gcode[ngr++] = code;
     }
     // lay the groups out instance by instance (one sweep launch per instance present)
     int ng = 0, ne = 0, nt = 0;
