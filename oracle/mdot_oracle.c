@@ -18,6 +18,11 @@
  *   - log-domain Sinkhorn projector ................. Alg. 4
  *   - MDOT annealing loop, entropy-aware tolerance,
  *     variable smoothing, Taylor warm start ......... Alg. 1, Sec. 4.2, eq. (approx-znext)
+ *   - ablation variants the paper compares against:
+ *     diagonal-Hessian direction with the [0.01, 100] switch ... Sec. 4.3, eq. (s-tilde)
+ *     epsilon-scaling warm start z' = (gamma'/gamma) z ......... Sec. 4.2.1
+ *     fixed smoothing weight H_min / (4 gamma_f^p) ............. App. D
+ *     log n in place of H_min in the tolerance ................. App. C
  *   - Round onto U(r,c) ............................. Alg. 3 (Altschuler et al.)
  *   - gap certificate (not in the paper; the paper measures error against an exact
  *     solver): the double c-transform of cost-unit potentials is dual-feasible, so by
@@ -49,6 +54,13 @@
  *   - sweep budget (max_sweeps, whole solve): the solve stops after the sweep that spends
  *     it, keeps the last accepted iterate, rounds and certifies it, and reports a warning.
  *   - adaptive mode reports OK exactly when the certified gap is at most the target.
+ *   - diagonal-Hessian variant: the switch is tested on the whole vector at every iteration
+ *     (s~ when every ratio of (r~/r(P), c~/c(P)) lies in [0.01, 100], else s), and the chosen
+ *     direction replaces s everywhere, in p and in the numerator of beta (the preconditioned
+ *     Hestenes-Stiefel formula with M = D(diag(Hessian))).
+ *   - log n variant: log n replaces H_min wherever eps_d is formed (tolerance and smoothing);
+ *     the adaptive gamma cap keeps H_min (Remark 1).
+ *   - fixed smoothing in adaptive mode uses the gamma cap as gamma_f.
  */
 #include <math.h>
 #include <stdint.h>
@@ -76,7 +88,13 @@ typedef struct {
     int32_t max_pncg_iters;   /* per stage */
     int64_t max_sweeps;       /* whole solve; 0 = unlimited */
     int32_t projector;        /* 0 = PNCG (Alg. 2), 1 = Sinkhorn (Alg. 4) */
-    int32_t warm_start;       /* 1 = Taylor extrapolation eq. (approx-znext), 0 = copy */
+    int32_t warm_start;       /* 1 = Taylor extrapolation eq. (approx-znext), 0 = copy,
+                                 2 = epsilon-scaling z' = (gamma'/gamma) z (Sec. 4.2.1) */
+    int32_t precond;          /* 0 = Sinkhorn direction eq. (sinkhorn-direction),
+                                 1 = diagonal-Hessian direction eq. (s-tilde) with the switch */
+    int32_t smoothing;        /* 0 = variable eps_d / 4 (Alg. 1), 1 = fixed at the final stage's (App. D) */
+    int32_t tol_log_n;        /* 0 = H_min in eps_d (Alg. 1), 1 = log n (App. C) */
+    int32_t pad_;
 } orc_params;
 
 typedef struct {
@@ -93,7 +111,9 @@ typedef struct {
 
 typedef struct {
     double gamma, eps_d, smooth_w, grad_norm, ub, lb;
+    double grad_norm0;  /* ||grad g||_1 at the stage's starting point (after the warm start) */
     int64_t pncg_iters, ls_trials, sweeps, cg_resets;
+    int64_t tilde_iters; /* diagonal-Hessian variant: iterations that took s~ */
 } orc_stage_log;
 
 void orc_default_params(orc_params* prm)
@@ -111,6 +131,34 @@ void orc_default_params(orc_params* prm)
     prm->max_sweeps = 0;
     prm->projector = 0;
     prm->warm_start = 1;
+    prm->precond = 0;
+    prm->smoothing = 0;
+    prm->tol_log_n = 0;
+    prm->pad_ = 0;
+}
+
+/* Debug record of the line search (test infrastructure): when a buffer is set, every
+ * accepted step appends (phi'(0), phi'(alpha), alpha, how) with how = 0 for an approximate
+ * Wolfe acceptance and 1 for the trial cap's fallback to alpha_lo. Not thread-safe. */
+static double* g_ls_log = NULL;
+static int64_t g_ls_cap = 0, g_ls_count = 0;
+
+void orc_set_ls_log(double* buf, int64_t cap)
+{
+    g_ls_log = buf;
+    g_ls_cap = buf ? cap : 0;
+    g_ls_count = 0;
+}
+
+int64_t orc_ls_log_count(void) { return g_ls_count; }
+
+static void ls_record(double dphi0, double d, double alpha, double how)
+{
+    if (g_ls_log && g_ls_count < g_ls_cap) {
+        double* e = g_ls_log + 4 * g_ls_count;
+        e[0] = dphi0; e[1] = d; e[2] = alpha; e[3] = how;
+    }
+    if (g_ls_log) g_ls_count++;
 }
 
 int orc_num_threads(void)
@@ -233,7 +281,7 @@ static double norm1(int m, const double* a)
 }
 
 typedef struct {
-    int64_t pncg_iters, ls_trials, sweeps, cg_resets, ls_failures;
+    int64_t pncg_iters, ls_trials, sweeps, cg_resets, ls_failures, tilde_iters;
 } counters;
 
 static int budget_left(const orc_params* prm, const counters* cn)
@@ -273,6 +321,7 @@ static int line_search(int n, const double* C, double gamma, const double* rt, c
         cn->ls_trials++;
         double d = phi_prime(n, lr, lc, rt, ct, p);
         if ((2.0 * c1 - 1.0) * dphi0 >= d && d >= c2 * dphi0) {
+            ls_record(dphi0, d, a, 0.0);
             *alpha_out = a;
             return 0;
         }
@@ -298,6 +347,7 @@ static int line_search(int n, const double* C, double gamma, const double* rt, c
         for (int k = 0; k < 2 * n; ++k) zt[k] = z[k] + alo * p[k];
         orc_lse2(n, C, zt, zt + n, gamma, lr, lc);
         cn->sweeps++;
+        ls_record(dphi0, dlo, alo, 1.0);
         *alpha_out = alo;
         return 1;
     }
@@ -308,7 +358,7 @@ static int line_search(int n, const double* C, double gamma, const double* rt, c
 /* PNCG (Alg. 2): minimise g(., .; gamma, r~, c~) from z = (u, v) until ||grad g||_1 <= tol.
  * z is updated in place. Returns ORC_OK or ORC_W_NOT_CONVERGED. */
 static int pncg(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
-                double* z, const orc_params* prm, counters* cn, double* gnorm_out)
+                double* z, const orc_params* prm, counters* cn, double* gnorm_out, double* gnorm0_out)
 {
     const int m = 2 * n;
     double* lr = (double*)malloc(sizeof(double) * m); /* lr = log r(P), lr + n = log c(P) */
@@ -334,6 +384,7 @@ static int pncg(int n, const double* C, double gamma, const double* rt, const do
     gradient(n, lr, lr + n, rt, ct, g);
     memset(p, 0, sizeof(double) * m);
     double gnorm = norm1(m, g);
+    if (gnorm0_out) *gnorm0_out = gnorm;
     double beta = 0.0, alpha_prev = 1.0;
     int64_t k = 1;
     while (gnorm > tol) {
@@ -343,6 +394,20 @@ static int pncg(int n, const double* C, double gamma, const double* rt, const do
         }
         /* Sinkhorn direction s = (log r~ - log r(P), log c~ - log c(P)) (eq. (sinkhorn-direction)) */
         for (int t = 0; t < m; ++t) s[t] = logt[t] - lr[t];
+        if (prm->precond == 1) {
+            /* diagonal-Hessian direction s~ = (r~ / r(P), c~ / c(P)) - 1 (eq. (s-tilde)), taken only
+             * when every ratio lies in [0.01, 100]; otherwise s stays (Sec. 4.3) */
+            const double* tgt[2] = {rt, ct};
+            int inrange = 1;
+            for (int t = 0; t < m; ++t) {
+                double ratio = tgt[t / n][t % n] / exp(lr[t]);
+                if (!(ratio >= 0.01 && ratio <= 100.0)) inrange = 0;
+            }
+            if (inrange) {
+                for (int t = 0; t < m; ++t) s[t] = tgt[t / n][t % n] / exp(lr[t]) - 1.0;
+                cn->tilde_iters++;
+            }
+        }
         /* preconditioned Hestenes-Stiefel beta (eq. (beta_PPR_OT)); beta^(1) = 0, p^(0) = 0 */
         if (k == 1) {
             beta = 0.0;
@@ -393,7 +458,7 @@ out:
  * residual ||r~ - r(P)||_1 (the whole gradient, since c(P) = c~ after each column update)
  * is at most tol. */
 static int sinkhorn(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
-                    double* z, const orc_params* prm, counters* cn, double* gnorm_out)
+                    double* z, const orc_params* prm, counters* cn, double* gnorm_out, double* gnorm0_out)
 {
     double* u = z;
     double* v = z + n;
@@ -408,6 +473,7 @@ static int sinkhorn(int n, const double* C, double gamma, const double* rt, cons
     cn->sweeps++;
     double res = 0.0;
     for (int i = 0; i < n; ++i) res += fabs(rt[i] - exp(lr[i]));
+    if (gnorm0_out) *gnorm0_out = res;
     int64_t it = 0;
     while (res > tol) {
         if (it >= prm->max_pncg_iters || !budget_left(prm, cn)) {
@@ -564,14 +630,14 @@ int orc_round_certify(int n, const double* C, const double* u, const double* v, 
 
 /* KL projection at fixed gamma from z (PNCG or Sinkhorn), as called by the inner solve of Alg. 1. */
 int orc_project(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
-                double* z, const orc_params* prm, int64_t* counts /* [5] or NULL */, double* gnorm)
+                double* z, const orc_params* prm, int64_t* counts /* [6] or NULL */, double* gnorm)
 {
-    counters cn = {0, 0, 0, 0, 0};
-    int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm)
-                                 : pncg(n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm);
+    counters cn = {0, 0, 0, 0, 0, 0};
+    int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm, NULL)
+                                 : pncg(n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm, NULL);
     if (counts) {
         counts[0] = cn.pncg_iters; counts[1] = cn.ls_trials; counts[2] = cn.sweeps;
-        counts[3] = cn.cg_resets; counts[4] = cn.ls_failures;
+        counts[3] = cn.cg_resets; counts[4] = cn.ls_failures; counts[5] = cn.tilde_iters;
     }
     return st;
 }
@@ -592,6 +658,8 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
     double gf;
     if (!adaptive) gf = prm->gamma_f;
     else gf = prm->gamma_cap > 0.0 ? prm->gamma_cap : 5.0 * hmin / (2.0 * prm->target_gap); /* Remark 1 */
+    /* the entropy term of eps_d: H_min (Alg. 1), or log n (App. C) */
+    const double hterm = prm->tol_log_n ? log((double)n) : hmin;
 
     double* z = (double*)malloc(sizeof(double) * m);      /* current (u, v) */
     double* zprev = (double*)malloc(sizeof(double) * m);  /* solution at the previous gamma */
@@ -602,14 +670,15 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
         free(z); free(zprev); free(zbest); free(rt); free(ct);
         return ORC_E_NOMEM;
     }
-    counters tot = {0, 0, 0, 0, 0};
+    counters tot = {0, 0, 0, 0, 0, 0};
     double gamma = fmin(prm->gamma_i, gf); /* Alg. 1: gamma <- min(gamma_i, gamma_f) */
     double gamma_prev = 0.0;               /* gamma^0 = 0 (Prop. 1) */
     double best_ub = INFINITY, best_lb = -INFINITY, best_gamma = gamma, best_me = 0.0, gnorm = 0.0;
     int status = ORC_OK, inner_warn = 0, t = 1;
     for (;;) {
-        double eps_d = hmin / pow(gamma, prm->p); /* entropy-aware tolerance (Alg. 1) */
-        double w = fmin(eps_d / 4.0, 0.5);        /* variable smoothing weight (Alg. 1) */
+        double eps_d = hterm / pow(gamma, prm->p); /* entropy-aware tolerance (Alg. 1) */
+        double w = fmin(eps_d / 4.0, 0.5);         /* variable smoothing weight (Alg. 1) */
+        if (prm->smoothing == 1) w = fmin(hterm / pow(gf, prm->p) / 4.0, 0.5); /* fixed (App. D) */
         for (int i = 0; i < n; ++i) {
             rt[i] = (1.0 - w) * r[i] + w / n;
             ct[i] = (1.0 - w) * c[i] + w / n;
@@ -623,13 +692,14 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
         }
         counters before = tot; /* the projector counts into the solve totals (one sweep budget) */
         double tol = fmax(eps_d / 2.0, TOL_FLOOR);
-        int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm)
-                                     : pncg(n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm);
+        double gnorm0 = 0.0;
+        int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm, &gnorm0)
+                                     : pncg(n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm, &gnorm0);
         if (st < 0) { status = st; break; }
         if (st == ORC_W_NOT_CONVERGED) inner_warn = 1;
         counters cn = {tot.pncg_iters - before.pncg_iters, tot.ls_trials - before.ls_trials,
                        tot.sweeps - before.sweeps, tot.cg_resets - before.cg_resets,
-                       tot.ls_failures - before.ls_failures};
+                       tot.ls_failures - before.ls_failures, tot.tilde_iters - before.tilde_iters};
         double ub = NAN, lb = NAN;
         int last = (gamma >= gf);
         const int budget_stop = !budget_left(prm, &tot);
@@ -647,8 +717,9 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
         if (log_ && t - 1 < log_cap) {
             orc_stage_log* L = &log_[t - 1];
             L->gamma = gamma; L->eps_d = eps_d; L->smooth_w = w; L->grad_norm = gnorm; L->ub = ub; L->lb = lb;
+            L->grad_norm0 = gnorm0;
             L->pncg_iters = cn.pncg_iters; L->ls_trials = cn.ls_trials; L->sweeps = cn.sweeps;
-            L->cg_resets = cn.cg_resets;
+            L->cg_resets = cn.cg_resets; L->tilde_iters = cn.tilde_iters;
         }
         res->stages = t;
         if (adaptive && best_ub - best_lb <= prm->target_gap) { status = ORC_OK; break; }
@@ -660,11 +731,12 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
         /* Alg. 1: Delta gamma <- (q-1) gamma, gamma <- min(gamma + Delta gamma, gamma_f) */
         double gnew = fmin(gamma + (prm->q - 1.0) * gamma, gf);
         double dg = gnew - gamma, dg_prev = gamma - gamma_prev;
-        /* warm start, eq. (approx-znext): z' = z^t + (dg^t / dg^{t-1}) (z^t - z^{t-1}) */
-        double ratio = prm->warm_start ? dg / dg_prev : 0.0;
+        /* warm start, eq. (approx-znext): z' = z^t + (dg^t / dg^{t-1}) (z^t - z^{t-1});
+         * the epsilon-scaling variant predicts z' = (gamma^{t+1} / gamma^t) z^t (Sec. 4.2.1) */
+        double ratio = prm->warm_start == 1 ? dg / dg_prev : 0.0;
         for (int k = 0; k < m; ++k) {
             double zt = z[k];
-            z[k] = zt + ratio * (zt - zprev[k]);
+            z[k] = prm->warm_start == 2 ? (gnew / gamma) * zt : zt + ratio * (zt - zprev[k]);
             zprev[k] = zt;
         }
         gamma_prev = gamma;

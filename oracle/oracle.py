@@ -34,6 +34,10 @@ class Params(ct.Structure):
         ("max_sweeps", ct.c_int64),
         ("projector", ct.c_int32),
         ("warm_start", ct.c_int32),
+        ("precond", ct.c_int32),
+        ("smoothing", ct.c_int32),
+        ("tol_log_n", ct.c_int32),
+        ("pad_", ct.c_int32),
     ]
 
 
@@ -63,10 +67,12 @@ class StageLog(ct.Structure):
         ("grad_norm", ct.c_double),
         ("ub", ct.c_double),
         ("lb", ct.c_double),
+        ("grad_norm0", ct.c_double),
         ("pncg_iters", ct.c_int64),
         ("ls_trials", ct.c_int64),
         ("sweeps", ct.c_int64),
         ("cg_resets", ct.c_int64),
+        ("tilde_iters", ct.c_int64),
     ]
 
 
@@ -107,6 +113,8 @@ def lib():
         L.orc_mdot.argtypes = [ct.c_int, _dp, _dp, _dp, ct.POINTER(Params), _dp, _dp,
                                ct.POINTER(Result), ct.POINTER(StageLog), ct.c_int]
         L.orc_num_threads.restype = ct.c_int
+        L.orc_set_ls_log.argtypes = [_dp, ct.c_int64]
+        L.orc_ls_log_count.restype = ct.c_int64
         _lib = L
     return _lib
 
@@ -121,6 +129,25 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+class LineSearchLog:
+    """Context manager recording every accepted line-search step of the oracle as rows
+    (phi'(0), phi'(alpha), alpha, how); how = 0 for an approximate-Wolfe acceptance, 1 for the
+    trial cap's fallback to alpha_lo."""
+
+    def __init__(self, cap: int = 1 << 20):
+        self.buf = np.zeros((cap, 4))
+
+    def __enter__(self):
+        lib().orc_set_ls_log(_d(self.buf), self.buf.shape[0])
+        return self
+
+    def __exit__(self, *exc):
+        self.count = int(lib().orc_ls_log_count())
+        lib().orc_set_ls_log(None, 0)
+        self.rows = self.buf[:min(self.count, self.buf.shape[0])].copy()
+        return False
 
 
 def default_params(**kw) -> Params:
@@ -183,12 +210,12 @@ def round_certify(C, u, v, gamma, r, c, want_plan: bool = False, u_prev=None, v_
 
 def project(C, gamma, rt, ct_, tol, u, v, params: Params | None = None):
     """KL projection at fixed gamma (PNCG, or Sinkhorn with params.projector=1).
-    Returns (u, v, status, counts[pncg_iters, ls_trials, sweeps, cg_resets, ls_failures], gnorm)."""
+    Returns (u, v, status, counts[pncg_iters, ls_trials, sweeps, cg_resets, ls_failures, tilde_iters], gnorm)."""
     C, rt, ct_ = _f64(C), _f64(rt), _f64(ct_)
     n = rt.size
     z = np.concatenate([_f64(u), _f64(v)])
     prm = params or default_params()
-    counts = (ct.c_int64 * 5)()
+    counts = (ct.c_int64 * 6)()
     gn = ct.c_double()
     st = lib().orc_project(n, _d(C), float(gamma), _d(rt), _d(ct_), float(tol), _d(z), ct.byref(prm),
                            counts, ct.byref(gn))

@@ -8,10 +8,17 @@ transposed operand, a dropped term) breaks at least one of them:
 
   transposed C / wrong index in the LSE ...... test_lse_matches_direct_definition (asymmetric C)
   wrong gradient sign or term ................ test_gradient_matches_finite_differences
-  wrong PNCG fixed point ..................... test_pncg_2x2_closed_form, test_separable_cost
+  wrong PNCG / Sinkhorn fixed point .......... test_pncg_2x2_closed_form, test_separable_cost,
+                                               test_init_independence (every projector and direction)
+  wrong Sinkhorn update or residual .......... test_sinkhorn_fixed_point_and_residual
+  wrong line-search acceptance ............... test_line_search_accepts_only_approximate_wolfe_steps
+  wrong warm-start ratio (incl. stage 2) ..... test_warm_start_exact_on_linear_trajectory,
+                                               test_warm_start_order
+  wrong diagonal-Hessian direction ........... test_diagonal_hessian_direction_matches_fd_hessian
   wrong Round ................................ test_round_feasible_and_close, exact-LP tests
   wrong c-transform / certificate ............ test_certificate_brackets_exact_ot
-  wrong smoothing / schedule / stop test ..... test_schedule_and_stage_tolerances
+  wrong smoothing / schedule / stop test ..... test_schedule_and_stage_tolerances, test_fixed_smoothing,
+                                               test_log_n_tolerance
   whole-solve errors ......................... exact LP, Birkhoff and 1-D closed-form tests
 """
 from __future__ import annotations
@@ -123,9 +130,14 @@ def test_sinkhorn_direction_kl_identity():
 # ---------------------------------------------------------------- PNCG fixed points
 
 
-def test_pncg_2x2_closed_form():
+PROJECTORS = [dict(projector=0), dict(projector=1), dict(projector=0, precond=1)]
+
+
+@pytest.mark.parametrize("variant", PROJECTORS, ids=["pncg", "sinkhorn", "pncg-diag-hessian"])
+def test_pncg_2x2_closed_form(variant):
     # For n = 2 the EOT plan has P11 P22 / (P12 P21) = exp(-gamma (C11 + C22 - C12 - C21))
-    # and the marginals fix the rest: a quadratic in P11.
+    # and the marginals fix the rest: a quadratic in P11. Every projector (PNCG with either
+    # direction, Sinkhorn) must land on it.
     C = np.array([[0.1, 0.9], [0.7, 0.2]])
     r = np.array([0.3, 0.7])
     c = np.array([0.55, 0.45])
@@ -142,13 +154,14 @@ def test_pncg_2x2_closed_form():
             roots = [(-b + disc) / (2 * a), (-b - disc) / (2 * a)]
             x = [t for t in roots if 0 < t < min(r[0], c[0]) + 1e-15 and r[1] - c[0] + t > 0][0]
         Pexp = np.array([[x, r[0] - x], [c[0] - x, r[1] - c[0] + x]])
-        u, v, st, counts, gn = O.project(C, gamma, r, c, 1e-13, np.log(r), np.log(c))
+        u, v, st, counts, gn = O.project(C, gamma, r, c, 1e-13, np.log(r), np.log(c), O.default_params(**variant))
         assert st == 0 and gn <= 1e-13
         P = np.exp(u[:, None] + v[None, :] - gamma * C)
         np.testing.assert_allclose(P, Pexp, rtol=1e-10, atol=1e-14)
 
 
-def test_separable_cost():
+@pytest.mark.parametrize("variant", PROJECTORS, ids=["pncg", "sinkhorn", "pncg-diag-hessian"])
+def test_separable_cost(variant):
     # C_ij = a_i + b_j: P*(gamma) = r c^T for every gamma and every plan costs <a,r> + <b,c>
     n = 10
     rng = np.random.default_rng(7)
@@ -159,24 +172,53 @@ def test_separable_cost():
     r /= r.sum()
     c = rng.random(n) + 0.1
     c /= c.sum()
-    u, v, st, _, _ = O.project(C, 37.0, r, c, 1e-13, np.zeros(n), np.zeros(n))
+    u, v, st, _, _ = O.project(C, 37.0, r, c, 1e-13, np.zeros(n), np.zeros(n), O.default_params(**variant))
     P = np.exp(u[:, None] + v[None, :] - 37.0 * C)
     np.testing.assert_allclose(P, np.outer(r, c), rtol=1e-10)
-    s = O.mdot(C, r, c, O.default_params(target_gap=1e-9))
+    s = O.mdot(C, r, c, O.default_params(target_gap=1e-9, **variant))
     assert s.result["primal_cost"] == pytest.approx(a @ r + b @ c, abs=1e-12)
     assert s.result["gap"] <= 1e-9
 
 
-def test_init_independence():
-    # Observation 1 / Prop. 1.2: the projection at gamma does not depend on the initial (u, v)
+@pytest.mark.parametrize("variant", PROJECTORS, ids=["pncg", "sinkhorn", "pncg-diag-hessian"])
+def test_init_independence(variant):
+    # Observation 1 / Prop. 1.2: the projection at gamma does not depend on the initial (u, v),
+    # nor on the projector that computes it
     C, r, c = W.grid_problem(6, "smooth", "sqeuclid", 11)
     gamma = 200.0
-    u1, v1, st1, _, _ = O.project(C, gamma, r, c, 1e-12, np.log(r), np.log(c))
+    prm = O.default_params(**variant)
+    u1, v1, st1, _, _ = O.project(C, gamma, r, c, 1e-12, np.log(r), np.log(c), prm)
     rng = np.random.default_rng(3)
-    u2, v2, st2, _, _ = O.project(C, gamma, r, c, 1e-12, rng.standard_normal(36), rng.standard_normal(36))
+    u2, v2, st2, _, _ = O.project(C, gamma, r, c, 1e-12, rng.standard_normal(36), rng.standard_normal(36), prm)
+    u0, v0, st0, _, _ = O.project(C, gamma, r, c, 1e-12, np.log(r), np.log(c))  # PNCG, Sinkhorn direction
+    assert st1 == 0 and st2 == 0 and st0 == 0
     P1 = np.exp(u1[:, None] + v1[None, :] - gamma * C)
     P2 = np.exp(u2[:, None] + v2[None, :] - gamma * C)
+    P0 = np.exp(u0[:, None] + v0[None, :] - gamma * C)
     assert np.abs(P1 - P2).sum() < 1e-10
+    assert np.abs(P1 - P0).sum() < 1e-10
+
+
+def test_sinkhorn_fixed_point_and_residual():
+    # Alg. 4 ends right after a column update: the columns of P are exactly c~ (to rounding),
+    # and the reported residual is ||r(P) - r~||_1, recomputed here by scipy from the returned
+    # potentials. A Sinkhorn that never converges, or that updates with a wrong sign, fails it.
+    C, r, c = W.grid_problem(7, "blobs", "l1", 17)
+    gamma = 300.0
+    tol = 1e-9
+    prm = O.default_params(projector=1)
+    u, v, st, counts, gn = O.project(C, gamma, r, c, tol, np.log(r), np.log(c), prm)
+    assert st == 0
+    X = u[:, None] + v[None, :] - gamma * C
+    rows, cols = np.exp(logsumexp(X, axis=1)), np.exp(logsumexp(X, axis=0))
+    assert np.abs(cols - c).sum() <= 1e-13
+    assert np.abs(rows - r).sum() == pytest.approx(gn, rel=1e-6, abs=1e-15)
+    assert gn <= tol
+    assert counts[2] == 1 + 2 * counts[0]  # one row pass, then a column and a row pass per iteration
+    # the plan is the PNCG projection's (the same strictly convex problem)
+    up, vp, _, _, _ = O.project(C, gamma, r, c, tol, np.log(r), np.log(c))
+    Pp = np.exp(up[:, None] + vp[None, :] - gamma * C)
+    assert np.abs(np.exp(X) - Pp).sum() <= 10 * tol
 
 
 def test_pncg_beats_sinkhorn_at_low_temperature():
@@ -350,3 +392,180 @@ def test_sweep_budget_stops_and_certifies():
         assert s.status == 1
         assert R["sweeps"] == 40
         assert np.isfinite(R["primal_cost"]) and R["dual_bound"] <= ot + 1e-12 <= R["primal_cost"] + 2e-12
+
+
+# ---------------------------------------------------------------- line search (App. B)
+
+
+def test_line_search_accepts_only_approximate_wolfe_steps():
+    # eq. (approximate-wolfe): every accepted alpha satisfies (2 c1 - 1) phi'(0) >= phi'(alpha) >= c2 phi'(0)
+    # with phi'(0) < 0 (a descent direction), unless the trial cap forced alpha_lo (then phi'(alpha) < 0).
+    C, r, c = W.grid_problem(8, "cauchy", "l1", 14)
+    prm = O.default_params(gamma_f=2.0**12)
+    with O.LineSearchLog() as log:
+        s = O.mdot(C, r, c, prm)
+    rows = log.rows
+    assert log.count == s.result["pncg_iters"] > 100
+    wolfe = rows[rows[:, 3] == 0]
+    forced = rows[rows[:, 3] == 1]
+    assert len(forced) == s.result["ls_failures"]
+    assert (wolfe[:, 0] < 0).all() and (wolfe[:, 2] > 0).all()
+    assert ((2 * prm.ls_c1 - 1) * wolfe[:, 0] >= wolfe[:, 1]).all()
+    assert (wolfe[:, 1] >= prm.ls_c2 * wolfe[:, 0]).all()
+    assert (forced[:, 1] < 0).all()
+
+
+# ---------------------------------------------------------------- warm start (Sec. 4.2.1)
+
+
+def test_warm_start_exact_on_linear_trajectory():
+    # For a separable cost C_ij = a_i + b_j the dual solution is linear in gamma:
+    # z*(gamma) = (log r~ - gamma a, log c~ - gamma b) up to the gauge. The extrapolation of
+    # eq. (approx-znext) is then exact, at stage 2 too, where it extrapolates from
+    # z^0 = (log r~, log c~), the solution at gamma^0 = 0, with Delta gamma^0 = gamma_i. Each stage
+    # therefore starts within a few tolerances of its solution (p = 4 keeps the smoothing change
+    # between stages negligible). A wrong ratio (q in place of q - 1, a wrong Delta gamma^0) leaves
+    # an O(gamma a) error, as the copy and epsilon-scaling starts show.
+    n = 40
+    rng = np.random.default_rng(7)
+    a, b = rng.random(n) * 0.5, rng.random(n) * 0.5
+    C = a[:, None] + b[None, :]
+    r = rng.random(n) + 0.1
+    r /= r.sum()
+    c = rng.random(n) + 0.1
+    c /= c.sum()
+    taylor = O.mdot(C, r, c, O.default_params(gamma_f=2.0**8, p=4.0, warm_start=1)).stages
+    copy = O.mdot(C, r, c, O.default_params(gamma_f=2.0**8, p=4.0, warm_start=0)).stages
+    scaled = O.mdot(C, r, c, O.default_params(gamma_f=2.0**8, p=4.0, warm_start=2)).stages
+    for t in range(1, len(taylor)):
+        assert taylor[t]["grad_norm0"] <= 4 * taylor[t - 1]["eps_d"] / 2 + 1e-5
+        assert copy[t]["grad_norm0"] > 0.5 and scaled[t]["grad_norm0"] > 0.5
+    # epsilon-scaling z' = (gamma'/gamma) z* misses z* by (gamma'/gamma - 1)(log r~, log c~) (+ gauge): a
+    # fixed error, so the stages start at the same gradient norm whatever gamma (Sec. 4.2.1: it
+    # "stays relatively fixed"); a reversed ratio would leave an error growing with gamma a
+    g0 = [x["grad_norm0"] for x in scaled[1:]]
+    assert max(g0) <= 1.2 * min(g0)
+
+
+def _init_grad(prm_kw, log2_gammas, k):
+    C, r, c = W.grid_problem(6, "smooth", "sqeuclid", 3)
+    s = O.mdot(C, r, c, O.default_params(gamma_f=2.0**9, q=2 ** (1 / k), p=4.0, **prm_kw))
+    d = {round(math.log2(x["gamma"]), 9): x["grad_norm0"] for x in s.stages}
+    return np.array([d[g] for g in log2_gammas])
+
+
+def test_warm_start_order():
+    # The error of a start predicted over Delta gamma is O(Delta gamma^2) for the Taylor start
+    # (eq. (approx-znext): a secant extrapolation), O(Delta gamma) for the copy and for
+    # epsilon-scaling (z' = (gamma'/gamma) z misses (dz/dgamma - z/gamma) Delta gamma). Halving q - 1
+    # (q = 2^(1/6) -> 2^(1/12): Delta gamma shrinks by 2.06) must divide the stage's initial gradient
+    # norm by about 2.06^2 = 4.24 for the Taylor start and by about 2 for the others, at the same
+    # gamma (2^5 and 2^6, where both schedules have a stage). p = 4 keeps the previous stage's
+    # tolerance far below these errors.
+    gs = [5.0, 6.0]
+    for kw, lo, hi in [(dict(warm_start=1), 3.3, 5.5), (dict(warm_start=0), 1.3, 2.6), (dict(warm_start=2), 1.3, 2.6)]:
+        ratio = _init_grad(kw, gs, 6) / _init_grad(kw, gs, 12)
+        assert ((ratio > lo) & (ratio < hi)).all(), (kw, ratio)
+    t, cp, sc = (_init_grad(dict(warm_start=w), gs, 6) for w in (1, 0, 2))
+    assert (t < 0.25 * cp).all() and (t < 0.25 * sc).all()
+
+
+# ---------------------------------------------------------------- diagonal-Hessian direction (Sec. 4.3)
+
+
+def test_diagonal_hessian_direction_matches_fd_hessian():
+    # eq. (s-tilde): s~ = -D(diag(Hessian))^-1 grad g. The Hessian diagonal is formed here by central
+    # differences of the gradient (itself pinned by finite differences of g), not from the formula.
+    # The first PNCG step (p = s~, beta = 0) must move z along it; with the default direction it
+    # moves along the Sinkhorn direction s = log r~ - log r(P) instead.
+    n = 9
+    C, r, c = _rand_problem(n, 21)
+    rng = np.random.default_rng(22)
+    u0 = np.log(r) + 0.3 * rng.standard_normal(n)
+    v0 = np.log(c) + 0.3 * rng.standard_normal(n)
+    gamma = 3.0
+
+    def grad(z):
+        lr, lc = O.lse2(C, z[:n], z[n:], gamma)
+        return np.concatenate([np.exp(lr) - r, np.exp(lc) - c])
+
+    z0 = np.concatenate([u0, v0])
+    g0 = grad(z0)
+    h = 1e-6
+    hdiag = np.array([(grad(z0 + h * np.eye(2 * n)[k])[k] - grad(z0 - h * np.eye(2 * n)[k])[k]) / (2 * h)
+                      for k in range(2 * n)])
+    stilde = -g0 / hdiag
+    lr, lc = O.lse2(C, u0, v0, gamma)
+    ssink = np.concatenate([np.log(r) - lr, np.log(c) - lc])
+    assert np.abs(stilde - ssink).max() > 1e-2  # the two directions differ here
+    for precond, want in ((1, stilde), (0, ssink)):
+        prm = O.default_params(precond=precond, max_pncg_iters=1)
+        u1, v1, st, counts, _ = O.project(C, gamma, r, c, 1e-14, u0, v0, prm)
+        assert counts[0] == 1
+        step = np.concatenate([u1, v1]) - z0
+        alpha = step @ want / (want @ want)
+        np.testing.assert_allclose(step, alpha * want, rtol=0, atol=1e-7 * abs(alpha) * np.abs(want).max())
+
+
+def test_diagonal_hessian_switch():
+    # The diagonal-Hessian variant takes s~ only when every ratio r~ / r(P), c~ / c(P) lies in
+    # [0.01, 100]: from a start far off (ratios ~ e^5) the first iterations take s, and the
+    # iterations near the solution take s~. Solves still bracket the exact OT.
+    from tests.exact_ot import exact_lp
+
+    C, r, c = W.grid_problem(6, "blobs", "sqeuclid", 9)
+    prm = O.default_params(precond=1)
+    u0, v0 = np.log(r) - 5.0, np.log(c)  # r~ / r(P) ~ e^5 > 100 at the start
+    _, _, st, counts, _ = O.project(C, 50.0, r, c, 1e-10, u0, v0, prm)
+    assert st == 0
+    assert 0 < counts[5] < counts[0]  # some iterations took s, the later ones s~
+    _, _, st, counts, _ = O.project(C, 50.0, r, c, 1e-10, np.log(r), np.log(c), O.default_params())
+    assert st == 0 and counts[5] == 0  # the default direction never takes s~
+    ot = exact_lp(C, r, c)
+    s2 = O.mdot(C, r, c, O.default_params(precond=1, target_gap=1e-6))
+    assert s2.status == 0 and s2.result["dual_bound"] <= ot + 1e-12 <= s2.result["primal_cost"] + 2e-12
+    assert s2.result["primal_cost"] - ot <= 1e-6
+    assert sum(x["tilde_iters"] for x in s2.stages) > 0
+
+
+# ---------------------------------------------------------------- smoothing and tolerance ablations (App. C, D)
+
+
+def test_fixed_smoothing():
+    # App. D: the fixed-smoothing baseline keeps the weight at H_min / (4 gamma_f^p) in every stage
+    from tests.exact_ot import exact_lp
+
+    C, r, c = W.grid_problem(6, "smooth", "l1", 4)
+    gf = 2.0**11
+    prm = O.default_params(gamma_f=gf, smoothing=1)
+    s = O.mdot(C, r, c, prm)
+    hmin = min(O.entropy(r), O.entropy(c))
+    for st in s.stages:
+        assert st["smooth_w"] == pytest.approx(hmin / gf**prm.p / 4, rel=1e-14)
+        assert st["eps_d"] == pytest.approx(hmin / st["gamma"] ** prm.p, rel=1e-14)
+    ot = exact_lp(C, r, c)
+    s2 = O.mdot(C, r, c, O.default_params(target_gap=1e-6, smoothing=1))
+    assert s2.status == 0 and s2.result["dual_bound"] <= ot + 1e-12 <= s2.result["primal_cost"] + 2e-12
+
+
+def test_log_n_tolerance():
+    # App. C: log n replaces H_min in eps_d (and so in the smoothing weight). For a marginal of low
+    # entropy the stages become looser: H_min / log n smaller tolerance is what the paper's choice buys.
+    from tests.exact_ot import exact_lp
+
+    n = 49
+    C = W.grid_cost(7, "sqeuclid")
+    rng = np.random.default_rng(5)
+    r = rng.dirichlet(np.full(n, 0.05)) + 1e-9
+    r /= r.sum()
+    c = np.full(n, 1.0 / n)
+    gf = 2.0**10
+    for flag, h in ((1, math.log(n)), (0, min(O.entropy(r), O.entropy(c)))):
+        s = O.mdot(C, r, c, O.default_params(gamma_f=gf, tol_log_n=flag))
+        for st in s.stages:
+            assert st["eps_d"] == pytest.approx(h / st["gamma"] ** 1.5, rel=1e-13)
+            assert st["smooth_w"] == pytest.approx(min(st["eps_d"] / 4, 0.5), rel=1e-13)
+    assert min(O.entropy(r), O.entropy(c)) < 0.5 * math.log(n)
+    ot = exact_lp(C, r, c)
+    s2 = O.mdot(C, r, c, O.default_params(target_gap=1e-6, tol_log_n=1))
+    assert s2.status == 0 and s2.result["dual_bound"] <= ot + 1e-12 <= s2.result["primal_cost"] + 2e-12
