@@ -7,8 +7,11 @@
 // flight. Every engine step advances all of them with one launch per kernel, one workgroup per
 // tile and per finalize block of the solves in flight (a device batch descriptor maps
 // workgroups to solves; the graph is captured again when the batch changes). A finished solve
-// frees its slot and workspace when its chunk is read back, where new requests can be admitted
-// if a slot and the HBM budget allow.
+// frees its slot when its chunk is read back, where new requests can be admitted if a slot and
+// the HBM budget allow. Neither an admission nor a retirement waits for the chunk in flight:
+// intake runs on a side stream, a retiring solve's potentials and state are copied out behind
+// the chunk in flight (its workspace returns to the pool once that copy has completed), and
+// the batch descriptor is uploaded from alternating host buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +36,7 @@ constexpr int kConvBlocks = 1024; // workgroups of the FP16 conversion (MIXED)
 
 // Device buffers of one problem: workspace, device copy of Work + 2 state slots, parameters.
 struct ProblemBufs {
+    bool borrowed = false;  // the buffers live in memory the context does not own (never freed)
     void* ws = nullptr;
     size_t ws_bytes = 0;
     int cap_n = 0;
@@ -41,6 +45,22 @@ struct ProblemBufs {
     Work host_work{};
     void* proxy = nullptr;  // MIXED: FP16 copy of the cost
     size_t proxy_bytes = 0;
+};
+
+// Device bytes a problem's buffers hold.
+static size_t bufs_bytes(const ProblemBufs& pb)
+{
+    if (pb.borrowed) return 0;
+    return (pb.d_work ? sizeof(Control) : 0) + pb.ws_bytes + pb.proxy_bytes;
+}
+
+// A solve whose chunk reported it finished: its finish kernel and the copy of its state into
+// h_states[hs] are queued behind the chunk in flight, and `ev` is recorded after them. Its
+// buffers return to the pool once `ev` has completed.
+struct Retiring {
+    ProblemBufs pb;
+    uint64_t ticket = 0;
+    int hs = 0;
 };
 
 struct Slot {
@@ -79,14 +99,25 @@ struct mdot_ctx {
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipGraphExec_t graph = nullptr;  // captured chunk of solver steps for `main`
-    int graph_n = 0, graph_kind = -1, graph_dtype = -1;
+    // what the graph was captured with: n and the sweep kernel instance (cost code, which also
+    // tells planar point clouds from d = 3 ones)
+    int graph_n = 0, graph_code = -1;
     // serving engine
+    hipStream_t side = nullptr;     // intake of admitted solves (does not wait for the chunk in flight)
     Slot slots[kMaxBatch];
     std::vector<ProblemBufs> pool;  // released problem buffers kept for reuse
-    BatchDesc* h_batch = nullptr;   // pinned
+    std::vector<Retiring> retiring;
+    State* h_states = nullptr;      // pinned, one state per retiring solve
+    hipEvent_t ret_ev[kMaxBatch] = {};
+    std::vector<int> free_hs;       // free indices of h_states / ret_ev
+    BatchDesc* h_batch[2] = {nullptr, nullptr};  // pinned, alternating upload buffers
+    hipEvent_t batch_ev[2] = {nullptr, nullptr};  // recorded after each buffer's upload
+    int hb_cur = 0;                 // buffer holding the current descriptor
     BatchDesc* d_batch = nullptr;
     bool batch_dirty = true;
     hipGraphExec_t bgraph = nullptr;
+    // replaced batch graphs, destroyed once the last chunk launched from them has been read back
+    std::vector<std::pair<hipGraphExec_t, int64_t>> graveyard;
     // what the batch graph was captured with: its sweep instances and their tile ranges, the
     // finalize grid, and whether a problem has n > 8192
     int bgraph_ncodes = 0, bgraph_code[kMaxCodes] = {}, bgraph_begin[kMaxCodes + 1] = {};
@@ -104,7 +135,7 @@ struct mdot_ctx {
     int chunk_slot[2][kMaxBatch];
     uint64_t chunk_ticket[2][kMaxBatch];
     uint64_t next_ticket = 1;
-    size_t bytes_in_use = 0;
+    size_t bytes_in_use = 0;  // buffers of the solves in slots and retiring
     std::map<uint64_t, mdot_result> finished;
 };
 
@@ -159,6 +190,10 @@ static size_t problem_footprint(int n)
 
 static void free_bufs(ProblemBufs& pb)
 {
+    if (pb.borrowed) {
+        pb = ProblemBufs{};
+        return;
+    }
     if (pb.ws) (void)hipFree(pb.ws);
     if (pb.d_work) (void)hipFree(pb.d_work);
     if (pb.proxy) (void)hipFree(pb.proxy);
@@ -181,7 +216,7 @@ static int ensure_scratch(mdot_ctx* ctx, int n)
 }
 
 // Make pb hold a workspace for size n (reallocating when it is too small).
-static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n)
+static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n, hipStream_t stream)
 {
     if (!pb.d_work) {
         HIPCHK(ctx, hipMalloc(&pb.d_work, sizeof(Control)));
@@ -206,13 +241,13 @@ static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n)
     }
     pb.ws_bytes = need;
     pb.cap_n = n;
-    HIPCHK(ctx, hipMemsetAsync(pb.ws, 0, need, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(pb.ws, 0, need, stream));
     return ensure_scratch(ctx, n);
 }
 
 // Lay the Work struct out over pb's workspace for size n (n <= cap_n) and upload it.
 static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc* cost, double scale,
-                     const double* r, const double* c)
+                     const double* r, const double* c, hipStream_t stream)
 {
     size_t off[32];
     workspace_bytes(n, off);
@@ -248,7 +283,7 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
     w.st = ctl->st;
     w.prm = &ctl->prm;
     w.bdots = ctl->bdots;
-    HIPCHK(ctx, hipMemcpyAsync(pb.d_work, &w, sizeof w, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(pb.d_work, &w, sizeof w, hipMemcpyHostToDevice, stream));
     return MDOT_OK;
 }
 
@@ -299,15 +334,16 @@ static int check_params(mdot_ctx* ctx, const mdot_params& prm, double target_gap
 }
 
 // Range of the raw cost (one pass) -> resolved scale; MDOT_E_COST if scale*raw leaves [0,1].
-static int resolve_scale(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, double* scale_out)
+static int resolve_scale(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, double* scale_out,
+                         hipStream_t stream)
 {
     const int n = cost->n;
     const int tiles = tiles_r(n) * tiles_c(n);
-    if (launch_cost_range(pb.host_work, pb.d_work, ctx->d_scratch, ctx->stream))
+    if (launch_cost_range(pb.host_work, pb.d_work, ctx->d_scratch, stream))
         return fail(ctx, MDOT_E_DEVICE, "cost range kernel launch failed");
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 2 * tiles * sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+                               stream));
+    HIPCHK(ctx, hipStreamSynchronize(stream));
     double lo = INFINITY, hi = -INFINITY;
     bool nonfinite = false;
     for (int t = 0; t < tiles; ++t) {
@@ -326,12 +362,12 @@ static int resolve_scale(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
     return MDOT_OK;
 }
 
-static int intake_marginals(mdot_ctx* ctx, ProblemBufs& pb, int n, double* hmin)
+static int intake_marginals(mdot_ctx* ctx, ProblemBufs& pb, int n, double* hmin, hipStream_t stream)
 {
-    if (launch_intake(pb.d_work, ctx->d_scratch, ctx->stream))
+    if (launch_intake(pb.d_work, ctx->d_scratch, stream))
         return fail(ctx, MDOT_E_DEVICE, "intake kernel launch failed");
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(ctx, hipStreamSynchronize(stream));
     const double* s = ctx->h_scratch;
     const double tol = 1e-9 * n;
     if (s[6] > 0) return fail(ctx, MDOT_E_MARGINAL, "marginals contain non-finite values");
@@ -342,25 +378,26 @@ static int intake_marginals(mdot_ctx* ctx, ProblemBufs& pb, int n, double* hmin)
     return MDOT_OK;
 }
 
-// Intake of one problem into pb: workspace, Work, cost scale, marginal checks, parameters,
-// initial state. Leaves the problem ready for its first solver step (state slot 0).
+// Intake of one problem into pb on `stream`: workspace, Work, cost scale, marginal checks,
+// parameters, initial state. Leaves the problem ready for its first solver step (state slot 0)
+// and the stream idle.
 static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, const double* r,
-                         const double* c, double target_gap, const mdot_params& prm)
+                         const double* c, double target_gap, const mdot_params& prm, hipStream_t stream)
 {
     const int n = cost->n;
-    int rc = ensure_workspace(ctx, pb, n);
+    int rc = ensure_workspace(ctx, pb, n, stream);
     if (rc) return rc;
-    rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c);
+    rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c, stream);
     if (rc) return rc;
     double scale;
-    rc = resolve_scale(ctx, pb, cost, &scale);
+    rc = resolve_scale(ctx, pb, cost, &scale, stream);
     if (rc) return rc;
     if (scale != pb.host_work.scale) {
-        rc = bind_work(ctx, pb, n, cost, scale, r, c);
+        rc = bind_work(ctx, pb, n, cost, scale, r, c, stream);
         if (rc) return rc;
     }
     double hmin;
-    rc = intake_marginals(ctx, pb, n, &hmin);
+    rc = intake_marginals(ctx, pb, n, &hmin, stream);
     if (rc) return rc;
     const bool adaptive = !(prm.gamma_f > 0.0);
     DevParams& P = *ctx->h_prm;
@@ -395,11 +432,11 @@ static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
             HIPCHK(ctx, hipMalloc(&pb.proxy, count * 2));
             pb.proxy_bytes = count * 2;
         }
-        if (launch_to_f16(cost->data, cost->dtype, pb.proxy, count, ctx->d_scratch, kConvBlocks, ctx->stream))
+        if (launch_to_f16(cost->data, cost->dtype, pb.proxy, count, ctx->d_scratch, kConvBlocks, stream))
             return fail(ctx, MDOT_E_DEVICE, "conversion launch failed");
         HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, kConvBlocks * sizeof(double), hipMemcpyDeviceToHost,
-                                   ctx->stream));
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+                                   stream));
+        HIPCHK(ctx, hipStreamSynchronize(stream));
         double delta = 0.0;
         for (int b = 0; b < kConvBlocks; ++b) delta = std::max(delta, ctx->h_scratch[b]);
         const double scale = pb.host_work.scale;
@@ -407,18 +444,18 @@ static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
         mg = std::min(mg, P.gamma_f / prm.q);
         P.mix_gamma = (mg >= std::min(P.gamma_i, P.gamma_f)) ? mg : 0.0;
     }
-    HIPCHK(ctx, hipMemcpyAsync(pb.d_prm, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
-    if (launch_init(pb.d_work, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "init launch failed");
+    HIPCHK(ctx, hipMemcpyAsync(pb.d_prm, &P, sizeof P, hipMemcpyHostToDevice, stream));
+    if (launch_init(pb.d_work, stream)) return fail(ctx, MDOT_E_DEVICE, "init launch failed");
     if (P.mix_gamma > 0.0) {  // the first stages read the FP16 copy
         mdot_cost_desc proxy = *cost;
         proxy.dtype = MDOT_DT_F16;
         proxy.data = pb.proxy;
         const double scale = pb.host_work.scale;
-        rc = bind_work(ctx, pb, n, &proxy, scale, r, c);
+        rc = bind_work(ctx, pb, n, &proxy, scale, r, c, stream);
         if (rc) return rc;
     }
     // the pinned parameter block is reused by the next intake: let this copy land first
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(stream));
     return MDOT_OK;
 }
 
@@ -448,8 +485,8 @@ static void fill_result(const State& S, double seconds, mdot_result* res)
 static int ensure_graph(mdot_ctx* ctx, int n)
 {
     const Work& hw = ctx->main.host_work;
-    if (ctx->graph && ctx->graph_n == n && ctx->graph_kind == hw.cost_kind && ctx->graph_dtype == hw.dtype)
-        return MDOT_OK;
+    const int code = cost_code(hw);
+    if (ctx->graph && ctx->graph_n == n && ctx->graph_code == code) return MDOT_OK;
     if (ctx->graph) {
         (void)hipGraphExecDestroy(ctx->graph);
         ctx->graph = nullptr;
@@ -471,8 +508,7 @@ static int ensure_graph(mdot_ctx* ctx, int n)
         return fail(ctx, MDOT_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
     }
     ctx->graph_n = n;
-    ctx->graph_kind = hw.cost_kind;
-    ctx->graph_dtype = hw.dtype;
+    ctx->graph_code = code;
     return MDOT_OK;
 }
 
@@ -512,7 +548,11 @@ static int read_state(mdot_ctx* ctx, const ProblemBufs& pb)
 // ---------------------------------------------------------------- serving engine helpers
 static int rebuild_batch(mdot_ctx* ctx)
 {
-    BatchDesc& B = *ctx->h_batch;
+    // the other host buffer: its last upload was queued at least one rebuild ago, behind a chunk
+    // that has been read back since, so waiting for it does not wait for the chunk in flight
+    const int hbuf = ctx->hb_cur ^ 1;
+    HIPCHK(ctx, hipEventSynchronize(ctx->batch_ev[hbuf]));
+    BatchDesc& B = *ctx->h_batch[hbuf];
     memset(&B, 0, sizeof B);
     int nf = 0, m = 0;
     const Work* hw[kMaxBatch];
@@ -583,8 +623,10 @@ static int rebuild_batch(mdot_ctx* ctx)
     B.ngroups = ng;
     B.grp_prefix[ng] = nt;
     B.total_tiles = nt;
+    // stream order puts the upload behind the chunk in flight, which still reads the old one
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_batch, &B, sizeof B, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // h_batch is reused on the next rebuild
+    HIPCHK(ctx, hipEventRecord(ctx->batch_ev[hbuf], ctx->stream));
+    ctx->hb_cur = hbuf;
     ctx->batch_dirty = false;
     return MDOT_OK;
 }
@@ -595,15 +637,15 @@ static int rebuild_batch(mdot_ctx* ctx)
 // chunks).
 static int ensure_batch_graph(mdot_ctx* ctx)
 {
-    const BatchDesc& hb = *ctx->h_batch;
+    const BatchDesc& hb = *ctx->h_batch[ctx->hb_cur];
     const int fin = std::max(1, hb.total_fin);
     const bool big = ctx->batch_big;
     bool same = ctx->bgraph && ctx->bgraph_ncodes == hb.ncodes && ctx->bgraph_fin == fin && ctx->bgraph_big == big;
     for (int c = 0; same && c < hb.ncodes; ++c)
         same = ctx->bgraph_code[c] == hb.code[c] && ctx->bgraph_begin[c + 1] == hb.code_begin[c + 1];
     if (same) return MDOT_OK;
-    if (ctx->bgraph) {
-        (void)hipGraphExecDestroy(ctx->bgraph);
+    if (ctx->bgraph) {  // a chunk launched from it may still run: destroy it once that is read back
+        ctx->graveyard.emplace_back(ctx->bgraph, ctx->eng_seq);
         ctx->bgraph = nullptr;
     }
     hipStream_t cap;
@@ -632,12 +674,23 @@ static int ensure_batch_graph(mdot_ctx* ctx)
     return MDOT_OK;
 }
 
-static void release_slot(mdot_ctx* ctx, Slot& sl)
+// Destroy the replaced batch graphs whose last chunk has been read back (chunk `seq` and
+// everything launched before it have completed).
+static void bury_graphs(mdot_ctx* ctx, int64_t seq)
 {
-    ctx->bytes_in_use -= sl.footprint;
-    ctx->pool.push_back(sl.pb);
-    sl = Slot{};
-    ctx->batch_dirty = true;
+    for (size_t k = 0; k < ctx->graveyard.size();) {
+        if (ctx->graveyard[k].second <= seq) {
+            (void)hipGraphExecDestroy(ctx->graveyard[k].first);
+            ctx->graveyard.erase(ctx->graveyard.begin() + k);
+        } else {
+            ++k;
+        }
+    }
+}
+
+static void pool_put(mdot_ctx* ctx, const ProblemBufs& pb)
+{
+    ctx->pool.push_back(pb);
     // keep the pool bounded: free the smallest buffers beyond kMaxBatch entries
     while (ctx->pool.size() > (size_t)kMaxBatch) {
         auto it = std::min_element(ctx->pool.begin(), ctx->pool.end(),
@@ -645,6 +698,64 @@ static void release_slot(mdot_ctx* ctx, Slot& sl)
         free_bufs(*it);
         ctx->pool.erase(it);
     }
+}
+
+static size_t pool_bytes(const mdot_ctx* ctx)
+{
+    size_t b = 0;
+    for (const ProblemBufs& pb : ctx->pool) b += bufs_bytes(pb);
+    return b;
+}
+
+// Results of retiring solves whose state copies have completed (all of them with wait): the
+// result becomes pollable and the buffers return to the pool. Adds the number collected to
+// *collected (may be NULL).
+static int collect_retired(mdot_ctx* ctx, bool wait, int* collected)
+{
+    for (size_t k = 0; k < ctx->retiring.size();) {
+        Retiring& rt = ctx->retiring[k];
+        hipError_t e = wait ? hipEventSynchronize(ctx->ret_ev[rt.hs]) : hipEventQuery(ctx->ret_ev[rt.hs]);
+        if (e == hipErrorNotReady) {
+            ++k;
+            continue;
+        }
+        if (e != hipSuccess) return fail(ctx, MDOT_E_DEVICE, "retirement event failed: %s", hipGetErrorString(e));
+        mdot_result res;
+        fill_result(ctx->h_states[rt.hs], 0.0, &res);
+        ctx->finished[rt.ticket] = res;
+        ctx->bytes_in_use -= bufs_bytes(rt.pb);
+        pool_put(ctx, rt.pb);
+        ctx->free_hs.push_back(rt.hs);
+        ctx->retiring.erase(ctx->retiring.begin() + k);
+        if (collected) ++*collected;
+    }
+    return MDOT_OK;
+}
+
+// Retire the solve in `sl` (its chunk reported it finished): queue its finish kernel and the
+// copy of its state behind the work in flight, free the slot, keep the buffers until the copy
+// has completed.
+static int retire_slot(mdot_ctx* ctx, Slot& sl)
+{
+    if (ctx->free_hs.empty()) {  // every state buffer is taken: wait for the oldest retirement
+        int rc = collect_retired(ctx, true, nullptr);
+        if (rc) return rc;
+    }
+    const int hs = ctx->free_hs.back();
+    ctx->free_hs.pop_back();
+    if (launch_finish(sl.pb.d_work, sl.u_out, sl.v_out, ctx->stream))
+        return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_states + hs, sl.pb.host_work.st, sizeof(State), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->ret_ev[hs], ctx->stream));
+    Retiring rt;
+    rt.pb = sl.pb;
+    rt.ticket = sl.ticket;
+    rt.hs = hs;
+    ctx->retiring.push_back(rt);
+    sl = Slot{};
+    ctx->batch_dirty = true;
+    return MDOT_OK;
 }
 
 extern "C" {
@@ -676,13 +787,22 @@ int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_
                   hipSuccess &&
               hipHostGetDevicePointer((void**)&ctx->d_hdone, ctx->h_done, 0) == hipSuccess &&
               hipMalloc(&ctx->d_seq, 2 * sizeof(int)) == hipSuccess && hipMemset(ctx->d_seq, 0, 2 * sizeof(int)) == hipSuccess &&
-              hipHostMalloc(&ctx->h_batch, sizeof(BatchDesc), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_batch[0], sizeof(BatchDesc), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_batch[1], sizeof(BatchDesc), hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&ctx->h_states, kMaxBatch * sizeof(State), hipHostMallocDefault) == hipSuccess &&
               hipMalloc(&ctx->d_batch, sizeof(BatchDesc)) == hipSuccess &&
+              hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->batch_ev[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&ctx->batch_ev[1], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&ctx->eng_ev[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&ctx->eng_ev[1], hipEventDisableTiming) == hipSuccess &&
               hipEventCreate(&ctx->t0) == hipSuccess && hipEventCreate(&ctx->t1) == hipSuccess;
+    for (int k = 0; ok && k < kMaxBatch; ++k) {
+        ok = hipEventCreateWithFlags(&ctx->ret_ev[k], hipEventDisableTiming) == hipSuccess;
+        ctx->free_hs.push_back(kMaxBatch - 1 - k);
+    }
     if (!ok) {
         mdot_ctx_destroy(ctx);
         return MDOT_E_DEVICE;
@@ -697,18 +817,28 @@ int mdot_ctx_destroy(mdot_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
     if (ctx->bgraph) (void)hipGraphExecDestroy(ctx->bgraph);
+    for (auto& g : ctx->graveyard) (void)hipGraphExecDestroy(g.first);
     free_bufs(ctx->main);
     for (auto& sl : ctx->slots)
         if (sl.used) free_bufs(sl.pb);
+    for (auto& rt : ctx->retiring) free_bufs(rt.pb);
     for (auto& pb : ctx->pool) free_bufs(pb);
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
     if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
     if (ctx->h_state) (void)hipHostFree(ctx->h_state);
     if (ctx->h_prm) (void)hipHostFree(ctx->h_prm);
     if (ctx->h_done) (void)hipHostFree(ctx->h_done);
-    if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
+    for (auto& hb : ctx->h_batch)
+        if (hb) (void)hipHostFree(hb);
+    if (ctx->h_states) (void)hipHostFree(ctx->h_states);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    for (auto& e : ctx->batch_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->ret_ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->d_batch) (void)hipFree(ctx->d_batch);
     if (ctx->d_seq) (void)hipFree(ctx->d_seq);
     for (auto& e : ctx->ev)
@@ -736,13 +866,19 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
     if (rc) return rc;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     const int n = cost->n;
-    if (ctx->budget && problem_footprint(n) > ctx->budget)
-        return fail(ctx, MDOT_E_NOMEM, "workspace for n=%d needs %zu bytes > budget %zu", n, problem_footprint(n),
-                    ctx->budget);
+    // the single-problem buffers plus MIXED's FP16 copy, beside what the serving engine holds
+    const size_t need = problem_footprint(n) + (prm.precision == MDOT_PREC_MIXED ? (size_t)n * n * 2 : 0);
+    if (ctx->budget && need + ctx->bytes_in_use > ctx->budget) {
+        for (auto& pb : ctx->pool) free_bufs(pb);  // idle engine buffers go first
+        ctx->pool.clear();
+    }
+    if (ctx->budget && need + ctx->bytes_in_use > ctx->budget)
+        return fail(ctx, MDOT_E_NOMEM, "n=%d needs %zu bytes, budget %zu has %zu in use", n, need, ctx->budget,
+                    ctx->bytes_in_use);
     if (prm.precision == MDOT_PREC_MIXED &&
         (cost->kind != MDOT_COST_DENSE || (cost->dtype != MDOT_DT_F32 && cost->dtype != MDOT_DT_F64)))
         return fail(ctx, MDOT_E_ARG, "MIXED needs a dense FP32 or FP64 cost");
-    rc = setup_problem(ctx, ctx->main, cost, r, c, target_gap, prm);
+    rc = setup_problem(ctx, ctx->main, cost, r, c, target_gap, prm, ctx->stream);
     if (rc) return rc;
     HIPCHK(ctx, hipEventRecord(ctx->t0, ctx->stream));
     // hard cap on steps: every LSE sweep is one step, each stage adds at most a few more
@@ -754,7 +890,7 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
         rc = read_state(ctx, ctx->main);
         if (rc) return rc;
         if (ctx->h_state->done == 2) {
-            rc = bind_work(ctx, ctx->main, n, cost, ctx->main.host_work.scale, r, c);
+            rc = bind_work(ctx, ctx->main, n, cost, ctx->main.host_work.scale, r, c, ctx->stream);
             if (rc) return rc;
             static const int32_t kResume = 0;
             HIPCHK(ctx, hipMemcpyAsync(&ctx->main.host_work.st[0].done, &kResume, sizeof kResume,
@@ -783,15 +919,15 @@ static int standalone_setup(mdot_ctx* ctx, const mdot_cost_desc* cost, const dou
 {
     const int n = cost->n;
     ProblemBufs& pb = ctx->main;
-    int rc = ensure_workspace(ctx, pb, n);
+    int rc = ensure_workspace(ctx, pb, n, ctx->stream);
     if (rc) return rc;
-    rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c);
+    rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c, ctx->stream);
     if (rc) return rc;
     double scale;
-    rc = resolve_scale(ctx, pb, cost, &scale);
+    rc = resolve_scale(ctx, pb, cost, &scale, ctx->stream);
     if (rc) return rc;
     if (scale != pb.host_work.scale) {
-        rc = bind_work(ctx, pb, n, cost, scale, r, c);
+        rc = bind_work(ctx, pb, n, cost, scale, r, c, ctx->stream);
         if (rc) return rc;
     }
     const Work& w = pb.host_work;
@@ -936,31 +1072,62 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
     if (prm.precision == MDOT_PREC_MIXED &&
         (cost->kind != MDOT_COST_DENSE || (cost->dtype != MDOT_DT_F32 && cost->dtype != MDOT_DT_F64)))
         return fail(ctx, MDOT_E_ARG, "MIXED needs a dense FP32 or FP64 cost");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int n = cost->n;
+    const bool mixed = prm.precision == MDOT_PREC_MIXED;
+    const size_t proxy_need = mixed ? (size_t)n * n * 2 : 0;  // MIXED also holds an FP16 copy of the cost
+    const size_t fp = problem_footprint(n) + proxy_need;
+    if (ctx->budget && fp > ctx->budget)
+        return fail(ctx, MDOT_E_NOMEM, "n=%d needs %zu bytes > budget %zu", n, fp, ctx->budget);
+    rc = collect_retired(ctx, false, nullptr);  // finished retirements return their buffers first
+    if (rc) return rc;
     int active = 0;
     for (const Slot& sl : ctx->slots) active += sl.used;
-    // MIXED also holds an FP16 copy of the cost
-    const size_t fp = problem_footprint(cost->n) +
-                      (prm.precision == MDOT_PREC_MIXED ? (size_t)cost->n * cost->n * 2 : 0);
-    if (ctx->budget && fp > ctx->budget)
-        return fail(ctx, MDOT_E_NOMEM, "n=%d needs %zu bytes > budget %zu", cost->n, fp, ctx->budget);
-    if (active == kMaxBatch || (ctx->budget && ctx->bytes_in_use + fp > ctx->budget))
-        return fail(ctx, MDOT_E_BUSY, "no free slot or HBM budget (%zu of %zu bytes in use)", ctx->bytes_in_use,
-                    ctx->budget);
-    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (active == kMaxBatch) return fail(ctx, MDOT_E_BUSY, "no free slot (%d solves in flight)", active);
+    // reuse the smallest pooled workspace that fits. Every buffer the engine holds counts against
+    // the budget at its actual size: solves in flight, retiring and pooled.
+    auto pick = [&]() {
+        int best = -1;
+        for (int k = 0; k < (int)ctx->pool.size(); ++k)
+            if (ctx->pool[k].cap_n >= n && (best < 0 || ctx->pool[k].cap_n < ctx->pool[best].cap_n)) best = k;
+        return best;
+    };
+    auto held_after = [&](int cand) {
+        const size_t held = ctx->bytes_in_use + pool_bytes(ctx);
+        if (cand < 0) return held + fp;
+        const ProblemBufs& pb = ctx->pool[cand];
+        return held - bufs_bytes(pb) + sizeof(Control) + pb.ws_bytes + std::max(pb.proxy_bytes, proxy_need);
+    };
+    int best = pick();
+    if (ctx->budget && held_after(best) > ctx->budget) {
+        // the pool is idle memory: free it (all but the candidate, then the candidate too) before refusing
+        for (int k = (int)ctx->pool.size() - 1; k >= 0; --k) {
+            if (k == best) continue;
+            free_bufs(ctx->pool[k]);
+            ctx->pool.erase(ctx->pool.begin() + k);
+            if (best > k) --best;
+        }
+        if (held_after(best) > ctx->budget && best >= 0) {
+            free_bufs(ctx->pool[best]);
+            ctx->pool.erase(ctx->pool.begin() + best);
+            best = -1;
+        }
+        if (held_after(best) > ctx->budget)
+            return fail(ctx, MDOT_E_BUSY, "HBM budget: %zu of %zu bytes in use, n=%d needs %zu", ctx->bytes_in_use,
+                        ctx->budget, n, fp);
+    }
     int s = 0;
     while (ctx->slots[s].used) ++s;
     Slot& sl = ctx->slots[s];
-    // reuse the smallest pooled workspace that fits
-    int best = -1;
-    for (int k = 0; k < (int)ctx->pool.size(); ++k)
-        if (ctx->pool[k].cap_n >= cost->n && (best < 0 || ctx->pool[k].cap_n < ctx->pool[best].cap_n)) best = k;
     if (best >= 0) {
         sl.pb = ctx->pool[best];
         ctx->pool.erase(ctx->pool.begin() + best);
     }
-    rc = setup_problem(ctx, sl.pb, cost, r, c, target_gap, prm);
+    // intake on the side stream: the buffers are idle (fresh, or pooled after their retirement
+    // completed), so it need not wait for the chunk in flight on the context stream
+    rc = setup_problem(ctx, sl.pb, cost, r, c, target_gap, prm, ctx->side);
     if (rc) {
-        if (sl.pb.d_work) ctx->pool.push_back(sl.pb);
+        if (sl.pb.d_work) pool_put(ctx, sl.pb);
         sl = Slot{};
         return rc;
     }
@@ -968,12 +1135,12 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
     sl.ticket = ctx->next_ticket++;
     sl.u_out = u_out;
     sl.v_out = v_out;
-    sl.footprint = fp;
+    sl.footprint = bufs_bytes(sl.pb);
     sl.exact = *cost;
     sl.r = r;
     sl.c = c;
     sl.resumed_at = -1;
-    ctx->bytes_in_use += fp;
+    ctx->bytes_in_use += sl.footprint;
     ctx->batch_dirty = true;
     *ticket = sl.ticket;
     return MDOT_OK;
@@ -981,9 +1148,10 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
 
 // Read back an engine chunk: retire the solves it finished (their slots may already hold newer
 // solves, admitted after the chunk was launched: those are told apart by the ticket).
-static int process_chunk(mdot_ctx* ctx, int buf, int* completed)
+static int process_chunk(mdot_ctx* ctx, int buf)
 {
     HIPCHK(ctx, hipEventSynchronize(ctx->eng_ev[buf]));
+    bury_graphs(ctx, ctx->chunk_seq[buf]);
     const int* done = ctx->h_done + 2 + buf * kMaxBatch;
     for (int m = 0; m < ctx->chunk_m[buf]; ++m) {
         Slot& sl = ctx->slots[ctx->chunk_slot[buf][m]];
@@ -991,7 +1159,7 @@ static int process_chunk(mdot_ctx* ctx, int buf, int* completed)
         if (done[m] == 2) {  // MIXED: paused at the switch to the exact cost
             // the chunk launched before the resume below still reports the pause: skip it
             if (ctx->chunk_seq[buf] <= sl.resumed_at) continue;
-            int rc = bind_work(ctx, sl.pb, sl.exact.n, &sl.exact, sl.pb.host_work.scale, sl.r, sl.c);
+            int rc = bind_work(ctx, sl.pb, sl.exact.n, &sl.exact, sl.pb.host_work.scale, sl.r, sl.c, ctx->stream);
             if (rc) return rc;
             // chunks have an even number of steps, so the next step reads state slot 0
             static const int32_t kResume = 0;
@@ -1001,15 +1169,8 @@ static int process_chunk(mdot_ctx* ctx, int buf, int* completed)
             ctx->batch_dirty = true;  // its sweep group now needs the exact cost's kernel instance
             continue;
         }
-        if (launch_finish(sl.pb.d_work, sl.u_out, sl.v_out, ctx->stream))
-            return fail(ctx, MDOT_E_DEVICE, "finish launch failed");
-        int rc = read_state(ctx, sl.pb);
+        int rc = retire_slot(ctx, sl);
         if (rc) return rc;
-        mdot_result res;
-        fill_result(*ctx->h_state, 0.0, &res);
-        ctx->finished[sl.ticket] = res;
-        release_slot(ctx, sl);
-        ++*completed;
     }
     return MDOT_OK;
 }
@@ -1020,12 +1181,13 @@ int mdot_run(mdot_ctx* ctx, int steps, int* n_done)
     if (n_done) *n_done = 0;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     int completed = 0;
+    int rc = collect_retired(ctx, false, &completed);
+    if (rc) return rc;
     const int chunks = std::max(1, (steps + kBatchChunk - 1) / kBatchChunk);
     for (int ch = 0; ch < chunks; ++ch) {
         int active = 0;
         for (const Slot& sl : ctx->slots) active += sl.used;
         if (active == 0 && ctx->eng_pending < 0) break;
-        int rc;
         if (active > 0) {  // launch the next chunk before reading the previous one back
             if (ctx->batch_dirty) {
                 rc = rebuild_batch(ctx);
@@ -1048,17 +1210,22 @@ int mdot_run(mdot_ctx* ctx, int steps, int* n_done)
             HIPCHK(ctx, hipGraphLaunch(ctx->bgraph, ctx->stream));
             HIPCHK(ctx, hipEventRecord(ctx->eng_ev[buf], ctx->stream));
             if (ctx->eng_pending >= 0) {
-                rc = process_chunk(ctx, ctx->eng_pending, &completed);
+                rc = process_chunk(ctx, ctx->eng_pending);
                 if (rc) return rc;
             }
             ctx->eng_pending = buf;
             ctx->eng_next = buf ^ 1;
         } else {  // nothing left to advance: read the last chunk back
-            rc = process_chunk(ctx, ctx->eng_pending, &completed);
+            rc = process_chunk(ctx, ctx->eng_pending);
             if (rc) return rc;
             ctx->eng_pending = -1;
         }
     }
+    // results whose copies have landed; with nothing else in flight, wait for the rest
+    bool idle = ctx->eng_pending < 0;
+    for (const Slot& sl : ctx->slots) idle &= !sl.used;
+    rc = collect_retired(ctx, idle, &completed);
+    if (rc) return rc;
     if (n_done) *n_done = completed;
     return MDOT_OK;
 }
@@ -1073,6 +1240,16 @@ int mdot_poll(mdot_ctx* ctx, uint64_t ticket, int wait, mdot_result* res)
             ctx->finished.erase(it);
             return MDOT_OK;
         }
+        const Retiring* rt = nullptr;
+        for (const Retiring& x : ctx->retiring)
+            if (x.ticket == ticket) rt = &x;
+        if (rt) {  // finished: its result lands with the copy queued at its retirement
+            if (wait) HIPCHK(ctx, hipEventSynchronize(ctx->ret_ev[rt->hs]));
+            int rc = collect_retired(ctx, false, nullptr);
+            if (rc) return rc;
+            if (!wait && !ctx->finished.count(ticket)) return 2;
+            continue;
+        }
         bool inflight = false;
         for (const Slot& sl : ctx->slots) inflight |= (sl.used && sl.ticket == ticket);
         if (!inflight) return fail(ctx, MDOT_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
@@ -1085,7 +1262,9 @@ int mdot_poll(mdot_ctx* ctx, uint64_t ticket, int wait, mdot_result* res)
 int mdot_inflight(mdot_ctx* ctx, int* n_active, size_t* bytes_in_use)
 {
     if (!ctx) return MDOT_E_ARG;
-    int a = 0;
+    int rc = collect_retired(ctx, false, nullptr);
+    if (rc) return rc;
+    int a = (int)ctx->retiring.size();  // finished but their results not yet copied out
     for (const Slot& sl : ctx->slots) a += sl.used;
     if (n_active) *n_active = a;
     if (bytes_in_use) *bytes_in_use = ctx->bytes_in_use;

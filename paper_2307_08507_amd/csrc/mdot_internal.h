@@ -187,6 +187,8 @@ int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, doubl
 int cost_code_of(int cost_kind, int dtype);
 // The planar (d <= 2) instance of a point cost code; other codes are returned unchanged.
 int cost_code_planar(int cost_code);
+// The sweep kernel instance a single-problem launch of hw takes (its cost code, planar for d <= 2).
+int cost_code(const Work& hw);
 // big: some problem in flight has n > 8192 (the finalize instance for fin_per(n) = 32)
 int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, bool big, void* stream);
 // End-of-chunk done flags into host-visible memory: chunk number *seq (a device counter, advanced

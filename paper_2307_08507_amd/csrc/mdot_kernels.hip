@@ -2010,7 +2010,7 @@ int cost_code_planar(int cc)
 }
 
 // Kernel instance of a single-problem launch: planar point clouds take the planar instance.
-static int cost_code(const Work& w)
+int cost_code(const Work& w)
 {
     const int cc = cost_code_of(w.cost_kind, w.dtype);
     return w.d <= 2 ? cost_code_planar(cc) : cc;

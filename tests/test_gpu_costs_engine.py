@@ -97,20 +97,63 @@ def test_lse2_point_costs(ctx, n, d, kind, prec):
 
 @pytest.mark.parametrize("kind", ["sqeuclid", "l1"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_planar_points_match_padded_3d(ctx, kind, prec):
+def test_planar_points_match_padded_3d(kind, prec):
     # Clouds with d <= 2 take a kernel instance without the third coordinate's arithmetic. The
     # same points with an explicit zero third coordinate take the general one; every term the
-    # planar instance leaves out is an exact zero, so the sweeps must agree bit for bit.
+    # planar instance leaves out is an exact zero, so the sweeps must agree bit for bit. Each
+    # call runs on a fresh context, so neither can replay the other's captured step graph.
     n = 700
     print(f"planar vs padded points n={n} {kind} prec={prec}", flush=True)
     XY2, C64, scale = _points(n, 2, 31, kind)
     XY3 = torch.cat([XY2.view(2 * n, 2), torch.zeros(2 * n, 1, device="cuda")], 1).contiguous().view(-1)
     gamma = 300.0
     u, v = _potentials(n, 4, C64, gamma)
-    lr2, lc2 = _lse2(ctx, M.point_cost(XY2, n, 2, kind, scale=scale), u, v, gamma, prec)
-    lr3, lc3 = _lse2(ctx, M.point_cost(XY3, n, 3, kind, scale=scale), u, v, gamma, prec)
+    out = []
+    for XY, d in ((XY2, 2), (XY3, 3)):
+        c = M.Context(0)
+        try:
+            out.append(_lse2(c, M.point_cost(XY, n, d, kind, scale=scale), u, v, gamma, prec))
+        finally:
+            c.close()
+    (lr2, lc2), (lr3, lc3) = out
     np.testing.assert_array_equal(lr2, lr3)
     np.testing.assert_array_equal(lc2, lc3)
+    lr_o, lc_o = O.lse2(C64, u, v, gamma)
+    tol = 1e-11 * gamma if prec == "f64" else 2e-6
+    np.testing.assert_allclose(lr3, lr_o, rtol=0, atol=tol)
+    np.testing.assert_allclose(lc3, lc_o, rtol=0, atol=tol)
+
+
+@pytest.mark.parametrize("kind", ["sqeuclid", "l1"])
+def test_point_dimension_change_on_one_context(kind):
+    # Regression: a context caches its captured step graph, whose sweep kernel instance depends
+    # on the point dimension (planar for d <= 2). Interleaving planar and d = 3 clouds of the
+    # same n on one context must run the right instance every time: each result is checked
+    # against the oracle on clouds whose third coordinate is non-zero.
+    n = 640
+    print(f"d=2 / d=3 interleaved on one context n={n} {kind}", flush=True)
+    c = M.Context(0)
+    try:
+        for rep in range(2):
+            for d in (2, 3, 2, 3):
+                XY, C64, scale = _points(n, d, 90 + 7 * d + rep, kind)
+                if d == 3:
+                    assert float(XY.view(2 * n, 3)[:, 2].abs().max()) > 0.1
+                gamma = 250.0
+                u, v = _potentials(n, 5 + d, C64, gamma)
+                lr, lc = _lse2(c, M.point_cost(XY, n, d, kind, scale=scale), u, v, gamma, "f32")
+                lr_o, lc_o = O.lse2(C64, u, v, gamma)
+                np.testing.assert_allclose(lr, lr_o, rtol=0, atol=2e-6)
+                np.testing.assert_allclose(lc, lc_o, rtol=0, atol=2e-6)
+                r = W.dirichlet_marginal(n, 3 + d)
+                cc = W.dirichlet_marginal(n, 4 + d)
+                ub, lb, me = c.round_certify(M.point_cost(XY, n, d, kind, scale=scale), dev(u), dev(v), gamma,
+                                             dev(r), dev(cc))
+                ub_o, lb_o, _, _ = O.round_certify(C64, u, v, gamma, r, cc)
+                assert ub == pytest.approx(ub_o, rel=1e-11, abs=1e-14)
+                assert lb == pytest.approx(lb_o, rel=1e-11, abs=1e-14)
+    finally:
+        c.close()
 
 
 def test_point_cost_default_scale(ctx):
