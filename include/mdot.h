@@ -76,6 +76,7 @@ typedef enum { MDOT_DT_F64 = 0, MDOT_DT_F32 = 1, MDOT_DT_F16 = 2, MDOT_DT_BF16 =
 typedef enum { MDOT_PREC_F64 = 0, MDOT_PREC_F32 = 1, MDOT_PREC_MIXED = 2 } mdot_precision;
 
 #define MDOT_MAX_N 65536 /* largest n; larger sizes return MDOT_E_ARG */
+#define MDOT_NOALLOC_MAX_N 4096 /* largest n of mdot_lse2_noalloc */
 
 typedef struct {
     int32_t n;            /* problem size, 1..MDOT_MAX_N */
@@ -158,6 +159,25 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
  * precision: MDOT_PREC_F32 or MDOT_PREC_F64. Synchronous. */
 int mdot_lse2(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
               const double* shift, mdot_precision precision, double* lr_out, double* lc_out);
+
+/* Allocation-free variant of mdot_lse2, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and return values as mdot_lse2 (the same kernels run; lr_out and
+ * lc_out are bit-identical to mdot_lse2's), with these limits:
+ *   - n <= MDOT_NOALLOC_MAX_N (4096), else MDOT_E_ARG;
+ *   - cost->scale > 0 for point costs too (scale 0 asks for a max pass, which this call does
+ *     not run), else MDOT_E_ARG.
+ * Its partials, state and control block live in one static device array per GPU (about
+ * 9.7 MB, held from library load until the process ends), not in the context's workspace;
+ * the context supplies only its stream and the pinned host block created by mdot_ctx_create.
+ * It calls no hipMalloc/hipFree and no allocating library routine. Every call on one GPU
+ * uses that GPU's array, so calls that overlap on one GPU (two contexts or threads, or
+ * streams that run concurrently) race and must be serialised by the caller; the array keeps
+ * the last call's contents, and the call clears what must start at zero itself.
+ * Synchronous. */
+int mdot_lse2_noalloc(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v,
+                      double gamma, const double* shift, mdot_precision precision, double* lr_out,
+                      double* lc_out);
 
 /* Round (Alg. 3) and certify the plan P(u, v; gamma) without materialising it: two sweeps
  * give UB = <G, C> with G = Round(P, r, c), and LB = the larger double c-transform bound of

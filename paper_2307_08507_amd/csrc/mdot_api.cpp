@@ -85,6 +85,10 @@ struct mdot_ctx {
     size_t budget = 0;
     std::string err;
     ProblemBufs main;             // single solves and the standalone entry points
+    // mdot_lse2_noalloc: its buffers are borrowed from the library's static device array, whose
+    // address on this device was taken at context creation
+    ProblemBufs fixed;
+    unsigned char* d_fixed = nullptr;
     State* h_state = nullptr;     // pinned
     // done flags written by the last kernel of each graph chunk (pinned, mapped, fine-grained):
     // 2 for the single solves, then 2 x kMaxBatch for the engine; d_hdone is the device alias
@@ -161,26 +165,13 @@ static int fail(mdot_ctx* ctx, int code, const char* fmt, ...)
 static inline int tiles_r(int n) { return (n + kBR - 1) / kBR; }
 static inline int tiles_c(int n) { return (n + kBC - 1) / kBC; }
 
-// Bytes of workspace for size n (see Work in mdot_internal.h).
+// Bytes of workspace for size n (see Work and ws_offset in mdot_internal.h); out_offsets, if
+// given, receives the kWsBuffers + 1 buffer offsets.
 static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
 {
-    const size_t nrt = tiles_r(n), nct = tiles_c(n), N = n;
-    const size_t counts[] = {
-        2 * N, 2 * N, 2 * N, 2 * N, 2 * N, 2 * N, 2 * N, 2 * N, 2 * N,  // rt logt z zprev zbest p g lz lzt
-        N, N, N,                                                      // xr yc errc
-        2 * N, 2 * N,                                                 // gp fpp
-        nct * N, nrt * N, nct * N, nct * N,                           // rowpart colpart rowpart2 rowpart3
-        2 * nct * N, 2 * nrt * N,                                     // rowmin colmin
-        nrt,                                                          // tshift
-    };
-    size_t off = 0;
-    const int k = sizeof(counts) / sizeof(counts[0]);
-    for (int i = 0; i < k; ++i) {
-        if (out_offsets) out_offsets[i] = off;
-        off += ((counts[i] * sizeof(double) + 255) / 256) * 256;
-    }
-    if (out_offsets) out_offsets[k] = off;
-    return off;
+    if (out_offsets)
+        for (int i = 0; i <= kWsBuffers; ++i) out_offsets[i] = ws_offset(i, (size_t)n);
+    return ws_offset(kWsBuffers, (size_t)n);
 }
 
 static size_t problem_footprint(int n)
@@ -334,15 +325,16 @@ static int check_params(mdot_ctx* ctx, const mdot_params& prm, double target_gap
 }
 
 // Range of the raw cost (one pass) -> resolved scale; MDOT_E_COST if scale*raw leaves [0,1].
+// dpart: device buffer of 2 * tiles partials (the context's scratch unless given).
 static int resolve_scale(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, double* scale_out,
-                         hipStream_t stream)
+                         hipStream_t stream, double* dpart = nullptr)
 {
     const int n = cost->n;
     const int tiles = tiles_r(n) * tiles_c(n);
-    if (launch_cost_range(pb.host_work, pb.d_work, ctx->d_scratch, stream))
+    if (!dpart) dpart = ctx->d_scratch;
+    if (launch_cost_range(pb.host_work, pb.d_work, dpart, stream))
         return fail(ctx, MDOT_E_DEVICE, "cost range kernel launch failed");
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 2 * tiles * sizeof(double), hipMemcpyDeviceToHost,
-                               stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, dpart, 2 * tiles * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHK(ctx, hipStreamSynchronize(stream));
     double lo = INFINITY, hi = -INFINITY;
     bool nonfinite = false;
@@ -803,6 +795,12 @@ int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_
         ok = hipEventCreateWithFlags(&ctx->ret_ev[k], hipEventDisableTiming) == hipSuccess;
         ctx->free_hs.push_back(kMaxBatch - 1 - k);
     }
+    // address of the static array of mdot_lse2_noalloc on this device (taken once per device),
+    // and the host and device scratch its cost-range pass uses, so that call allocates nothing
+    void* fixed = nullptr;
+    if (ok) ok = noalloc_scratch(device, &fixed) == 0 && fixed != nullptr;
+    if (ok) ctx->d_fixed = static_cast<unsigned char*>(fixed);
+    if (ok) ok = ensure_scratch(ctx, kNoAllocMaxN) == MDOT_OK;
     if (!ok) {
         mdot_ctx_destroy(ctx);
         return MDOT_E_DEVICE;
@@ -912,31 +910,37 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
     return S.status;
 }
 
-// Set up `main` for a standalone sweep sequence (one LSE, or Round + certificate).
-static int standalone_setup(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
-                            const double* shift, int exp64, int kind, const double* u_prev, const double* v_prev,
-                            double gamma_prev, const double* r, const double* c)
+// Set up pb for a standalone sweep sequence (one LSE, or Round + certificate). pb is the
+// context's `main` (workspace allocated on demand) or its `fixed` buffers (borrowed from the
+// static array: nothing is allocated, and the cost range partials go to `dpart` in that array).
+static int standalone_setup(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, const double* u,
+                            const double* v, double gamma, const double* shift, int exp64, int kind,
+                            const double* u_prev, const double* v_prev, double gamma_prev, const double* r,
+                            const double* c, double* dpart = nullptr)
 {
     const int n = cost->n;
-    ProblemBufs& pb = ctx->main;
-    int rc = ensure_workspace(ctx, pb, n, ctx->stream);
-    if (rc) return rc;
-    rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c, ctx->stream);
+    if (!pb.borrowed) {
+        int rc = ensure_workspace(ctx, pb, n, ctx->stream);
+        if (rc) return rc;
+    }
+    int rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c, ctx->stream);
     if (rc) return rc;
     double scale;
-    rc = resolve_scale(ctx, pb, cost, &scale, ctx->stream);
+    rc = resolve_scale(ctx, pb, cost, &scale, ctx->stream, dpart);
     if (rc) return rc;
     if (scale != pb.host_work.scale) {
         rc = bind_work(ctx, pb, n, cost, scale, r, c, ctx->stream);
         if (rc) return rc;
     }
     const Work& w = pb.host_work;
+    // rt .. lzt and the n-vectors xr, yc, errc (the vectors these sweeps read besides z and lz)
+    // start at zero: a fill kernel, since the static array keeps the previous call's contents
+    size_t off[kWsBuffers + 1];
+    workspace_bytes(n, off);
+    if (launch_fill(w.rt, off[12] / sizeof(double), 0.0, ctx->stream))
+        return fail(ctx, MDOT_E_DEVICE, "fill launch failed");
     HIPCHK(ctx, hipMemcpyAsync(w.z, u, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(w.z + n, v, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(w.p, 0, 2 * n * sizeof(double), ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(w.g, 0, 2 * n * sizeof(double), ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(w.rt, 0, 2 * n * sizeof(double), ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(w.logt, 0, 2 * n * sizeof(double), ctx->stream));
     if (shift) HIPCHK(ctx, hipMemcpyAsync(w.lz, shift, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     const bool ext = u_prev && v_prev && gamma > gamma_prev;
     if (ext) {
@@ -975,7 +979,7 @@ int mdot_lse2(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const 
     if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(ctx, MDOT_E_ARG, "bad gamma %g", gamma);
     if (precision != MDOT_PREC_F32 && precision != MDOT_PREC_F64) return fail(ctx, MDOT_E_ARG, "bad precision");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    rc = standalone_setup(ctx, cost, u, v, gamma, shift, precision == MDOT_PREC_F64, 1, nullptr, nullptr, 0.0, nullptr,
+    rc = standalone_setup(ctx, ctx->main, cost, u, v, gamma, shift, precision == MDOT_PREC_F64, 1, nullptr, nullptr, 0.0, nullptr,
                           nullptr);
     if (rc) return rc;
     rc = run_steps(ctx, cost->n, 1);
@@ -984,6 +988,46 @@ int mdot_lse2(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const 
     if (rc) return rc;
     if (!ctx->h_state->done) return fail(ctx, MDOT_E_DEVICE, "standalone sweep did not finish");
     const Work& w = ctx->main.host_work;
+    const int n = cost->n;
+    HIPCHK(ctx, hipMemcpyAsync(lr_out, w.lzt, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(lc_out, w.lzt + n, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return ctx->h_state->status;
+}
+
+int mdot_lse2_noalloc(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
+                      const double* shift, mdot_precision precision, double* lr_out, double* lc_out)
+{
+    if (!ctx) return MDOT_E_ARG;
+    int rc = check_cost_desc(ctx, cost);
+    if (rc) return rc;
+    if (cost->n > kNoAllocMaxN)
+        return fail(ctx, MDOT_E_ARG, "mdot_lse2_noalloc: n=%d exceeds its maximum n=%d (MDOT_NOALLOC_MAX_N)", cost->n,
+                    kNoAllocMaxN);
+    if (!u || !v || !lr_out || !lc_out) return fail(ctx, MDOT_E_ARG, "NULL vector pointer");
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(ctx, MDOT_E_ARG, "bad gamma %g", gamma);
+    if (precision != MDOT_PREC_F32 && precision != MDOT_PREC_F64) return fail(ctx, MDOT_E_ARG, "bad precision");
+    if (!ctx->d_fixed) return fail(ctx, MDOT_E_DEVICE, "no static scratch on device %d", ctx->device);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    ProblemBufs& pb = ctx->fixed;
+    pb.borrowed = true;
+    pb.d_work = reinterpret_cast<Work*>(ctx->d_fixed);
+    pb.d_prm = &reinterpret_cast<Control*>(ctx->d_fixed)->prm;
+    pb.ws = ctx->d_fixed + kNoAllocCtl;
+    pb.ws_bytes = workspace_bytes(cost->n);
+    pb.cap_n = kNoAllocMaxN;
+    double* dpart = reinterpret_cast<double*>(ctx->d_fixed + kNoAllocCtl + ws_offset(kWsBuffers, kNoAllocMaxN));
+    rc = standalone_setup(ctx, pb, cost, u, v, gamma, shift, precision == MDOT_PREC_F64, 1, nullptr, nullptr, 0.0,
+                          nullptr, nullptr, dpart);
+    if (rc) return rc;
+    // at most three steps do work (row-max pass, LSE sweep, its FP64 re-run); later steps carry
+    // the finished state over, and after an even number of steps slot 0 holds the newest state
+    const Work& w = pb.host_work;
+    for (int k = 0; k < 4; ++k)
+        if (launch_step(w, pb.d_work, k & 1, ctx->stream)) return fail(ctx, MDOT_E_DEVICE, "step launch failed");
+    rc = read_state(ctx, pb);
+    if (rc) return rc;
+    if (!ctx->h_state->done) return fail(ctx, MDOT_E_DEVICE, "standalone sweep did not finish");
     const int n = cost->n;
     HIPCHK(ctx, hipMemcpyAsync(lr_out, w.lzt, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(lc_out, w.lzt + n, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
@@ -1001,7 +1045,7 @@ int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* 
     if (!u || !v || !r || !c || !ub || !lb || !marg_err) return fail(ctx, MDOT_E_ARG, "NULL pointer argument");
     if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(ctx, MDOT_E_ARG, "bad gamma %g", gamma);
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    rc = standalone_setup(ctx, cost, u, v, gamma, nullptr, 1, 2, u_prev, v_prev, gamma_prev, r, c);
+    rc = standalone_setup(ctx, ctx->main, cost, u, v, gamma, nullptr, 1, 2, u_prev, v_prev, gamma_prev, r, c);
     if (rc) return rc;
     rc = run_steps(ctx, cost->n, 1);
     if (rc) return rc;
@@ -1025,7 +1069,7 @@ int mdot_bench_sweep(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u,
     HIPCHK(ctx, hipSetDevice(ctx->device));
     const int exp64 = precision == MDOT_PREC_F64;
     // exact log-sums first (max pass + LSE pass) so the timed sweeps run with converged shifts
-    rc = standalone_setup(ctx, cost, u, v, gamma, nullptr, exp64, 1, nullptr, nullptr, 0.0, nullptr, nullptr);
+    rc = standalone_setup(ctx, ctx->main, cost, u, v, gamma, nullptr, exp64, 1, nullptr, nullptr, 0.0, nullptr, nullptr);
     if (rc) return rc;
     rc = run_steps(ctx, cost->n, 1);
     if (rc) return rc;

@@ -171,6 +171,45 @@ struct BatchDesc {
     int32_t code_begin[kMaxCodes + 1];
 };
 
+// Workspace layout of one problem (the vectors of Work, in the order bind_work assigns them):
+// FP64 counts per buffer, each buffer rounded up to 256 bytes.
+constexpr int kWsBuffers = 21;
+constexpr size_t ws_count(int b, size_t n)
+{
+    const size_t nrt = (n + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
+    return b < 9 ? 2 * n                      // rt logt z zprev zbest p g lz lzt
+         : b < 12 ? n                         // xr yc errc
+         : b < 14 ? 2 * n                     // gp fpp
+         : b == 14 || b == 16 || b == 17 ? nct * n  // rowpart rowpart2 rowpart3
+         : b == 15 ? nrt * n                  // colpart
+         : b == 18 ? 2 * nct * n              // rowmin
+         : b == 19 ? 2 * nrt * n              // colmin
+         : nrt;                               // tshift
+}
+constexpr size_t ws_round(size_t bytes) { return (bytes + 255) / 256 * 256; }
+// Byte offset of buffer b (b = kWsBuffers gives the total).
+constexpr size_t ws_offset(int b, size_t n)
+{
+    size_t off = 0;
+    for (int i = 0; i < b; ++i) off += ws_round(ws_count(i, n) * sizeof(double));
+    return off;
+}
+
+// The allocation-free LSE entry point keeps its control block, workspace and cost-range
+// partials in one static device array of kNoAllocBytes per device: the control block first,
+// then the workspace of n = kNoAllocMaxN, then 2 partials per tile of that n.
+constexpr int kNoAllocMaxN = MDOT_NOALLOC_MAX_N;
+constexpr size_t kNoAllocCtl = ws_round(sizeof(Control));
+constexpr size_t kNoAllocRange =
+    ws_round(2 * sizeof(double) * ((kNoAllocMaxN + kBR - 1) / kBR) * ((kNoAllocMaxN + kBC - 1) / kBC));
+constexpr size_t kNoAllocBytes = kNoAllocCtl + ws_offset(kWsBuffers, kNoAllocMaxN) + kNoAllocRange;
+// Device address of that array on the current device (hipGetSymbolAddress, taken once per
+// device and cached). Returns 0 or a hipError_t code.
+int noalloc_scratch(int device, void** out);
+// Fill count doubles at dst with val (a kernel, so the fill is an ordinary kernel node if the
+// caller's stream is being captured).
+int launch_fill(double* dst, size_t count, double val, void* stream);
+
 // Host-side launchers (mdot_kernels.hip). `hw` is the host copy of the Work struct (sizes
 // and cost type pick the grid and the kernel instance), `wd` its device copy.
 int launch_step(const Work& hw, const Work* wd, int parity, void* stream);  // sweep, finalize, decide

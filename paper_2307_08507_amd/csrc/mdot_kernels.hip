@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "mdot_internal.h"
@@ -2132,6 +2134,48 @@ int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, doubl
 int launch_finish(const Work* wd, double* u_out, double* v_out, void* stream)
 {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, (hipStream_t)stream, wd, u_out, v_out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------------ allocation-free entry point
+// Control block and workspace of mdot_lse2_noalloc: one array per device, loaded with the code
+// object and held until the process ends. In host code `scratch` names a host-side stand-in,
+// not the device array: host code only ever uses the address noalloc_scratch() returns.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+int noalloc_scratch(int device, void** out)
+{
+    if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return (int)e;
+        if (cur != device) return (int)hipErrorInvalidDevice;  // the caller makes `device` current
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!ptr) return (int)hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return 0;
+}
+
+__global__ void __launch_bounds__(256) k_fill(double* __restrict__ dst, size_t count, double val)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) dst[i] = val;
+}
+
+int launch_fill(double* dst, size_t count, double val, void* stream)
+{
+    if (count == 0) return 0;
+    const size_t blocks = std::min<size_t>((count + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, dst, count, val);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

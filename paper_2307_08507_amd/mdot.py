@@ -71,6 +71,7 @@ def lib():
         L.mdot_solve.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, ct.POINTER(Params), dp, dp,
                                  ct.POINTER(Result)]
         L.mdot_lse2.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, dp, ct.c_int, dp, dp]
+        L.mdot_lse2_noalloc.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, dp, ct.c_int, dp, dp]
         L.mdot_round_certify.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, dp, dp, ct.c_double,
                                          dp, dp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                                          ct.POINTER(ct.c_double)]
@@ -204,6 +205,14 @@ class Context:
         prec = PREC_F64 if precision == "f64" else PREC_F32
         rc = lib().mdot_lse2(self._h, ct.byref(cost), _ptr(u), _ptr(v), float(gamma), _ptr(shift), prec,
                              _ptr(lr_out), _ptr(lc_out))
+        return self._check(rc)
+
+    def lse2_noalloc(self, cost: CostDesc, u, v, gamma: float, lr_out, lc_out, shift=None,
+                     precision: str = "f32") -> int:
+        """mdot_lse2 without device allocation (n <= MDOT_NOALLOC_MAX_N = 4096)."""
+        prec = PREC_F64 if precision == "f64" else PREC_F32
+        rc = lib().mdot_lse2_noalloc(self._h, ct.byref(cost), _ptr(u), _ptr(v), float(gamma), _ptr(shift), prec,
+                                     _ptr(lr_out), _ptr(lc_out))
         return self._check(rc)
 
     # ---- serving: continuous batching
