@@ -100,8 +100,24 @@ typedef struct {
     int32_t max_pncg_iters;   /* per stage (default 100000) */
     int64_t max_sweeps;       /* LSE sweeps per solve, 0 = unlimited */
     mdot_precision precision; /* default MDOT_PREC_F32 */
-    int32_t warm_start;       /* 1: Taylor warm start eq. (approx-znext); 0: reuse z^t */
+    int32_t warm_start;       /* 1: Taylor warm start eq. (approx-znext); 0: reuse z^t;
+                                 2: epsilon-scaling z' = (gamma^{t+1} / gamma^t) z^t (Sec. 4.2.1) */
     double mixed_switch;      /* MIXED: largest gamma * scale * delta run on the FP16 copy (default 0.05) */
+    /* The variants the paper compares against (defaults 0 = the method as in Alg. 1 and 2). */
+    int32_t projector;        /* 0: PNCG (Alg. 2); 1: log-domain Sinkhorn (Alg. 4): per iteration the
+                                 row update u += log r~ - log r(P), then the column update
+                                 v += log c~ - log c(P), two sweeps; the stage ends when
+                                 ||r(P) - r~||_1 <= eps_d / 2 after a column update */
+    int32_t precond;          /* 0: Sinkhorn direction eq. (sinkhorn-direction); 1: diagonal-Hessian
+                                 direction eq. (s-tilde) (r~ / r(P) - 1, c~ / c(P) - 1), taken at an
+                                 iteration only when every ratio lies in [0.01, 100], otherwise the
+                                 Sinkhorn direction (Sec. 4.3); the choice also enters the numerator
+                                 of beta. PNCG only */
+    int32_t smoothing;        /* 0: variable weight eps_d / 4 per stage (Alg. 1); 1: fixed weight, the
+                                 final stage's H / (4 gamma_f^p) in every stage (App. D); in adaptive
+                                 mode gamma_f is the gamma cap */
+    int32_t tol_log_n;        /* 0: eps_d = H_min / gamma^p (Alg. 1); 1: log n in place of H_min in
+                                 eps_d, tolerance and smoothing (App. C); the gamma cap keeps H_min */
 } mdot_params;
 
 typedef struct {
@@ -119,6 +135,7 @@ typedef struct {
     int64_t cert_sweeps;  /* Round/certificate sweeps */
     int64_t prec_switches; /* F32 stages continued with FP64 exp after the gradient norm stalled */
     int64_t proxy_stages;  /* MIXED: stages run on the FP16 copy of the cost */
+    int64_t tilde_iters;   /* precond = 1: iterations whose direction was the diagonal-Hessian one */
 } mdot_result;
 
 typedef struct mdot_ctx mdot_ctx;

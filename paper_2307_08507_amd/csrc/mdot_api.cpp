@@ -263,8 +263,9 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
     w.c = c;
     double** vec[] = {&w.rt, &w.logt, &w.z, &w.zprev, &w.zbest, &w.p, &w.g, &w.lz, &w.lzt, &w.xr, &w.yc,
                       &w.errc, &w.gp, &w.fpp, &w.rowpart, &w.colpart, &w.rowpart2, &w.rowpart3, &w.rowmin,
-                      &w.colmin, &w.tshift};
+                      &w.colmin, &w.tshift, &w.sdt};
     const int k = sizeof(vec) / sizeof(vec[0]);
+    static_assert(sizeof(vec) / sizeof(vec[0]) == kWsBuffers, "one workspace buffer per Work vector");
     for (int i = 0; i < k; ++i) *vec[i] = (double*)(b + off[i]);
     // standalone sweeps bind no marginals; point r and c at an n-vector of the workspace so
     // that no kernel can ever dereference a null pointer (their values are unused there)
@@ -293,6 +294,10 @@ static void fill_defaults(mdot_params* p)
     p->precision = MDOT_PREC_F32;
     p->warm_start = 1;
     p->mixed_switch = 0.05;
+    p->projector = 0;
+    p->precond = 0;
+    p->smoothing = 0;
+    p->tol_log_n = 0;
 }
 
 static int check_cost_desc(mdot_ctx* ctx, const mdot_cost_desc* cost)
@@ -321,6 +326,12 @@ static int check_params(mdot_ctx* ctx, const mdot_params& prm, double target_gap
         (prm.precision != MDOT_PREC_F32 && prm.precision != MDOT_PREC_F64 && prm.precision != MDOT_PREC_MIXED) ||
         (prm.precision == MDOT_PREC_MIXED && !(prm.mixed_switch > 0.0 && std::isfinite(prm.mixed_switch))))
         return fail(ctx, MDOT_E_ARG, "invalid parameters");
+    if (prm.warm_start < 0 || prm.warm_start > 2 || (prm.projector != 0 && prm.projector != 1) ||
+        (prm.precond != 0 && prm.precond != 1) || (prm.smoothing != 0 && prm.smoothing != 1) ||
+        (prm.tol_log_n != 0 && prm.tol_log_n != 1))
+        return fail(ctx, MDOT_E_ARG, "invalid variant parameters (warm_start, projector, precond, smoothing, tol_log_n)");
+    if (prm.projector == 1 && prm.precond == 1)
+        return fail(ctx, MDOT_E_ARG, "precond applies to the PNCG projector only");
     return MDOT_OK;
 }
 
@@ -404,6 +415,11 @@ static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
     P.c1 = prm.ls_c1;
     P.c2 = prm.ls_c2;
     P.hmin = hmin;
+    P.hterm = prm.tol_log_n ? std::log((double)n) : hmin;  // App. C variant: log n in eps_d
+    P.smooth_fixed = prm.smoothing == 1;
+    P.w_fixed = std::min(P.hterm / std::pow(P.gamma_f, prm.p) / 4.0, 0.5);  // App. D: the final stage's weight
+    P.projector = prm.projector;
+    P.precond = prm.precond;
     P.tol_floor = 1e-14;
     P.f32_min_tol = 1e-7;  // about the L1 gradient resolution of FP32 exp sums
     P.max_sweeps = prm.max_sweeps;
@@ -472,6 +488,7 @@ static void fill_result(const State& S, double seconds, mdot_result* res)
     res->cert_sweeps = S.cert_sweeps;
     res->prec_switches = S.prec_switches;
     res->proxy_stages = S.proxy_stages;
+    res->tilde_iters = S.tilde_iters;
 }
 
 static int ensure_graph(mdot_ctx* ctx, int n)

@@ -40,6 +40,14 @@ enum SweepMode : int32_t { SM_NONE = 0, SM_LSE = 1, SM_R1 = 2, SM_R2 = 3, SM_MAX
 enum LsPhase : int32_t { LS_INIT = 0, LS_TRIAL = 1, LS_FORCE = 2, LS_STANDALONE = 3 };
 // O(n) work the vector kernel applies before the next sweep (bit mask, applied in this order).
 enum VecAction : int32_t { VA_ACCEPT = 1, VA_SAVE_BEST = 2, VA_STAGE_INIT = 4, VA_ROUND_PREP = 8 };
+// How an accepted step forms the next direction (State::reset, bit mask). RS_RESET: p = d,
+// else p = d + beta p. d is the Sinkhorn direction s, or the diagonal-Hessian direction s~
+// (stored by the finalize kernel of the trial) with RS_TILDE. RS_ROWS / RS_COLS keep only the
+// row or column entries of d (the Sinkhorn projector's half-steps).
+enum ResetBits : int32_t { RS_RESET = 1, RS_TILDE = 2, RS_ROWS = 4, RS_COLS = 8 };
+// The line-search phase of the Sinkhorn projector's half-steps (alpha = 1, always accepted).
+constexpr int32_t LS_SINK = 4;
+constexpr double kOutrUnit = 1048576.0;  // 2^20: D_BAD's unit for out-of-range ratios
 
 // Per-block partial reductions written by the row / column finalizers.
 enum Dot : int {
@@ -49,7 +57,11 @@ enum Dot : int {
     D_DEN = 2,   // <y, p>                denominator of beta
     D_SG = 3,    // <s_new, g_new>
     D_GN = 4,    // ||g_new||_1
-    D_BAD = 5,   // number of rows/columns outside the exponent range
+    D_BAD = 5,   // number of rows/columns outside the exponent range, plus 2^20 times the
+                 // number of ratios r~/r(P), c~/c(P) outside [0.01, 100] (precond variant)
+    D_GNR = 6,   // ||g_new||_1 over the rows alone (Sinkhorn projector)
+    D_NUMT = 6,  // <y, -s~_new>  numerator of beta with the diagonal-Hessian direction (precond)
+    D_SGT = 7,   // <s~_new, g_new> (precond)
     // R1 sweep
     D_CG1 = 0,   // sum_j c_j g'_j   (from f = u/gamma)
     D_CG2 = 1,   // sum_j c_j g'_j   (from the finite-difference potentials)
@@ -73,9 +85,12 @@ struct DevParams {
     double tol_floor;     // lower limit of the PNCG tolerance eps_d / 2
     double f32_min_tol;   // F32 sweeps while eps_d / 2 >= this, FP64 exp below it (initial floor)
     double mix_gamma;     // MIXED: stages with gamma <= this run on the FP16 copy (0: none)
+    double hterm;         // entropy term of eps_d = hterm / gamma^p: H_min, or log n (App. C)
+    double w_fixed;       // fixed smoothing weight (App. D), used when smooth_fixed
     int64_t max_sweeps;
     int32_t max_ls_trials, max_pncg_iters;
     int32_t adaptive, exp64_default, warm_start, n;
+    int32_t projector, precond, smooth_fixed, pad_;
 };
 
 // Scalar solver state in device memory. Written only by the last workgroup of a sweep
@@ -85,8 +100,9 @@ struct State {
     int32_t exp64, ls_phase, stage, reset;
     int32_t save_best, inner_warn, ls_trials_cur, standalone;  // standalone: 0 solve, 1 LSE only, 2 round+certify
     int32_t budget_stop, exp64_stage;
-    int32_t on_proxy, pad_;  // on_proxy: the stage runs on the FP16 copy of the cost (MIXED)
-    double gamma, gamma_prev, eps_d, w, ws_ratio, tol;
+    int32_t on_proxy, sk_half;  // on_proxy: the stage runs on the FP16 copy of the cost (MIXED);
+                                // sk_half: Sinkhorn projector, 1 after the row update of an iteration
+    double gamma, gamma_prev, eps_d, w, ws_ratio, ws_scale, tol;
     double alpha, alpha_acc, alpha_prev, beta;
     double dphi0, alo, dlo, ahi, dhi, gnorm;
     double r1[4];   // R1 sums: c.g'(2), r.f''(2)
@@ -95,7 +111,7 @@ struct State {
     double f32_floor;   // FP64 exp for stages with tolerance below this (raised by the stall guard)
     double stall_best;  // smallest ||grad||_1 of the stage when it last halved, at iteration stall_k
     int64_t k, sweeps, pncg_iters, ls_trials, cg_resets, ls_failures, fallbacks, cert_sweeps;
-    int64_t stall_k, prec_switches, proxy_stages;
+    int64_t stall_k, prec_switches, proxy_stages, tilde_iters;
 };
 
 // Device buffers of one problem (all FP64 unless noted). 2n-vectors hold rows then columns.
@@ -128,6 +144,7 @@ struct Work {
     double* rowmin;    // [2 * nct * n] per-tile row minima (two variants)
     double* colmin;    // [2 * nrt * n] per-tile column minima
     double* tshift;    // [nrt] per-row-tile column shift S_I
+    double* sdt;       // [2n] diagonal-Hessian direction s~ at the current trial (precond variant)
     double* bdots;     // [fin_grid(n) * kNDot] per-workgroup dot products (in the control block)
     State* st;         // [2] state slots: step k reads slot k % 2, its decide kernel writes the other
     DevParams* prm;
@@ -173,7 +190,7 @@ struct BatchDesc {
 
 // Workspace layout of one problem (the vectors of Work, in the order bind_work assigns them):
 // FP64 counts per buffer, each buffer rounded up to 256 bytes.
-constexpr int kWsBuffers = 21;
+constexpr int kWsBuffers = 22;
 constexpr size_t ws_count(int b, size_t n)
 {
     const size_t nrt = (n + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
@@ -184,7 +201,8 @@ constexpr size_t ws_count(int b, size_t n)
          : b == 15 ? nrt * n                  // colpart
          : b == 18 ? 2 * nct * n              // rowmin
          : b == 19 ? 2 * nrt * n              // colmin
-         : nrt;                               // tshift
+         : b == 20 ? nrt                      // tshift
+         : 2 * n;                             // sdt
 }
 constexpr size_t ws_round(size_t bytes) { return (bytes + 255) / 256 * 256; }
 // Byte offset of buffer b (b = kWsBuffers gives the total).

@@ -341,7 +341,7 @@ struct TileCtx {
 // Scalars a kernel needs from the state: the trial and the pending vector update.
 struct SweepArgs {
     double alpha, gamma, gamma_prev;
-    double alpha_acc, beta, w, ws_ratio;
+    double alpha_acc, beta, w, ws_ratio, ws_scale;
     int va, reset, stage;
 };
 
@@ -350,13 +350,14 @@ __device__ __forceinline__ SweepArgs args_of(const State* S)
     SweepArgs a;
     const int mode = S->sweep_mode, ph = S->ls_phase;
     const double alpha = S->alpha;  // read unconditionally: no branch between the state reads
-    a.alpha = ((mode == SM_LSE) & ((ph == LS_TRIAL) | (ph == LS_FORCE))) ? alpha : 0.0;
+    a.alpha = ((mode == SM_LSE) & ((ph == LS_TRIAL) | (ph == LS_FORCE) | (ph == LS_SINK))) ? alpha : 0.0;
     a.gamma = S->gamma;
     a.gamma_prev = S->gamma_prev;
     a.alpha_acc = S->alpha_acc;
     a.beta = S->beta;
     a.w = S->w;
     a.ws_ratio = S->ws_ratio;
+    a.ws_scale = S->ws_scale;
     a.va = S->vec_action;
     a.reset = S->reset;
     a.stage = S->stage;
@@ -364,13 +365,25 @@ __device__ __forceinline__ SweepArgs args_of(const State* S)
 }
 
 // Entry k of the 2n-vectors (rows then columns) after the pending vector update:
-//   accept : (u, v) += alpha p, log r(P) <- trial log-sums, p <- s + beta p or s (Alg. 2)
+//   accept : (u, v) += alpha p, log r(P) <- trial log-sums, p <- d + beta p or d (Alg. 2), with
+//            d the Sinkhorn direction s or (precond variant) the stored s~, restricted to the
+//            rows or the columns for the Sinkhorn projector's half-steps (Alg. 4)
 //   stage  : smoothed marginals (Alg. 1), rank-1 start (stage 1) or warm start
-//            z' = z + ratio (z - z_prev) (eq. (approx-znext)), p = 0, shifts = log r~.
+//            z' = scale z + ratio (z - z_prev): eq. (approx-znext) with scale = 1, the
+//            epsilon-scaling start (Sec. 4.2.1) with ratio = 0; p = 0, shifts = log r~.
 // zacc is z after the accept and before the stage start (the stage's solution).
 struct Entry {
     double z, zacc, p, lz, logt, rt, zprev;
 };
+
+// The direction entry of an accepted step (see ResetBits).
+__device__ __forceinline__ double next_dir(const SweepArgs& a, double p, double logt, double lz, double sdt, bool row)
+{
+    const double sdir = (a.reset & RS_TILDE) ? sdt : logt - lz;  // eq. (s-tilde) / eq. (sinkhorn-direction)
+    double pn = (a.reset & RS_RESET) ? sdir : fma(a.beta, p, sdir);
+    if (((a.reset & RS_ROWS) && !row) || ((a.reset & RS_COLS) && row)) pn = 0.0;
+    return pn;
+}
 
 __device__ __forceinline__ Entry entry_after(const Work& w, const SweepArgs& a, int k)
 {
@@ -384,8 +397,8 @@ __device__ __forceinline__ Entry entry_after(const Work& w, const SweepArgs& a, 
     if (a.va & VA_ACCEPT) {
         e.z = fma(a.alpha_acc, e.p, e.z);
         e.lz = w.lzt[k];
-        const double sdir = e.logt - e.lz;  // Sinkhorn direction, eq. (sinkhorn-direction)
-        e.p = a.reset ? sdir : fma(a.beta, e.p, sdir);
+        const double sdt = (a.reset & RS_TILDE) ? w.sdt[k] : 0.0;
+        e.p = next_dir(a, e.p, e.logt, e.lz, sdt, k < w.n);
     }
     e.zacc = e.z;
     if (a.va & VA_STAGE_INIT) {
@@ -399,7 +412,7 @@ __device__ __forceinline__ Entry entry_after(const Work& w, const SweepArgs& a, 
         } else {
             const double zp = e.zprev;
             e.zprev = e.z;
-            e.z = fma(a.ws_ratio, e.z - zp, e.z);
+            e.z = fma(a.ws_ratio, e.z - zp, a.ws_scale * e.z);
         }
         e.p = 0.0;
         e.lz = e.logt;
@@ -1125,10 +1138,40 @@ __device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool val
     return cb;
 }
 
+// Terms of the LSE sweep's dots for entry k with trial log-sum l (row or column): the line
+// search and PNCG dots, the row-only gradient norm (Sinkhorn projector) or, with `pre`, the
+// diagonal-Hessian direction s~ = r~/r(P) - 1 (stored for the accept) and its dots.
+__device__ __forceinline__ void lse_terms(const Work& w, const Entry& e, double g_cur, int k, double l, double sum,
+                                          bool e64, bool pre, bool row, double v[kNDot])
+{
+    w.lzt[k] = l;
+    const double rp = exp(l);
+    const double gnew = rp - e.rt;
+    const double snew = e.logt - l;
+    const double y = gnew - g_cur;
+    v[D_PHI] += e.p * gnew;
+    v[D_NUM] += -y * snew;
+    v[D_DEN] += y * e.p;
+    v[D_SG] += snew * gnew;
+    v[D_GN] += fabs(gnew);
+    v[D_BAD] += in_range(sum, e64) ? 0.0 : 1.0;
+    if (pre) {  // eq. (s-tilde) and the [0.01, 100] switch (Sec. 4.3)
+        const double ratio = e.rt / rp;
+        const double st = ratio - 1.0;
+        w.sdt[k] = st;
+        v[D_NUMT] += -y * st;
+        v[D_SGT] += st * gnew;
+        v[D_BAD] += (ratio >= 0.01 && ratio <= 100.0) ? 0.0 : kOutrUnit;
+    } else if (row) {
+        v[D_GNR] += fabs(gnew);
+    }
+}
+
 // Finalize entry k of the 2n-vector after a sweep from its combined partials and add this
 // entry's terms to the dots. M = max_I S_I (column entries of LSE and R1 sweeps).
 __device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a, const Entry& e, double g_cur, int k,
-                                               int mode, bool e64, const Comb& cb, double M, double v[kNDot])
+                                               int mode, bool e64, bool pre, const Comb& cb, double M,
+                                               double v[kNDot])
 {
     const int n = w.n;
     if (k < n) {  // row i = k
@@ -1138,16 +1181,7 @@ __device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a
         } else if (mode == SM_LSE) {
             const double sum = cb.a;
             const double l = fma(a.alpha, e.p, e.lz) + log(sum);  // shift used by the sweep
-            w.lzt[i] = l;
-            const double gnew = exp(l) - e.rt;
-            const double snew = e.logt - l;
-            const double y = gnew - g_cur;
-            v[D_PHI] += e.p * gnew;
-            v[D_NUM] += -y * snew;
-            v[D_DEN] += y * e.p;
-            v[D_SG] += snew * gnew;
-            v[D_GN] += fabs(gnew);
-            v[D_BAD] += in_range(sum, e64) ? 0.0 : 1.0;
+            lse_terms(w, e, g_cur, k, l, sum, e64, pre, true, v);
         } else if (mode == SM_R1) {
             w.fpp[i] = cb.b;
             w.fpp[n + i] = cb.c;
@@ -1170,16 +1204,7 @@ __device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a
     } else if (mode == SM_LSE) {
         const double sum = cb.a;
         const double l = M + log(sum);
-        w.lzt[n + j] = l;
-        const double gnew = exp(l) - e.rt;
-        const double snew = e.logt - l;
-        const double y = gnew - g_cur;
-        v[D_PHI] += e.p * gnew;
-        v[D_NUM] += -y * snew;
-        v[D_DEN] += y * e.p;
-        v[D_SG] += snew * gnew;
-        v[D_GN] += fabs(gnew);
-        v[D_BAD] += in_range(sum, e64) ? 0.0 : 1.0;
+        lse_terms(w, e, g_cur, k, l, sum, e64, pre, false, v);
     } else if (mode == SM_R1) {  // c(F)_j, y_j = c_j / c(F)_j ^ 1, err_c, g'_j (Alg. 3)
         const double cF = exp(M) * cb.a;
         const double cj = w.c[j];
@@ -1203,12 +1228,15 @@ __device__ __forceinline__ void next_stage(State& S, const DevParams& P)
 {
     const double gnew = fmin(S.gamma + (P.q - 1.0) * S.gamma, P.gamma_f);  // Alg. 1
     const double dg = gnew - S.gamma, dgp = S.gamma - S.gamma_prev;
-    S.ws_ratio = P.warm_start ? dg / dgp : 0.0;  // eq. (approx-znext)
+    // warm start: eq. (approx-znext) (1), epsilon-scaling z' = (gamma' / gamma) z (2, Sec. 4.2.1),
+    // or the previous solution unchanged (0)
+    S.ws_ratio = P.warm_start == 1 ? dg / dgp : 0.0;
+    S.ws_scale = P.warm_start == 2 ? gnew / S.gamma : 1.0;
     S.gamma_prev = S.gamma;
     S.gamma = gnew;
     S.stage += 1;
-    S.eps_d = P.hmin / pow(gnew, P.p);  // entropy-aware tolerance
-    S.w = fmin(S.eps_d / 4.0, 0.5);     // variable smoothing weight
+    S.eps_d = P.hterm / pow(gnew, P.p);  // entropy-aware tolerance (H_min, or log n: App. C)
+    S.w = P.smooth_fixed ? P.w_fixed : fmin(S.eps_d / 4.0, 0.5);  // variable smoothing weight (fixed: App. D)
     S.tol = fmax(S.eps_d / 2.0, P.tol_floor);
     // precision ladder: FP32 exp while the tolerance is far above FP32 resolution
     S.exp64_stage = P.exp64_default || S.tol < S.f32_floor;
@@ -1267,6 +1295,69 @@ __device__ __forceinline__ void start_line_search(State& S)
 // control (Alg. 1) and the certified-gap termination. `sum` holds the global dots.
 constexpr int kStallF32 = 256, kStallF64 = 4096;
 
+// Precision ladder and stall guard after an accepted iteration with gradient norm gn: a stage
+// whose gradient norm has not halved in kStallF32 iterations with FP32 exp continues with FP64
+// exp (and so do the later stages, whose tolerances are smaller); after kStallF64 more
+// iterations without halving it ends unconverged (returns true).
+__device__ __forceinline__ bool stall_guard(State& S, double gn)
+{
+    if (gn <= 0.5 * S.stall_best) {
+        S.stall_best = gn;
+        S.stall_k = S.k;
+    } else if (!S.exp64_stage && S.k - S.stall_k >= kStallF32) {
+        S.exp64_stage = 1;
+        S.exp64 = 1;
+        S.f32_floor = fmax(S.f32_floor, 2.0 * S.tol);
+        S.prec_switches++;
+        S.stall_best = gn;
+        S.stall_k = S.k;
+    } else if (S.k - S.stall_k >= kStallF64) {
+        return true;
+    }
+    return false;
+}
+
+// The Sinkhorn projector (Alg. 4) after a sweep: every half-step is taken whole (alpha = 1).
+// The stage start's sweep gives log r(P), so the first half-step updates the rows; the sweep
+// after a row update gives log c(P) for the column update; the sweep after a column update
+// gives log r(P) again, ends the iteration and is where the stop test and the caps apply.
+// gn is ||r(P) - r~||_1 (the column residual is zero up to rounding after a column update).
+__device__ __forceinline__ void decide_sinkhorn(State& S, const DevParams& P, double gn, bool bad)
+{
+    S.alpha_acc = 0.0;
+    S.beta = 0.0;
+    S.vec_action = VA_ACCEPT;
+    if (S.ls_phase == LS_INIT) {
+        S.reset = RS_RESET | RS_ROWS;
+        S.gnorm = gn;
+        S.k = 1;
+        S.stall_best = gn;
+        S.stall_k = 1;
+        S.sk_half = 0;
+        if (gn <= S.tol) end_stage(S, P, true);
+        else if (S.budget_stop || P.max_pncg_iters < 1 || bad) end_stage(S, P, false);
+        else {
+            S.ls_phase = LS_SINK;
+            S.alpha = 1.0;
+        }
+        return;
+    }
+    S.alpha_acc = 1.0;
+    if (S.sk_half == 0) {  // after the row update: the column update comes next
+        S.reset = RS_RESET | RS_COLS;
+        S.sk_half = 1;
+        return;
+    }
+    S.reset = RS_RESET | RS_ROWS;
+    S.sk_half = 0;
+    S.pncg_iters++;
+    S.k++;
+    S.gnorm = gn;
+    const bool stalled = stall_guard(S, gn);
+    if (gn <= S.tol && !bad) end_stage(S, P, true);
+    else if (S.k - 1 >= P.max_pncg_iters || S.budget_stop || stalled || bad) end_stage(S, P, false);
+}
+
 __device__ __forceinline__ void decide(State& S, const DevParams& P, const double* sum)
 {
     const int mode = S.sweep_mode;
@@ -1276,7 +1367,10 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
         return;
     }
     if (mode == SM_LSE) {
-        const bool bad = sum[D_BAD] > 0.0;
+        // D_BAD counts range failures plus kOutrUnit per ratio outside [0.01, 100] (precond)
+        const double outr = floor(sum[D_BAD] * (1.0 / kOutrUnit));
+        const bool bad = sum[D_BAD] - outr * kOutrUnit > 0.0;
+        const bool tilde = P.precond && outr == 0.0;  // diagonal-Hessian direction this time
         if (bad && !S.exp64) {  // re-run this sweep with FP64 exp
             S.exp64 = 1;
             S.fallbacks++;
@@ -1298,12 +1392,16 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
         }
         S.sweeps++;
         if (P.max_sweeps > 0 && S.sweeps >= P.max_sweeps) S.budget_stop = 1;
-        const double gn = sum[D_GN], sg = sum[D_SG];
+        if (P.projector == 1) {
+            decide_sinkhorn(S, P, sum[D_GNR], bad);
+            return;
+        }
+        const double gn = sum[D_GN], sg = tilde ? sum[D_SGT] : sum[D_SG];
         const double d = bad ? NAN : sum[D_PHI];
-        if (S.ls_phase == LS_INIT) {  // first sweep of a stage: p = s, beta = 0
+        if (S.ls_phase == LS_INIT) {  // first sweep of a stage: p = s (or s~), beta = 0
             S.alpha_acc = 0.0;
             S.beta = 0.0;
-            S.reset = 1;
+            S.reset = RS_RESET | (tilde ? RS_TILDE : 0);
             S.vec_action = VA_ACCEPT;
             S.gnorm = gn;
             S.k = 1;
@@ -1312,7 +1410,10 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
             S.dphi0 = sg;
             if (gn <= S.tol) end_stage(S, P, true);
             else if (!(sg < 0.0) || S.budget_stop) end_stage(S, P, false);
-            else start_line_search(S);
+            else {
+                S.tilde_iters += tilde;
+                start_line_search(S);
+            }
             return;
         }
         bool accept;
@@ -1324,7 +1425,8 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
             accept = ((2.0 * P.c1 - 1.0) * S.dphi0 >= d) && (d >= P.c2 * S.dphi0);  // eq. (approximate-wolfe)
         }
         if (accept) {
-            const double num = sum[D_NUM], den = sum[D_DEN];
+            // numerator of beta with the direction this iterate takes (s, or s~ under the switch)
+            const double num = tilde ? sum[D_NUMT] : sum[D_NUM], den = sum[D_DEN];
             const double beta = (den != 0.0) ? num / den : 0.0;  // eq. (beta_PPR_OT)
             double pg = sg + beta * sum[D_PHI];                  // <s + beta p, g_new>
             const int reset = !(pg < 0.0);
@@ -1335,33 +1437,19 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
             S.alpha_acc = S.alpha;
             S.alpha_prev = S.alpha;
             S.beta = beta;
-            S.reset = reset;
+            S.reset = (reset ? RS_RESET : 0) | (tilde ? RS_TILDE : 0);
             S.vec_action = VA_ACCEPT;
             S.pncg_iters++;
             S.k++;
             S.gnorm = gn;
             S.dphi0 = pg;
-            // precision ladder and stall guard: a stage whose gradient norm has not halved in
-            // kStallF32 iterations with FP32 exp continues with FP64 exp (and so do the later
-            // stages, whose tolerances are smaller); after kStallF64 more iterations without
-            // halving it ends unconverged
-            bool stalled = false;
-            if (gn <= 0.5 * S.stall_best) {
-                S.stall_best = gn;
-                S.stall_k = S.k;
-            } else if (!S.exp64_stage && S.k - S.stall_k >= kStallF32) {
-                S.exp64_stage = 1;
-                S.exp64 = 1;
-                S.f32_floor = fmax(S.f32_floor, 2.0 * S.tol);
-                S.prec_switches++;
-                S.stall_best = gn;
-                S.stall_k = S.k;
-            } else if (S.k - S.stall_k >= kStallF64) {
-                stalled = true;
-            }
+            const bool stalled = stall_guard(S, gn);
             if (gn <= S.tol) end_stage(S, P, true);
             else if (S.k > P.max_pncg_iters || S.budget_stop || !(pg < 0.0) || stalled) end_stage(S, P, false);
-            else start_line_search(S);
+            else {
+                S.tilde_iters += tilde;
+                start_line_search(S);
+            }
             return;
         }
         // not accepted: shrink the bracket [alpha_lo, alpha_hi] with phi'(lo) < 0 < phi'(hi)
@@ -1525,7 +1613,7 @@ struct FinShared {
 // flight at once. The marginal is read only when the update starts a stage: only solves do
 // that, and only solves bind r and c.
 struct EntryIn {
-    double z, p, lz, logt, rt, zprev, lzt, m, g;
+    double z, p, lz, logt, rt, zprev, lzt, m, g, sdt;
 };
 __device__ __forceinline__ EntryIn entry_load(const Work& w, const SweepArgs& a, int k)
 {
@@ -1540,10 +1628,11 @@ __device__ __forceinline__ EntryIn entry_load(const Work& w, const SweepArgs& a,
     in.lzt = w.lzt[k];
     in.m = (a.va & VA_STAGE_INIT) ? *((k < n) ? w.r + k : w.c + (k - n)) : 0.0;
     in.g = w.g[k];
+    in.sdt = ((a.va & VA_ACCEPT) && (a.reset & RS_TILDE)) ? w.sdt[k] : 0.0;
     return in;
 }
 // entry_after from loaded inputs (same arithmetic, so bit-identical to the sweeps' copy)
-__device__ __forceinline__ Entry entry_from(const EntryIn& in, const SweepArgs& a, int n)
+__device__ __forceinline__ Entry entry_from(const EntryIn& in, const SweepArgs& a, int n, int k)
 {
     Entry e;
     e.z = in.z;
@@ -1555,8 +1644,7 @@ __device__ __forceinline__ Entry entry_from(const EntryIn& in, const SweepArgs& 
     if (a.va & VA_ACCEPT) {
         e.z = fma(a.alpha_acc, e.p, e.z);
         e.lz = in.lzt;
-        const double sdir = e.logt - e.lz;
-        e.p = a.reset ? sdir : fma(a.beta, e.p, sdir);
+        e.p = next_dir(a, e.p, e.logt, e.lz, in.sdt, k < n);
     }
     e.zacc = e.z;
     if (a.va & VA_STAGE_INIT) {
@@ -1568,7 +1656,7 @@ __device__ __forceinline__ Entry entry_from(const EntryIn& in, const SweepArgs& 
         } else {
             const double zp = e.zprev;
             e.zprev = e.z;
-            e.z = fma(a.ws_ratio, e.z - zp, e.z);
+            e.z = fma(a.ws_ratio, e.z - zp, a.ws_scale * e.z);
         }
         e.p = 0.0;
         e.lz = e.logt;
@@ -1606,7 +1694,7 @@ __device__ __forceinline__ double store_update(const Work& w, const SweepArgs& a
 // any arithmetic.
 template <int PER>
 __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a, int k, bool valid, int l, int L,
-                                              bool e64, double v[kNDot], double* sfac, bool first)
+                                              bool e64, bool pre, double v[kNDot], double* sfac, bool first)
 {
     const int n = w.n, nrt = w.nrt;
     const int kc = valid ? k : 0;
@@ -1640,9 +1728,9 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
     Comb cb{};
     cb.a = group_fold<0>(acc, L);
     if (!valid || l != 0) return;
-    const Entry e = entry_from(in, a, n);
+    const Entry e = entry_from(in, a, n, k);
     const double g_cur = store_update(w, a, e, in.g, k);
-    finalize_entry(w, a, e, g_cur, k, SM_LSE, e64, cb, M, v);
+    finalize_entry(w, a, e, g_cur, k, SM_LSE, e64, pre, cb, M, v);
 }
 
 // Finalize workgroup `blk` of the problem's `nblk` (= fin_grid(n)) workgroups. Entry k is
@@ -1664,6 +1752,7 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     const State* Sp = C->st + parity;
     const int done = Sp->done, mode = Sp->sweep_mode, exp64 = Sp->exp64;
     const SweepArgs a = args_of(Sp);
+    const bool pre = C->prm.precond != 0;
     asm volatile("" ::: "memory");
     const int tid = threadIdx.x;
     const int n = wl.n;
@@ -1689,8 +1778,8 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         const int k = (vb * kVecWG + tid) >> lgL;
         const bool valid = k < 2 * n;
         if (fast) {
-            if (!BIG || per == 8) fin_lse_entry<8>(wl, a, k, valid, l, L, e64, v, sh.fac, vb == blk);
-            else fin_lse_entry<32>(wl, a, k, valid, l, L, e64, v, sh.fac, vb == blk);
+            if (!BIG || per == 8) fin_lse_entry<8>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
+            else fin_lse_entry<32>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
             continue;
         }
         const int kc = valid ? k : 0;
@@ -1698,9 +1787,9 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         Comb cb{};
         if (active) cb = combine(wl, mode, k, valid, l, L, M);
         if (!valid || l != 0) continue;
-        const Entry e = entry_from(in, a, n);
+        const Entry e = entry_from(in, a, n, k);
         const double g_cur = store_update(wl, a, e, in.g, k);
-        if (active) finalize_entry(wl, a, e, g_cur, k, mode, e64, cb, M, v);
+        if (active) finalize_entry(wl, a, e, g_cur, k, mode, e64, pre, cb, M, v);
     }
     if (active) block_dots(v, bdots_of(w) + (size_t)blk * kNDot, tid, sh.red);
 }
@@ -1856,9 +1945,10 @@ __global__ void k_init(const Work* __restrict__ wp)
     S.stage = 1;
     S.gamma = fmin(P.gamma_i, P.gamma_f);
     S.gamma_prev = 0.0;
-    S.eps_d = P.hmin / pow(S.gamma, P.p);
-    S.w = fmin(S.eps_d / 4.0, 0.5);
+    S.eps_d = P.hterm / pow(S.gamma, P.p);
+    S.w = P.smooth_fixed ? P.w_fixed : fmin(S.eps_d / 4.0, 0.5);
     S.tol = fmax(S.eps_d / 2.0, P.tol_floor);
+    S.ws_scale = 1.0;
     S.f32_floor = P.f32_min_tol;
     S.on_proxy = P.mix_gamma > 0.0 && S.gamma <= P.mix_gamma;
     S.exp64_stage = P.exp64_default || S.tol < S.f32_floor;

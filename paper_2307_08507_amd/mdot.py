@@ -33,7 +33,9 @@ class Params(ct.Structure):
     _fields_ = [("p", ct.c_double), ("q", ct.c_double), ("gamma_i", ct.c_double), ("gamma_f", ct.c_double),
                 ("gamma_cap", ct.c_double), ("ls_c1", ct.c_double), ("ls_c2", ct.c_double),
                 ("max_ls_trials", ct.c_int32), ("max_pncg_iters", ct.c_int32), ("max_sweeps", ct.c_int64),
-                ("precision", ct.c_int), ("warm_start", ct.c_int32), ("mixed_switch", ct.c_double)]
+                ("precision", ct.c_int), ("warm_start", ct.c_int32), ("mixed_switch", ct.c_double),
+                ("projector", ct.c_int32), ("precond", ct.c_int32), ("smoothing", ct.c_int32),
+                ("tol_log_n", ct.c_int32)]
 
 
 class Result(ct.Structure):
@@ -42,7 +44,8 @@ class Result(ct.Structure):
                 ("seconds", ct.c_double), ("stages", ct.c_int32), ("status", ct.c_int32),
                 ("pncg_iters", ct.c_int64), ("ls_trials", ct.c_int64), ("sweeps", ct.c_int64),
                 ("cg_resets", ct.c_int64), ("ls_failures", ct.c_int64), ("fp64_retries", ct.c_int64),
-                ("cert_sweeps", ct.c_int64), ("prec_switches", ct.c_int64), ("proxy_stages", ct.c_int64)]
+                ("cert_sweeps", ct.c_int64), ("prec_switches", ct.c_int64), ("proxy_stages", ct.c_int64),
+                ("tilde_iters", ct.c_int64)]
 
 
 class MdotError(RuntimeError):
@@ -156,6 +159,7 @@ class SolveResult:
     cert_sweeps: int
     prec_switches: int
     proxy_stages: int
+    tilde_iters: int
 
 
 class Context:
