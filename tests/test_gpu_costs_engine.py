@@ -250,6 +250,45 @@ def test_engine_bitwise_equals_solve(ctx, prec):
         eng.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_engine_results_against_oracle_and_exact_lp(prec):
+    # engine results judged against independent references, not only against mdot_solve: three
+    # problems of uneven n in one batch, each certified to gap 1e-5. The exact LP (scipy HiGHS)
+    # must lie in [LB, UB] with UB - OT <= 1e-5, and the FP64 oracle's solve to the same gap must
+    # agree on the primal cost to 1e-5 (both lie in [OT, OT + 1e-5]).
+    from tests.exact_ot import exact_lp
+
+    probs = []
+    for k, fam, cost, seed in [(16, "smooth", "sqeuclid", 1), (17, "cauchy", "l1", 4), (24, "uniform", "l1", 2)]:
+        C, r, c = W.grid_problem(k, fam, cost, seed)
+        Cd = dev(C, torch.float32)
+        probs.append((Cd, r, c, Cd.double().cpu().numpy()))
+    prm = M.default_params(precision=prec)
+    eng = M.Context(0)
+    try:
+        tickets, held = [], []  # the engine borrows inputs and outputs until the ticket is polled
+        for Cd, r, c, _ in probs:
+            rd, cd = dev(r), dev(c)
+            u = torch.empty(r.size, dtype=torch.float64, device="cuda")
+            v = torch.empty_like(u)
+            held.append((rd, cd, u, v))
+            t = eng.submit(M.dense_cost(Cd), rd, cd, 1e-5, prm, u, v)
+            assert t is not None
+            tickets.append(t)
+        results = [eng.poll(t, wait=True) for t in tickets]
+    finally:
+        eng.close()
+    for (Cd, r, c, C64), res in zip(probs, results):
+        ot = exact_lp(C64, r, c)
+        ref = O.mdot(C64, r, c, O.default_params(target_gap=1e-5)).result
+        print(f"engine {prec} n={r.size}: gap={res.gap:.3e} UB-OT={res.primal_cost - ot:.3e} "
+              f"oracle UB-OT={ref['primal_cost'] - ot:.3e}")
+        assert res.status == 0 and res.gap <= 1e-5
+        assert res.dual_bound <= ot + 1e-12 and ot <= res.primal_cost + 1e-12
+        assert res.primal_cost - ot <= 1e-5
+        assert abs(res.primal_cost - ref["primal_cost"]) <= 1e-5
+
+
 @pytest.mark.parametrize("mix", ["planar", "mixed"])
 def test_engine_point_clouds_bitwise_equals_solve(ctx, mix):
     # Planar clouds run the planar point instance, d = 3 clouds the general one: a mixed batch

@@ -108,6 +108,45 @@ def test_solve_fullsize_recertified_by_oracle(ctx):
     assert me_o <= 1e-12
 
 
+_ORACLE_4096 = {}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_solve_fullsize_schedule_mode_matches_oracle(ctx, prec):
+    # The benchmark's size (n = 4096, FP32-stored squared-Euclidean grid cost, smoothed-field
+    # marginals) on the paper's schedule to a short gamma_f = 2^7 (10 stages), which keeps the
+    # FP64 oracle to seconds. FP64 sweeps take the oracle's decisions exactly (stages, PNCG
+    # iterations, trials, sweeps) with UB and LB within 1e-9 relative. FP32 sweeps (FP32 exp)
+    # follow other iterates inside each stage's stopping ball ||grad||_1 <= eps_d / 2, which at
+    # gamma <= 2^7 is wide (eps_d / 2 ~ 3e-3); both paths still run the same stages and end at
+    # the same gamma, and their rounded plans' costs agree to 1e-4 relative.
+    k, gf = 64, 2.0**7
+    C, r, c = W.grid_problem(k, "smooth", "sqeuclid", 0)
+    Cd = dev(C, torch.float32)
+    C64 = Cd.double().cpu().numpy()
+    if "s" not in _ORACLE_4096:
+        _ORACLE_4096["s"] = O.mdot(C64, r, c, O.default_params(gamma_f=gf))
+    s = _ORACLE_4096["s"]
+    R = s.result
+    u = torch.empty(k * k, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+    print(f"n=4096 schedule {prec}", flush=True)
+    res = ctx.solve(M.dense_cost(Cd), dev(r), dev(c), 1e-4, M.default_params(gamma_f=gf, precision=prec), u, v)
+    got = (res.stages, res.pncg_iters, res.ls_trials, res.sweeps)
+    want = (R["stages"], R["pncg_iters"], R["ls_trials"], R["sweeps"])
+    print(f"gpu {got} UB={res.primal_cost!r} LB={res.dual_bound!r}; oracle {want} UB={R['primal_cost']!r} "
+          f"LB={R['dual_bound']!r}")
+    assert res.status == 0 and s.status == 0
+    assert res.stages == R["stages"] and res.gamma_final == R["gamma_final"] == gf
+    if prec == "f64":
+        assert got == want
+        assert res.primal_cost == pytest.approx(R["primal_cost"], rel=1e-9)
+        assert res.dual_bound == pytest.approx(R["dual_bound"], rel=1e-9)
+    else:
+        assert res.primal_cost == pytest.approx(R["primal_cost"], rel=1e-4)
+        assert res.dual_bound == pytest.approx(R["dual_bound"], rel=1e-4)
+
+
 def _points_problem(n, seed):
     rng = np.random.default_rng(seed)
     X = rng.random((n, 2)).astype(np.float32)

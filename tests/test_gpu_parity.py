@@ -118,62 +118,161 @@ def _solve(ctx, C, r, c, target=1e-4, dtype=torch.float64, **kw):
     return res, u.cpu().numpy(), v.cpu().numpy(), Cd.double().cpu().numpy()
 
 
+def _counts(res):
+    return (res.stages, res.pncg_iters, res.ls_trials, res.sweeps)
+
+
+def _ocounts(s):
+    R = s.result
+    return (R["stages"], R["pncg_iters"], R["ls_trials"], R["sweeps"])
+
+
 @pytest.mark.parametrize("cost", ["sqeuclid", "l1"])
 def test_schedule_mode_f64_matches_oracle(ctx, cost):
-    # paper's schedule to a fixed gamma_f: same stage count, iteration counts within 2 %,
-    # same rounded cost and bound to 1e-7 relative. The two FP64 paths round differently
-    # (reduction order, libm vs device exp), and PNCG amplifies last-bit differences over
-    # hundreds of iterations; both stop anywhere with ||grad g||_1 <= eps_d / 2, so exact
-    # agreement of the iterates is not expected beyond that.
+    # The paper's schedule to a fixed gamma_f, FP64 sweeps. The two FP64 paths round differently
+    # (device exp and reduction order against libm), but here every decision lands on the same
+    # side of its threshold: the same stages, PNCG iterations, line-search trials and sweeps.
+    # UB and LB then agree to 1e-9 relative (measured: 1e-15 for sqeuclid; for L1 about 1e-10,
+    # rounding amplified inside the stopping ball of the last stage).
     C, r, c = W.grid_problem(16, "smooth", cost, 0)
     gf = 2.0**9
     print(f"schedule f64 cost={cost}", flush=True)
     res, u, v, C64 = _solve(ctx, C, r, c, gamma_f=gf, precision="f64")
     s = O.mdot(C64, r, c, O.default_params(gamma_f=gf))
     R = s.result
-    print(f"gpu: stages={res.stages} iters={res.pncg_iters} trials={res.ls_trials} UB={res.primal_cost!r} "
-          f"LB={res.dual_bound!r}; oracle: stages={R['stages']} iters={R['pncg_iters']} trials={R['ls_trials']} "
+    print(f"gpu: {_counts(res)} UB={res.primal_cost!r} LB={res.dual_bound!r}; oracle: {_ocounts(s)} "
           f"UB={R['primal_cost']!r} LB={R['dual_bound']!r}")
     assert res.status == 0 and s.status == 0
-    assert res.stages == R["stages"]
-    assert abs(res.pncg_iters - R["pncg_iters"]) <= max(2, 0.02 * R["pncg_iters"])
-    assert res.primal_cost == pytest.approx(R["primal_cost"], rel=1e-7)
-    assert res.dual_bound == pytest.approx(R["dual_bound"], rel=1e-7)
+    assert _counts(res) == _ocounts(s)
+    assert res.primal_cost == pytest.approx(R["primal_cost"], rel=1e-9)
+    assert res.dual_bound == pytest.approx(R["dual_bound"], rel=1e-9)
     assert res.gamma_final == R["gamma_final"]
     # potentials: gauge-invariant comparison of u_i + v_j on a sample
     np.testing.assert_allclose((u[:, None] + v[None, :])[::7, ::5], (s.u[:, None] + s.v[None, :])[::7, ::5],
                                rtol=0, atol=1e-6 * gf)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_adaptive_config1(ctx, prec):
-    # the small grid workload: n = 256, smoothed fields, squared-Euclidean cost, gap 1e-4
+_LP = {}
+
+
+def _exact(C64, r, c, key):
     from tests.exact_ot import exact_lp
 
-    for seed in (0, 1):
+    if key not in _LP:
+        _LP[key] = exact_lp(C64, r, c)
+    return _LP[key]
+
+
+# Seeds of the small grid workload (gap 1e-4) whose FP64 solve does not take the oracle's
+# decisions exactly, with the difference in (stages, PNCG iterations, line-search trials).
+# Every other seed must match exactly.
+ADAPTIVE_F64_DIVERGENT = {0: (0, 1, 1), 6: (0, -6, -7)}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adaptive_config1(ctx, prec):
+    # The small grid workload: n = 256, smoothed fields, squared-Euclidean cost, gap 1e-4, seeds
+    # 0-9. Every seed: certified, and the exact LP inside [LB, UB]. FP64 sweeps: the oracle's
+    # decisions exactly (stages, PNCG iterations, trials), except the named seeds, which must show
+    # exactly the named difference. With equal decisions the iterates differ only by rounding,
+    # accumulated over ~600 iterations up to gamma ~ 2^11: |dUB| <= 1e-3 target (measured
+    # <= 4e-9). A seed where a stage's gradient norm crosses eps_d / 2 at another iteration
+    # moves UB by up to 1e-2 target (seed 0: one more trial, 7.4e-7, the same trial the oracle
+    # takes with exp perturbed by 2 ulp; seed 6: 6 iterations fewer, 7.6e-8).
+    mism = []
+    for seed in range(10):
         C, r, c = W.grid_problem(16, "smooth", "sqeuclid", seed)
         print(f"adaptive {prec} seed={seed}", flush=True)
         res, u, v, C64 = _solve(ctx, C, r, c, target=1e-4, dtype=torch.float32, precision=prec)
-        ot = exact_lp(C64, r, c)
+        ot = _exact(C64, r, c, ("config1", seed))
         s = O.mdot(C64, r, c, O.default_params(target_gap=1e-4))
+        print(f"{prec} seed {seed}: gpu {_counts(res)} gap={res.gap:.3e} UB={res.primal_cost!r}; oracle "
+              f"{_ocounts(s)} gap={s.result['gap']:.3e} UB={s.result['primal_cost']!r}; UB-OT={res.primal_cost - ot:.3e}")
         assert res.status == 0
         assert res.gap <= 1e-4
         assert res.dual_bound <= ot + 1e-12
         assert res.primal_cost >= ot - 1e-12
         assert res.primal_cost - ot <= 1e-4
         assert res.marg_err_l1 <= 1e-12
-        print(f"{prec}: gap={res.gap:.3e} UB-OT={res.primal_cost - ot:.3e} stages={res.stages} sweeps={res.sweeps} "
-              f"retries={res.fp64_retries} time={res.seconds * 1e3:.2f} ms; oracle stages={s.result['stages']} "
-              f"sweeps={s.result['sweeps']} gap={s.result['gap']:.3e}")
         if prec == "f64":
-            # same stage decisions. The inner solve stops anywhere in ||grad||_1 <= eps_d / 2, and a
-            # last-bit difference in exp can end it one line-search trial earlier or later: the
-            # oracle itself, with exp perturbed by at most 2 ulp, moves UB and the gap by up to
-            # 0.9 % of the target here (seed 0: one more trial, UB +8.9e-7). 2 % of the target
-            # bounds that spread and is still 50 times tighter than the certificate.
-            assert res.stages == s.result["stages"]
-            assert abs(res.primal_cost - s.result["primal_cost"]) <= 2e-2 * 1e-4
-            assert abs(res.gap - s.result["gap"]) <= 2e-2 * 1e-4
+            delta = tuple(a - b for a, b in zip(_counts(res)[:3], _ocounts(s)[:3]))
+            tol = 1e-2 * 1e-4 if seed in ADAPTIVE_F64_DIVERGENT else 1e-3 * 1e-4
+            dub, dgap = abs(res.primal_cost - s.result["primal_cost"]), abs(res.gap - s.result["gap"])
+            print(f"  seed {seed}: decision delta {delta}, |dUB|={dub:.2e} |dgap|={dgap:.2e}")
+            if delta != ADAPTIVE_F64_DIVERGENT.get(seed, (0, 0, 0)) or dub > tol or dgap > tol:
+                mism.append((seed, delta, dub, dgap))
+    assert not mism, mism
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_f32_primal_within_1e6_of_oracle(ctx, seed):
+    # The FP32 path (FP32 exp while the stage tolerance is >= 1e-7, FP64 exp below) solved to the
+    # same certified gap as the FP64 oracle. Both primal costs lie in [OT, OT + gap], so they agree
+    # to max(gap) absolute; at gap 1e-8 and UB ~ 1e-2 that is 1e-6 relative, the criterion.
+    C, r, c = W.grid_problem(16, "smooth", "sqeuclid", seed)
+    target = 1e-8
+    res, u, v, C64 = _solve(ctx, C, r, c, target=target, dtype=torch.float32, precision="f32")
+    s = O.mdot(C64, r, c, O.default_params(target_gap=target))
+    R = s.result
+    rel = abs(res.primal_cost - R["primal_cost"]) / R["primal_cost"]
+    print(f"f32 seed {seed}: gap={res.gap:.3e} UB={res.primal_cost!r} oracle gap={R['gap']:.3e} "
+          f"UB={R['primal_cost']!r} rel={rel:.2e} switches={res.prec_switches}")
+    assert res.status == 0 and s.status == 0
+    assert res.gap <= target and R["gap"] <= target
+    assert rel <= 1e-6
+    assert res.dual_bound <= R["primal_cost"] + 1e-15 and R["dual_bound"] <= res.primal_cost + 1e-15
+
+
+def test_sweep_budget_matches_oracle(ctx):
+    # max_sweeps: the solve stops after the sweep that spends the budget, rounds and certifies the
+    # last accepted iterate and warns; the oracle reads the budget the same way
+    C, r, c = W.grid_problem(16, "blobs", "sqeuclid", 2)
+    kw = dict(max_sweeps=150)
+    res, u, v, C64 = _solve(ctx, C, r, c, target=1e-7, precision="f64", **kw)
+    s = O.mdot(C64, r, c, O.default_params(target_gap=1e-7, **kw))
+    R = s.result
+    print(f"budget: gpu {_counts(res)} status={res.status} UB={res.primal_cost!r} LB={res.dual_bound!r}; oracle "
+          f"{_ocounts(s)} status={s.status} UB={R['primal_cost']!r} LB={R['dual_bound']!r}")
+    assert res.status == M.MDOT_W_NOT_CONVERGED and s.status == 1
+    assert res.sweeps == 150 and R["sweeps"] == 150
+    assert _counts(res) == _ocounts(s)
+    assert res.primal_cost == pytest.approx(R["primal_cost"], rel=1e-9)
+    assert res.dual_bound == pytest.approx(R["dual_bound"], rel=1e-9)
+    assert res.gap > 1e-7
+
+
+def test_gamma_cap_matches_oracle(ctx):
+    # an explicit gamma cap below what the target needs: the last stage runs at the cap and the
+    # solve warns with the best certified gap it reached
+    C, r, c = W.grid_problem(16, "smooth", "l1", 3)
+    kw = dict(gamma_cap=2.0**8)
+    res, u, v, C64 = _solve(ctx, C, r, c, target=1e-7, precision="f64", **kw)
+    s = O.mdot(C64, r, c, O.default_params(target_gap=1e-7, **kw))
+    R = s.result
+    print(f"gamma cap: gpu {_counts(res)} status={res.status} gamma={res.gamma_final} gap={res.gap:.3e}; oracle "
+          f"{_ocounts(s)} status={s.status} gamma={R['gamma_final']} gap={R['gap']:.3e}")
+    assert res.status == M.MDOT_W_NOT_CONVERGED and s.status == 1
+    assert _counts(res) == _ocounts(s)
+    assert res.gamma_final <= 2.0**8 and res.gamma_final == R["gamma_final"]
+    assert res.gap == pytest.approx(R["gap"], rel=1e-7)
+    assert res.primal_cost == pytest.approx(R["primal_cost"], rel=1e-9)
+
+
+def test_line_search_cap_matches_oracle(ctx):
+    # at most 2 line-search trials: at the cap the step falls back to alpha_lo when it is > 0,
+    # otherwise the stage ends unconverged (schedule mode then warns)
+    C, r, c = W.grid_problem(16, "cauchy", "sqeuclid", 4)
+    kw = dict(gamma_f=2.0**9, max_ls_trials=2)
+    res, u, v, C64 = _solve(ctx, C, r, c, precision="f64", **kw)
+    s = O.mdot(C64, r, c, O.default_params(**kw))
+    R = s.result
+    print(f"ls cap: gpu {_counts(res)} status={res.status} failures={res.ls_failures}; oracle {_ocounts(s)} "
+          f"status={s.status} failures={R['ls_failures']}")
+    assert res.ls_failures > 0
+    assert res.status == s.status
+    assert res.ls_failures == R["ls_failures"]
+    assert _counts(res) == _ocounts(s)
+    assert res.primal_cost == pytest.approx(R["primal_cost"], rel=1e-9)
 
 
 def test_invalid_inputs(ctx):
