@@ -15,6 +15,18 @@ torch.cuda.synchronize(). `roofline` reports the dominant kernel (the fused LSE 
 with HIP events on the library stream; `cpu_baseline` times the FP64 CPU oracle on a bounded
 sample of the same workload and extrapolates to a full solve.
 
+The default run (no workload flags) adds, beside the headline, the rest of the metric:
+  lse_sweep_flushed      the sweep timed alone after a 512 MiB read evicts the cost from the
+                         L2 and last-level caches (HBM-streamed, against the MALL-resident
+                         figure of `roofline`)
+  legs.f64 / legs.mixed  the same 8 problems solved once each in FP64 and in MIXED precision
+  legs.batched_*         the 8 problems submitted together to the batched engine (FP32, MIXED)
+  legs.projectors        PNCG against the Sinkhorn projector (Alg. 4) at fixed gamma_f on the
+                         L1 problems: LSE sweeps per solve
+  legs.serving           a short continuous-batching run (--leg-requests requests, Poisson
+                         arrivals at 0.7 x saturation, HBM admission budget --hbm-budget)
+--no-legs reports the headline alone.
+
 Other workloads (not the default line):
   --grid 128             n = 16384 on a 128 x 128 grid (the cost is 1 GiB in FP32)
   --cost-storage S       f32 (default), f16, bf16 (stored dense cost) or points (the cost is
@@ -28,6 +40,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -124,31 +137,61 @@ def measured_traffic(n: int, storage: str):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(C64, prob, sweeps: int, stages: int, n_sweeps_sample: int, n_cert_sample: int, label: str):
-    """Time the FP64 CPU oracle on a bounded sample and extrapolate to one full solve."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(C64, probs, gpu_counts, n_sweeps_sample: int, n_cert_sample: int, label: str):
+    """Time the FP64 CPU oracle on a bounded sample (two-sided LSE sweeps and round+certify
+    evaluations on one problem's cost) with all host threads and with one, and extrapolate to
+    each problem's full solve from the GPU solve's sweep and certified-stage counts (the oracle
+    takes the same decisions; its per-sweep cost does not depend on the marginals)."""
     import numpy as np
 
     from oracle import oracle as O
 
-    r, c = prob["r"], prob["c"]
+    p0 = probs[0]
+    r, c = p0["r"], p0["c"]
     u, v = np.log(r), np.log(c)
-    t0 = time.perf_counter()
-    for k in range(n_sweeps_sample):
-        O.lse2(C64, u, v, 16.0 * 2 ** (k / 3))
-    t_sweep = (time.perf_counter() - t0) / n_sweeps_sample
-    t0 = time.perf_counter()
-    for k in range(n_cert_sample):
-        O.round_certify(C64, u, v, 64.0, r, c, u_prev=0.9 * u, v_prev=0.9 * v, gamma_prev=50.0)
-    t_cert = (time.perf_counter() - t0) / n_cert_sample
-    est = sweeps * t_sweep + stages * t_cert
+
+    def sample(ns, nc):
+        t0 = time.perf_counter()
+        for k in range(ns):
+            O.lse2(C64, u, v, 16.0 * 2 ** (k / 3))
+        t_sweep = (time.perf_counter() - t0) / ns
+        t0 = time.perf_counter()
+        for k in range(nc):
+            O.round_certify(C64, u, v, 64.0, r, c, u_prev=0.9 * u, v_prev=0.9 * v, gamma_prev=50.0)
+        return t_sweep, (time.perf_counter() - t0) / nc
+
+    threads = O.num_threads()
+    t_sweep, t_cert = sample(n_sweeps_sample, n_cert_sample)
+    O.set_num_threads(1)
+    try:
+        t_sweep1, t_cert1 = sample(max(2, n_sweeps_sample // 5), 1)
+    finally:
+        O.set_num_threads(0)
+    per = [sw * t_sweep + st * t_cert for sw, st in gpu_counts]
+    per1 = [sw * t_sweep1 + st * t_cert1 for sw, st in gpu_counts]
     return {
-        "value": round(est, 3),
+        "value": round(statistics.mean(per), 3),
         "unit": "s",
-        "cores": O.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"FP64 C oracle on {label} (n={r.size}): {n_sweeps_sample} two-sided LSE sweeps "
-                   f"({t_sweep:.4f} s each) and {n_cert_sample} round+certify evaluations ({t_cert:.3f} s each), "
-                   f"extrapolated to the GPU solve's {sweeps} sweeps and {stages} certified stages"),
+        "sample": (f"FP64 C oracle (gcc -O3 -march=x86-64-v3, OpenMP over rows/columns) on {label} (n={r.size}): "
+                   f"{n_sweeps_sample} two-sided LSE sweeps ({t_sweep:.4f} s each) and {n_cert_sample} round+certify "
+                   f"evaluations ({t_cert:.3f} s each) on {threads} threads, extrapolated to each of the "
+                   f"{len(per)} problems' sweep and certified-stage counts; value = mean over the problems"),
+        "cpu_model": _cpu_model(),
+        "per_problem_s": [round(x, 2) for x in per],
+        "one_thread": {"value": round(statistics.mean(per1), 3), "unit": "s", "cores": 1,
+                       "sweep_s": round(t_sweep1, 4), "round_certify_s": round(t_cert1, 3)},
     }
 
 
@@ -182,15 +225,19 @@ def bench_grid(args) -> dict:
         solve(probs[i % len(probs)])
     torch.cuda.synchronize()
     results, step_times = [], []
-    t_start = time.perf_counter()
+    per_prob = [[] for _ in probs]
     for i in range(args.steps):
         t0 = time.perf_counter()
         res = solve(probs[i % len(probs)])
         torch.cuda.synchronize()
         step_times.append(time.perf_counter() - t0)
+        per_prob[i % len(probs)].append(step_times[-1])
         results.append(res)
     torch.cuda.synchronize()
-    mean_s = (time.perf_counter() - t_start) / args.steps
+    # each problem's runs are averaged first, so steps that are not a multiple of the problem
+    # count do not weight some problems more than others
+    prob_means = [statistics.mean(t) for t in per_prob if t]
+    mean_s = statistics.mean(prob_means)
     # FP16/BF16 storage certifies the gap of the stored cost. Every plan's cost differs by at most
     # delta = max |C_stored - C_exact| between the stored and the exact FP64 cost (total mass 1),
     # so the returned plan is within gap + 2 delta of the exact problem's optimum.
@@ -245,6 +292,8 @@ def bench_grid(args) -> dict:
             "problems": len(probs),
             "cost_storage": args.cost_storage,
         },
+        "time_to_gap_per_problem_s": {f"{p['family']}/{p['cost']}": round(statistics.mean(t), 6)
+                                      for p, t in zip(probs, per_prob) if t},
         "time_to_gap_median_s": round(statistics.median(step_times), 6),
         "time_to_gap_max_s": round(max(step_times), 6),
         "certified_gap_max": max(r.gap for r in results),
@@ -259,13 +308,35 @@ def bench_grid(args) -> dict:
     if error_vs_exact is not None:
         out["error_vs_exact_cost"] = error_vs_exact
         out["error_bound_exact_cost_max"] = max(e["error_bound_exact_cost"] for e in error_vs_exact)
+    if args.legs and args.cost_storage == "f32" and args.precision == "f32":
+        out["lse_sweep_flushed"] = flushed_sweep(ctx, costs[p0["cost"]]["desc"](), u, v, r0.gamma_final, n,
+                                                 BYTES[args.cost_storage])
     if not args.no_cpu_baseline:
         big = n > 8192
-        out["cpu_baseline"] = cpu_baseline(costs[p0["cost"]]["host64"](), p0, r0.sweeps, r0.stages,
+        counts = []
+        for i, p in enumerate(probs):
+            rs = [r for j, r in enumerate(results) if j % len(probs) == i]
+            if rs:
+                counts.append((rs[0].sweeps, rs[0].stages))
+        out["cpu_baseline"] = cpu_baseline(costs[p0["cost"]]["host64"](), probs, counts,
                                            n_sweeps_sample=6 if big else 20, n_cert_sample=1 if big else 3,
-                                           label=f"the first problem ({p0['family']}/{p0['cost']})")
+                                           label=f"the first problem's cost ({p0['cost']})")
     ctx.close()
     return out
+
+
+def flushed_sweep(ctx, desc, u, v, gamma, n, nbytes):
+    """The LSE sweep timed alone after a 512 MiB read evicts the cost from the L2s and the 256 MB
+    last-level cache: every sweep streams the whole matrix from HBM."""
+    import torch
+
+    flush = torch.ones(64 << 20, dtype=torch.float64, device=u.device)  # 512 MiB
+    ms = ctx.bench_sweep_flushed(desc, u, v, gamma, flush, precision="f32", iters=40)
+    del flush
+    achieved = n * n * nbytes / (ms * 1e-3) / 1e9
+    return {"us": round(ms * 1e3, 3), "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "bytes_per_launch": n * n * nbytes,
+            "note": "each sweep timed alone (HIP events) after a 512 MiB read evicts the cost from L2 and MALL"}
 
 
 def bench_grid_batched(args) -> dict:
@@ -358,6 +429,103 @@ def bench_grid_batched(args) -> dict:
     }
 
 
+def leg_single(args, precision: str, problems=None, target=None, **kw) -> dict:
+    """Single solves (mdot_solve), each problem once after one warm-up solve: mean time-to-gap."""
+    import torch
+
+    from paper_2307_08507_amd import mdot as M
+
+    dev = torch.device("cuda", 0)
+    k = args.grid
+    n = k * k
+    probs = build_problems(k, args.problems)
+    if problems is not None:
+        probs = [probs[i] for i in problems]
+    costs = {kind: grid_cost_device(k, kind, args.cost_storage, dev) for kind in {p["cost"] for p in probs}}
+    ctx = M.Context(0)
+    prm = M.default_params(precision=precision, **kw)
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+    v = torch.empty_like(u)
+    tg = args.target if target is None else target
+    out = []
+    for i, p in enumerate(probs):
+        rd = torch.tensor(p["r"], dtype=torch.float64, device=dev)
+        cd = torch.tensor(p["c"], dtype=torch.float64, device=dev)
+        if i == 0:
+            ctx.solve(costs[p["cost"]]["desc"](), rd, cd, tg, prm, u, v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.solve(costs[p["cost"]]["desc"](), rd, cd, tg, prm, u, v)
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0, res))
+    ctx.close()
+    return {"time_to_gap_s": round(statistics.mean(t for t, _ in out), 6),
+            "all_certified": all(r.status == 0 and (kw.get("gamma_f") or r.gap <= tg) for _, r in out),
+            "sweeps_mean": statistics.mean(r.sweeps for _, r in out),
+            "per_problem": [{"problem": f"{p['family']}/{p['cost']}", "s": round(t, 5), "sweeps": r.sweeps,
+                             "gap": r.gap, "status": r.status} for p, (t, r) in zip(probs, out)]}
+
+
+def leg_projectors(args) -> dict:
+    """PNCG against the Sinkhorn projector (Alg. 4) inside the same annealing schedule, on the L1
+    grid problems (the paper's comparison uses L1 costs at n=4096): LSE sweeps and time per
+    solve at fixed gamma_f (the paper's setting), both with FP32 sweeps."""
+    import argparse as _ap
+
+    a = _ap.Namespace(**vars(args))
+    l1 = [i for i, p in enumerate(build_problems(args.grid, args.problems)) if p["cost"] == "l1"]
+    out = {}
+    for gf in (2.0**9, 2.0**12):
+        pn = leg_single(a, "f32", problems=l1, gamma_f=gf)
+        sk = leg_single(a, "f32", problems=l1, gamma_f=gf, projector=1)
+        out[f"gamma_f=2^{int(round(math.log2(gf)))}"] = {
+            "pncg_sweeps_mean": pn["sweeps_mean"], "sinkhorn_sweeps_mean": sk["sweeps_mean"],
+            "sweep_ratio_sinkhorn_over_pncg": round(sk["sweeps_mean"] / pn["sweeps_mean"], 3),
+            "pncg_s": pn["time_to_gap_s"], "sinkhorn_s": sk["time_to_gap_s"],
+            "status_ok": all(q["status"] == 0 for q in pn["per_problem"] + sk["per_problem"])}
+    return out
+
+
+def run_legs(args, head: dict) -> dict:
+    """The rest of the metric beside the headline: FP64 and MIXED single solves, the batched
+    engine (FP32 and MIXED), PNCG against the Sinkhorn projector, and a short serving run."""
+    import argparse as _ap
+
+    legs = {}
+    t0 = time.perf_counter()
+    legs["f64"] = leg_single(args, "f64")
+    legs["mixed"] = leg_single(args, "mixed")
+    print(f"legs: single f64/mixed done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    for prec in ("f32", "mixed"):
+        a = _ap.Namespace(**vars(args))
+        a.steps, a.warmup, a.precision = 2, 1, prec
+        b = bench_grid_batched(a)
+        legs[f"batched_{prec}"] = {k: b[k] for k in ("value", "unit", "batch_wall_s", "latency_p50_s",
+                                                     "latency_p99_s", "all_certified", "sweeps_mean",
+                                                     "sample_bitwise_equal_to_alone")}
+    print(f"legs: batched done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    legs["projectors"] = leg_projectors(args)
+    print(f"legs: projectors done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    a = _ap.Namespace(**vars(args))
+    a.requests = args.leg_requests
+    srv = bench_serving(a)
+    legs["serving"] = {k: srv[k] for k in ("value", "unit", "saturation_rps", "latency_p50_s", "latency_p99_s",
+                                           "latency_max_s", "all_certified", "sample_bitwise_equal_to_alone",
+                                           "hbm_budget_bytes", "peak_bytes_in_use")}
+    legs["serving"]["workload"] = srv["config"]["workload"]
+    print(f"legs: serving done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    fp32 = head["value"]
+    legs["summary"] = {
+        "fp32_single_s": fp32,
+        "f64_single_s": legs["f64"]["time_to_gap_s"],
+        "mixed_single_s": legs["mixed"]["time_to_gap_s"],
+        "fp32_batched_per_solve_s": legs["batched_f32"]["value"],
+        "mixed_batched_per_solve_s": legs["batched_mixed"]["value"],
+        "mixed_batched_vs_fp32_single": round(legs["batched_mixed"]["value"] / fp32, 4),
+    }
+    return legs
+
+
 def bench_serving(args) -> dict:
     import numpy as np
     import torch
@@ -376,8 +544,10 @@ def bench_serving(args) -> dict:
     prm = M.default_params(precision=args.precision)
     torch.cuda.synchronize()
 
+    peak = [0]
+
     def run(arrivals):
-        eng = M.Context(0)
+        eng = M.Context(0, hbm_budget_bytes=args.hbm_budget)
         order = sorted(range(len(reqs)), key=lambda i: arrivals[i])
         nxt, tickets, done = 0, {}, {}
         t0 = time.perf_counter()
@@ -391,6 +561,7 @@ def bench_serving(args) -> dict:
                 tickets[t] = order[nxt]
                 nxt += 1
             if tickets:
+                peak[0] = max(peak[0], eng.inflight()[1])
                 eng.run(8)
                 now = time.perf_counter() - t0
                 for t in list(tickets):
@@ -436,6 +607,8 @@ def bench_serving(args) -> dict:
                                 f"Dirichlet(1) marginals, squared-Euclidean cost / max, target gap in "
                                 f"{{1e-4, 1e-5, 1e-6, 1e-7}}")},
         "saturation_rps": round(sat, 3),
+        "hbm_budget_bytes": args.hbm_budget,
+        "peak_bytes_in_use": peak[0],
         "latency_p50_s": round(lat_s[len(lat_s) // 2], 4),
         "latency_p99_s": round(lat_s[min(len(lat_s) - 1, int(0.99 * len(lat_s)))], 4),
         "latency_max_s": round(lat_s[-1], 4),
@@ -461,6 +634,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", action="store_true",
                     help="grid workload: submit the problems together to the batched engine")
+    ap.add_argument("--hbm-budget", type=int, default=1 << 30,
+                    help="serving: HBM bytes the engine may hold for solves in flight (admission bound)")
+    ap.add_argument("--no-legs", dest="legs", action="store_false",
+                    help="default workload: report the headline only (no FP64/MIXED/batched/projector/serving "
+                         "legs and no flushed-cache sweep)")
+    ap.add_argument("--leg-requests", type=int, default=128, help="requests of the serving leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on one GPU; "
@@ -468,8 +647,13 @@ def main() -> int:
         return 2
     if args.workload == "serving":
         out = bench_serving(args)
+    elif args.batched:
+        out = bench_grid_batched(args)
     else:
-        out = bench_grid_batched(args) if args.batched else bench_grid(args)
+        out = bench_grid(args)
+        default = (args.grid == 64 and args.cost_storage == "f32" and args.precision == "f32" and args.target == 1e-6)
+        if args.legs and default:
+            out["legs"] = run_legs(args, out)
     print(json.dumps(out), flush=True)
     return 0
 

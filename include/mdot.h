@@ -252,6 +252,15 @@ int mdot_inflight(mdot_ctx* ctx, int* n_active, size_t* bytes_in_use);
 int mdot_bench_sweep(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
                      mdot_precision precision, int iters, double* ms_per_sweep);
 
+/* Measurement hook: as mdot_bench_sweep, but each of the `iters` sweeps (1..256) is timed alone
+ * with HIP events after a kernel reads the caller's buffer `flush` (device, flush_bytes; make it
+ * larger than the last-level cache, e.g. 512 MiB), so every sweep finds the cost evicted from
+ * the L2 and last-level caches and streams it from HBM. The buffer is read, not written (one
+ * element is written only if the buffer's sum is exactly -1.2345e300). Synchronous. */
+int mdot_bench_sweep_flushed(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v,
+                             double gamma, mdot_precision precision, int iters, const void* flush,
+                             size_t flush_bytes, double* ms_per_sweep);
+
 /* Text of the last error on this context (never NULL). */
 const char* mdot_last_error(const mdot_ctx* ctx);
 

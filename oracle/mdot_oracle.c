@@ -170,6 +170,19 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops (over independent rows or columns only, so the results do not
+ * depend on it); k < 1 restores the OpenMP default. Used to time the oracle on one core. */
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    static int deflt = 0;
+    if (!deflt) deflt = omp_get_max_threads();
+    omp_set_num_threads(k >= 1 ? k : deflt);
+#else
+    (void)k;
+#endif
+}
+
 /* Shannon entropy H(r) = -<r, log r> with 0 log 0 = 0 (Sec. 2, Notation). */
 double orc_entropy(int n, const double* r)
 {

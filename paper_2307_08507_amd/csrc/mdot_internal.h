@@ -227,6 +227,9 @@ int noalloc_scratch(int device, void** out);
 // Fill count doubles at dst with val (a kernel, so the fill is an ordinary kernel node if the
 // caller's stream is being captured).
 int launch_fill(double* dst, size_t count, double val, void* stream);
+// Read count doubles at src (cache eviction for cold-cache timing); sink[0] is written only if
+// their sum is -1.2345e300.
+int launch_touch(const double* src, size_t count, double* sink, void* stream);
 
 // Host-side launchers (mdot_kernels.hip). `hw` is the host copy of the Work struct (sizes
 // and cost type pick the grid and the kernel instance), `wd` its device copy.

@@ -2261,6 +2261,24 @@ __global__ void __launch_bounds__(256) k_fill(double* __restrict__ dst, size_t c
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) dst[i] = val;
 }
 
+// Read `count` doubles (used to evict a matrix from the L2 and last-level caches between timed
+// sweeps by filling them with other, clean lines); the sum is stored only if it equals `never`,
+// which keeps the loads without writing anything in practice.
+__global__ void __launch_bounds__(256) k_touch(const double* __restrict__ src, size_t count, double never,
+                                               double* sink)
+{
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) acc += src[i];
+    if (acc == never) sink[0] = acc;
+}
+
+int launch_touch(const double* src, size_t count, double* sink, void* stream)
+{
+    if (count == 0) return 0;
+    hipLaunchKernelGGL(k_touch, dim3(4096), dim3(256), 0, (hipStream_t)stream, src, count, -1.2345e300, sink);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_fill(double* dst, size_t count, double val, void* stream)
 {
     if (count == 0) return 0;

@@ -80,6 +80,8 @@ def lib():
                                          ct.POINTER(ct.c_double)]
         L.mdot_bench_sweep.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, ct.c_int, ct.c_int,
                                        ct.POINTER(ct.c_double)]
+        L.mdot_bench_sweep_flushed.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, ct.c_int, ct.c_int,
+                                               vp, ct.c_size_t, ct.POINTER(ct.c_double)]
         L.mdot_submit.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, ct.POINTER(Params), dp, dp,
                                   ct.POINTER(ct.c_uint64)]
         L.mdot_run.argtypes = [vp, ct.c_int, ct.POINTER(ct.c_int)]
@@ -257,6 +259,18 @@ class Context:
         prec = PREC_F64 if precision == "f64" else PREC_F32
         rc = lib().mdot_bench_sweep(self._h, ct.byref(cost), _ptr(u), _ptr(v), float(gamma), prec, int(iters),
                                     ct.byref(ms))
+        self._check(rc)
+        return ms.value
+
+    def bench_sweep_flushed(self, cost: CostDesc, u, v, gamma: float, flush, precision: str = "f32",
+                            iters: int = 20) -> float:
+        """Mean milliseconds per fused LSE sweep, each timed alone after reading `flush` (a device
+        tensor larger than the last-level cache) to evict the cost from the caches."""
+        ms = ct.c_double()
+        prec = PREC_F64 if precision == "f64" else PREC_F32
+        rc = lib().mdot_bench_sweep_flushed(self._h, ct.byref(cost), _ptr(u), _ptr(v), float(gamma), prec,
+                                            int(iters), flush.data_ptr(), flush.numel() * flush.element_size(),
+                                            ct.byref(ms))
         self._check(rc)
         return ms.value
 
