@@ -261,6 +261,23 @@ int mdot_bench_sweep_flushed(mdot_ctx* ctx, const mdot_cost_desc* cost, const do
                              double gamma, mdot_precision precision, int iters, const void* flush,
                              size_t flush_bytes, double* ms_per_sweep);
 
+/* ---- Launch-variant tuning ----
+ * The sweep kernel exists in variants that compute the same values bit for bit and differ only
+ * in speed: capped at 4 waves per SIMD (128 VGPRs) or 2 (256 VGPRs), and, for FP32 costs, with or
+ * without staging its second batch of cost rows in LDS. mdot_ctx_create reads the choice per
+ * cost type and size from a table: the file named by the environment variable MDOT_TUNING, else
+ * tuning.json in the directory above the one holding libmdot.so (written by the package's
+ * tuner, tune.py, from measurements on the GPU); without a table every size uses 4 waves per
+ * SIMD and staging above 2048 tiles.
+ *
+ * mdot_tune_override: force a variant for the later calls on this context (the tuner uses it):
+ * occ = 2 or 4 (0 = the table's), stage = 0 (never stage), 1 (always stage) or -1 (the
+ * table's). Returns MDOT_OK or MDOT_E_ARG.
+ * mdot_tune_variant: the variant a call on `cost` would take: *occ (2 or 4) and
+ * *stage_min_tiles (FP32 costs stage with more tiles than this). Host pointers. */
+int mdot_tune_override(mdot_ctx* ctx, int occ, int stage);
+int mdot_tune_variant(mdot_ctx* ctx, const mdot_cost_desc* cost, int* occ, int* stage_min_tiles);
+
 /* Text of the last error on this context (never NULL). */
 const char* mdot_last_error(const mdot_ctx* ctx);
 

@@ -12,12 +12,14 @@
 // intake runs on a side stream, a retiring solve's potentials and state are copied out behind
 // the chunk in flight (its workspace returns to the pool once that copy has completed), and
 // the batch descriptor is uploaded from alternating host buffers.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -79,8 +81,17 @@ struct Slot {
 
 }  // namespace
 
+// One entry of the launch-variant table (written by paper_2307_08507_amd/tune.py): for cost
+// type `code` (a base cost code, planar point codes separate) and sizes up to n_max, the sweep
+// instance at 2 waves per SIMD (occ 2) or 4 (occ 4), and the LDS staging threshold in tiles.
+struct TuneEntry {
+    int code = 0, n_max = 0, occ = 4, stage_min_tiles = kStageMinTilesDefault;
+};
+
 struct mdot_ctx {
     int device = 0;
+    std::vector<TuneEntry> tuning;  // sorted by (code, n_max)
+    int force_occ = 0, force_stage = -1;  // mdot_tune_override
     hipStream_t stream = nullptr;
     size_t budget = 0;
     std::string err;
@@ -236,6 +247,78 @@ static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n, hipStream_t s
     return ensure_scratch(ctx, n);
 }
 
+// Names of the base cost codes in the tuning file (the order of CostCode in the kernels).
+static const char* const kCodeNames[kCostCodes] = {"f64", "f32", "f16", "bf16", "pts_sq", "pts_l1", "pts_sq2",
+                                                   "pts_l12"};
+
+// Read the tuning table: $MDOT_TUNING, else tuning.json in the package directory (the parent of
+// the directory holding libmdot.so). The file is JSON written one entry per line by the tuner:
+//   {"code": "f32", "n_max": 4096, "occ": 4, "stage_min_tiles": 2048, ...}
+// Unknown fields are ignored; a missing or unreadable file leaves the built-in defaults (occ 4,
+// staging above kStageMinTilesDefault tiles). The variants never change results.
+static void load_tuning(mdot_ctx* ctx)
+{
+    std::string path;
+    if (const char* env = std::getenv("MDOT_TUNING")) {
+        path = env;
+    } else {
+        Dl_info info;
+        if (dladdr((void*)&load_tuning, &info) && info.dli_fname) {
+            std::string so = info.dli_fname;
+            const size_t a = so.find_last_of('/');
+            std::string dir = a == std::string::npos ? "." : so.substr(0, a);
+            const size_t b = dir.find_last_of('/');
+            path = (b == std::string::npos ? std::string(".") : dir.substr(0, b)) + "/tuning.json";
+        }
+    }
+    FILE* f = path.empty() ? nullptr : std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    auto field = [](const char* l, const char* key, int* out) {
+        const char* p = std::strstr(l, key);
+        if (!p) return false;
+        p = std::strchr(p + std::strlen(key), ':');
+        return p && std::sscanf(p + 1, " %d", out) == 1;
+    };
+    while (std::fgets(line, sizeof line, f)) {
+        const char* c = std::strstr(line, "\"code\"");
+        if (!c) continue;
+        char name[32] = {0};
+        if (std::sscanf(std::strchr(c + 6, ':') + 1, " \"%31[^\"]\"", name) != 1) continue;
+        TuneEntry e;
+        e.code = -1;
+        for (int k = 0; k < kCostCodes; ++k)
+            if (!std::strcmp(name, kCodeNames[k])) e.code = k;
+        if (e.code < 0 || !field(line, "\"n_max\"", &e.n_max) || !field(line, "\"occ\"", &e.occ) ||
+            !field(line, "\"stage_min_tiles\"", &e.stage_min_tiles))
+            continue;
+        if (e.occ != 2 && e.occ != 4) continue;
+        ctx->tuning.push_back(e);
+    }
+    std::fclose(f);
+    std::sort(ctx->tuning.begin(), ctx->tuning.end(), [](const TuneEntry& a, const TuneEntry& b) {
+        return a.code != b.code ? a.code < b.code : a.n_max < b.n_max;
+    });
+}
+
+// The launch variant for base cost code `code` at size n: the first table entry of that code
+// with n <= n_max (defaults if none), then the context's overrides.
+static void pick_variant(const mdot_ctx* ctx, int code, int n, int* occ2, int* stage_min_tiles)
+{
+    int occ = 4, st = kStageMinTilesDefault;
+    for (const TuneEntry& e : ctx->tuning)
+        if (e.code == code && n <= e.n_max) {
+            occ = e.occ;
+            st = e.stage_min_tiles;
+            break;
+        }
+    if (ctx->force_occ) occ = ctx->force_occ;
+    if (ctx->force_stage == 0) st = 0x7fffffff;
+    if (ctx->force_stage == 1) st = 0;
+    *occ2 = occ == 2;
+    *stage_min_tiles = st;
+}
+
 // Lay the Work struct out over pb's workspace for size n (n <= cap_n) and upload it.
 static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc* cost, double scale,
                      const double* r, const double* c, hipStream_t stream)
@@ -257,6 +340,10 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
     w.cost_kind = cost ? cost->kind : MDOT_COST_DENSE;
     w.dtype = cost ? cost->dtype : MDOT_DT_F32;
     w.d = cost ? cost->d : 0;
+    {
+        const int cc = cost_code_of(w.cost_kind, w.dtype);
+        pick_variant(ctx, w.d <= 2 ? cost_code_planar(cc) : cc, n, &w.occ2, &w.stage_min_tiles);
+    }
     w.cost = cost ? cost->data : nullptr;
     w.scale = scale;
     w.r = r;
@@ -591,8 +678,7 @@ static int rebuild_batch(mdot_ctx* ctx)
             if (y.cost == x.cost && y.n == x.n && y.d == x.d && y.cost_kind == x.cost_kind && y.dtype == x.dtype)
                 taken[b] = true;
         }
-        const int cc = cost_code_of(hw[a]->cost_kind, hw[a]->dtype);
-        const int code = hw[a]->d <= 2 ? cost_code_planar(cc) : cc;
+        const int code = cost_code(*hw[a]);  // includes the tuned occupancy variant
         if (code < 0 || code >= kMaxCodes)  // every code must get a tile range below
             return fail(ctx, MDOT_E_DEVICE, "cost code %d has no batched sweep range", code);
         gfirst[ngr] = a;
@@ -778,6 +864,29 @@ void mdot_default_params(mdot_params* out)
 
 const char* mdot_last_error(const mdot_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+int mdot_tune_override(mdot_ctx* ctx, int occ, int stage)
+{
+    if (!ctx) return MDOT_E_ARG;
+    if ((occ != 0 && occ != 2 && occ != 4) || stage < -1 || stage > 1)
+        return fail(ctx, MDOT_E_ARG, "bad variant override (occ %d, stage %d)", occ, stage);
+    ctx->force_occ = occ;
+    ctx->force_stage = stage;
+    return MDOT_OK;
+}
+
+int mdot_tune_variant(mdot_ctx* ctx, const mdot_cost_desc* cost, int* occ, int* stage_min_tiles)
+{
+    if (!ctx || !occ || !stage_min_tiles) return MDOT_E_ARG;
+    int rc = check_cost_desc(ctx, cost);
+    if (rc) return rc;
+    const int cc = cost_code_of(cost->kind, cost->dtype);
+    int o2 = 0;
+    pick_variant(ctx, cost->kind != MDOT_COST_DENSE && cost->d <= 2 ? cost_code_planar(cc) : cc, cost->n, &o2,
+                 stage_min_tiles);
+    *occ = o2 ? 2 : 4;
+    return MDOT_OK;
+}
+
 int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_ctx** out)
 {
     if (!out) return MDOT_E_ARG;
@@ -788,6 +897,7 @@ int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_
     if (hipSetDevice(device) != hipSuccess) return MDOT_E_DEVICE;
     mdot_ctx* ctx = new mdot_ctx();
     ctx->device = device;
+    load_tuning(ctx);
     ctx->stream = (hipStream_t)hip_stream;
     ctx->budget = hbm_budget_bytes;
     bool ok = hipHostMalloc(&ctx->h_state, sizeof(State), hipHostMallocDefault) == hipSuccess &&

@@ -119,6 +119,10 @@ struct Work {
     int32_t n, nrt, nct;     // size, row tiles, column tiles
     int32_t cost_kind, dtype, d, fin_per;  // cost kind and dtype, point dimension, fin_per(n)
     int32_t fin_L, fin_lgL, fin_nvb, fin_nblk;  // fin_lanes(n), log2 of it, fin_vblocks(n), fin_grid(n)
+    // launch variant from the tuning table (neither changes any arithmetic): occ2 = 1 runs the
+    // sweep instance capped at 2 waves per SIMD (256 VGPRs) instead of 4 (128 VGPRs); FP32 sweeps
+    // of more than stage_min_tiles tiles stage their second row batch in LDS
+    int32_t occ2, stage_min_tiles;
     const void* cost;        // dense cost or coordinates X then Y
     double scale;            // C = scale * raw
     const double* r;         // original marginals
@@ -171,7 +175,10 @@ struct Control {
 // one cost tile land on the same XCD (workgroups go round-robin over the 8 XCDs) at nearly the
 // same time, so the cost is read from HBM once per group and from that XCD's L2 by the rest.
 constexpr int kMaxBatch = 64;
-constexpr int kMaxCodes = 8;  // sweep kernel instances (cost codes)
+constexpr int kCostCodes = 8;            // cost types (dense dtypes, point metrics, planar point metrics)
+constexpr int kOccHi = 8;                // code bit: the same cost type at 2 waves per SIMD
+constexpr int kMaxCodes = 2 * kCostCodes;  // sweep kernel instances
+constexpr int kStageMinTilesDefault = 2048;
 struct BatchDesc {
     int32_t nitems, total_tiles, total_fin, ngroups;
     int32_t fin_prefix[kMaxBatch + 1];
@@ -247,7 +254,8 @@ int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, doubl
 int cost_code_of(int cost_kind, int dtype);
 // The planar (d <= 2) instance of a point cost code; other codes are returned unchanged.
 int cost_code_planar(int cost_code);
-// The sweep kernel instance a single-problem launch of hw takes (its cost code, planar for d <= 2).
+// The sweep kernel instance a launch of hw takes (its cost code, planar for d <= 2, plus kOccHi
+// for the 2-waves-per-SIMD variant).
 int cost_code(const Work& hw);
 // big: some problem in flight has n > 8192 (the finalize instance for fin_per(n) = 32)
 int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, bool big, void* stream);

@@ -555,7 +555,6 @@ constexpr int kRowPad = 65;
 // second batch of cost rows by direct-to-LDS loads and then, once the wave has read them, holds
 // its row-partial transpose buffer and its slice of the column combine. The other tile kinds
 // use the first 5 kBR + 4 kBC doubles.
-constexpr int kStageMinTiles = 2048;                    // staging pays with more tiles than this
 constexpr int kWaveRegion = 1024;                        // 8 KiB: 8 rows x 64 lanes x 16 B
 constexpr int kRowBufD = (kRPW * kRowPad + 1) / 2;      // transpose buffer, in doubles
 static_assert(kRowBufD + kBC <= kWaveRegion, "wave region too small");
@@ -689,7 +688,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     constexpr bool kCanStage = std::is_same<Cost, DenseCost<MDOT_DT_F32>>::value && RB < kRPW;
     bool staged = false;
     if constexpr (kCanStage) {
-        staged = cost.vec && w.nrt * w.nct > kStageMinTiles;
+        staged = cost.vec && w.nrt * w.nct > w.stage_min_tiles;
         if (staged) {
 #pragma unroll
             for (int r = 0; r < RB; ++r)
@@ -1542,7 +1541,7 @@ template <> struct CostOf<CC_PTS_L12> { using T = PointCost<2, 2>; };
 template <int CC, bool E64, bool ROUND>
 __device__ __forceinline__ void sweep_tiles(const Work& w, const SweepArgs& a, const TileCtx& t, int mode, double* smem)
 {
-    using Cost = typename CostOf<CC>::T;
+    using Cost = typename CostOf<CC % kCostCodes>::T;
     if constexpr (!ROUND) {
         if (mode == SM_MAX) tile_max<Cost>(w, a, t, smem);
         else tile_lse<Cost, E64>(w, a, t, smem);
@@ -1572,7 +1571,10 @@ __device__ __forceinline__ void sweep_kernel_body(const Work& w, const SweepArgs
 
 // One kernel for every sweep mode, so a step is a fixed sequence of launches. The register
 // cap keeps four workgroups per CU (the LDS limit is five): the LSE path needs 84 VGPRs, the
-// Round paths (twice per stage) spill a few values.
+// Round paths (twice per stage) spill a few values. Point-cost codes with kOccHi set are the
+// same kernel capped at two waves per SIMD (up to 256 VGPRs: their Round paths then need no
+// spills, at lower occupancy); the tuning table picks between them per cost type and size. The
+// dense instances fit the cap without spills, so their kOccHi codes launch the same kernel.
 template <int CC>
 __device__ __forceinline__ void sweep_any(const Work& w, int parity, int blk, double* smem)
 {
@@ -1592,7 +1594,7 @@ __device__ __forceinline__ void sweep_any(const Work& w, int parity, int blk, do
 }
 
 template <int CC>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CC >= kOccHi ? 2 : 4)))
 k_sweep(const Work* __restrict__ wp, int parity)
 {
     __shared__ double smem[kSmem];
@@ -1884,7 +1886,7 @@ __device__ __forceinline__ int batch_item(const int32_t* prefix, int nitems, int
 // 8). Same register cap as the single-problem sweep; a grid-stride loop here would keep the
 // loop-invariant values of the tile code live across tiles and spill.
 template <int CC>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CC >= kOccHi ? 2 : 4)))
 k_sweep_batch(const BatchDesc* __restrict__ bd, int parity, int tile_begin, int tile_end)
 {
     __shared__ double smem[kSmem];
@@ -2028,7 +2030,7 @@ __global__ void __launch_bounds__(kWG) k_cost_range(const Work* __restrict__ wp,
 {
     const Work w = *wp;
     double lo, hi;
-    cost_range_body<typename CostOf<CC>::T>(w, &lo, &hi);
+    cost_range_body<typename CostOf<CC % kCostCodes>::T>(w, &lo, &hi);
     __shared__ double s0[kWG], s1[kWG];
     const int t = threadIdx.x;
     s0[t] = lo;
@@ -2101,23 +2103,32 @@ int cost_code_planar(int cc)
     return cc;
 }
 
-// Kernel instance of a single-problem launch: planar point clouds take the planar instance.
+// Kernel instance of a launch: planar point clouds take the planar instance, and the tuning
+// table's 2-waves-per-SIMD variant adds kOccHi.
 int cost_code(const Work& w)
 {
     const int cc = cost_code_of(w.cost_kind, w.dtype);
-    return w.d <= 2 ? cost_code_planar(cc) : cc;
+    return (w.d <= 2 ? cost_code_planar(cc) : cc) + (w.occ2 ? kOccHi : 0);
 }
 
-#define MDOT_CC_SWITCH(cc, F)         \
-    switch (cc) {                     \
-        case CC_F64: F(CC_F64); break;       \
-        case CC_F32: F(CC_F32); break;       \
-        case CC_F16: F(CC_F16); break;       \
-        case CC_BF16: F(CC_BF16); break;     \
-        case CC_PTS_SQ: F(CC_PTS_SQ); break; \
-        case CC_PTS_SQ2: F(CC_PTS_SQ2); break; \
-        case CC_PTS_L12: F(CC_PTS_L12); break; \
-        default: F(CC_PTS_L1); break;        \
+#define MDOT_CC_SWITCH(cc, F)                                          \
+    switch (cc) {                                                      \
+        case CC_F64: F(CC_F64); break;                                 \
+        case CC_F32: F(CC_F32); break;                                 \
+        case CC_F16: F(CC_F16); break;                                 \
+        case CC_BF16: F(CC_BF16); break;                               \
+        case CC_PTS_SQ: F(CC_PTS_SQ); break;                           \
+        case CC_PTS_SQ2: F(CC_PTS_SQ2); break;                         \
+        case CC_PTS_L12: F(CC_PTS_L12); break;                         \
+        case CC_PTS_L1: F(CC_PTS_L1); break;                           \
+        case kOccHi + CC_F64: F(CC_F64); break;                        \
+        case kOccHi + CC_F32: F(CC_F32); break;                        \
+        case kOccHi + CC_F16: F(CC_F16); break;                        \
+        case kOccHi + CC_BF16: F(CC_BF16); break;                      \
+        case kOccHi + CC_PTS_SQ: F(kOccHi + CC_PTS_SQ); break;         \
+        case kOccHi + CC_PTS_SQ2: F(kOccHi + CC_PTS_SQ2); break;       \
+        case kOccHi + CC_PTS_L12: F(kOccHi + CC_PTS_L12); break;       \
+        default: F(kOccHi + CC_PTS_L1); break;                         \
     }
 
 int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
@@ -2186,7 +2197,7 @@ int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream
 {
     const int tiles = hw.nrt * hw.nct;
 #define L_(CC) hipLaunchKernelGGL(k_cost_range<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, part)
-    MDOT_CC_SWITCH(cost_code(hw), L_)
+    MDOT_CC_SWITCH(cost_code(hw) % kCostCodes, L_)
 #undef L_
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -82,6 +82,8 @@ def lib():
                                        ct.POINTER(ct.c_double)]
         L.mdot_bench_sweep_flushed.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, ct.c_int, ct.c_int,
                                                vp, ct.c_size_t, ct.POINTER(ct.c_double)]
+        L.mdot_tune_override.argtypes = [vp, ct.c_int, ct.c_int]
+        L.mdot_tune_variant.argtypes = [vp, ct.POINTER(CostDesc), ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
         L.mdot_submit.argtypes = [vp, ct.POINTER(CostDesc), dp, dp, ct.c_double, ct.POINTER(Params), dp, dp,
                                   ct.POINTER(ct.c_uint64)]
         L.mdot_run.argtypes = [vp, ct.c_int, ct.POINTER(ct.c_int)]
@@ -273,6 +275,16 @@ class Context:
                                             ct.byref(ms))
         self._check(rc)
         return ms.value
+
+    def tune_override(self, occ: int = 0, stage: int = -1) -> None:
+        """Force a sweep launch variant (occ 2 or 4, stage 0/1) for later calls; 0/-1: the table's."""
+        self._check(lib().mdot_tune_override(self._h, int(occ), int(stage)))
+
+    def tune_variant(self, cost: CostDesc) -> tuple[int, int]:
+        """(waves per SIMD, staging threshold in tiles) a call on `cost` takes."""
+        o, s = ct.c_int(), ct.c_int()
+        self._check(lib().mdot_tune_variant(self._h, ct.byref(cost), ct.byref(o), ct.byref(s)))
+        return o.value, s.value
 
     def round_certify(self, cost: CostDesc, u, v, gamma: float, r, c, u_prev=None, v_prev=None,
                       gamma_prev: float = 0.0):
