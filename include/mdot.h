@@ -75,7 +75,7 @@ typedef enum { MDOT_DT_F64 = 0, MDOT_DT_F32 = 1, MDOT_DT_F16 = 2, MDOT_DT_BF16 =
  * the exact cost, and the certified gap refers to it. */
 typedef enum { MDOT_PREC_F64 = 0, MDOT_PREC_F32 = 1, MDOT_PREC_MIXED = 2 } mdot_precision;
 
-#define MDOT_MAX_N 65536 /* largest n; larger sizes return MDOT_E_ARG */
+#define MDOT_MAX_N 131072 /* largest n; larger sizes return MDOT_E_ARG */
 #define MDOT_NOALLOC_MAX_N 4096 /* largest n of mdot_lse2_noalloc */
 
 typedef struct {

@@ -1067,11 +1067,11 @@ __device__ __forceinline__ double fold_op(double acc, double x, double f)
 }
 
 // Lane l of an entry's L-lane group folds partials l, l + L, l + 2L, ... of the m partials at
-// base[I * stride], in that order, 8 loads in flight at a time. With `shift` (column LSE
-// partials) partial I is scaled by exp(shift[I] - M).
+// base[I * stride], in that order, 8 loads in flight at a time. With `fac` (column LSE
+// partials) partial I is scaled by fac[I] = exp(S_I - M), a table the workgroup forms once.
 template <int OP>
 __device__ __forceinline__ double lane_fold(const double* __restrict__ base, size_t stride, int l, int L, int m,
-                                            const double* __restrict__ shift, double M, bool use)
+                                            const double* __restrict__ fac, bool use)
 {
     double acc = (OP == 0) ? 0.0 : (OP == 1 ? INFINITY : -INFINITY);
     if (!use) return acc;
@@ -1081,12 +1081,12 @@ __device__ __forceinline__ double lane_fold(const double* __restrict__ base, siz
         for (int u = 0; u < 8; ++u) {
             const int I = q0 + u * L;
             x[u] = (I < m) ? base[(size_t)I * stride] : 0.0;
-            f[u] = (shift && I < m) ? shift[I] : M;
+            f[u] = (fac && I < m) ? fac[I] : 1.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int I = q0 + u * L;
-            if (I < m) acc = fold_op<OP>(acc, x[u], shift ? exp(f[u] - M) : 1.0);
+            if (I < m) acc = fold_op<OP>(acc, x[u], f[u]);
         }
     }
     return acc;
@@ -1111,7 +1111,7 @@ __device__ __forceinline__ double group_fold(double v, int L)
 
 // Combine the tile partials of entry k (row k < n, column k - n otherwise) for `mode`.
 // Called by every lane of the wave; `valid` is false past the end of the 2n-vector.
-__device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool valid, int l, int L, double M)
+__device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool valid, int l, int L, const double* fac)
 {
     const int n = w.n;
     const bool row = k < n;
@@ -1119,19 +1119,19 @@ __device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool val
     const size_t ix = row ? (size_t)k : (size_t)(k - n);
     Comb cb{0.0, INFINITY, INFINITY, 0.0, 0.0};
     if (mode == SM_LSE) {
-        cb.a = group_fold<0>(lane_fold<0>((row ? w.rowpart : w.colpart) + ix, n, l, L, m, row ? nullptr : w.tshift, M, valid), L);
+        cb.a = group_fold<0>(lane_fold<0>((row ? w.rowpart : w.colpart) + ix, n, l, L, m, row ? nullptr : fac, valid), L);
     } else if (mode == SM_MAX) {
-        cb.b = group_fold<2>(lane_fold<2>((row ? w.rowmin : w.colmin) + ix, n, l, L, m, nullptr, 0.0, valid), L);
+        cb.b = group_fold<2>(lane_fold<2>((row ? w.rowmin : w.colmin) + ix, n, l, L, m, nullptr, valid), L);
     } else {
         const double* mn = (row ? w.rowmin : w.colmin) + ix;
-        cb.b = group_fold<1>(lane_fold<1>(mn, n, l, L, m, nullptr, 0.0, valid), L);
-        cb.c = group_fold<1>(lane_fold<1>(mn + (size_t)m * n, n, l, L, m, nullptr, 0.0, valid), L);
+        cb.b = group_fold<1>(lane_fold<1>(mn, n, l, L, m, nullptr, valid), L);
+        cb.c = group_fold<1>(lane_fold<1>(mn + (size_t)m * n, n, l, L, m, nullptr, valid), L);
         if (mode == SM_R1) {
-            cb.a = group_fold<0>(lane_fold<0>(w.colpart + ix, n, l, L, m, w.tshift, M, valid && !row), L);
+            cb.a = group_fold<0>(lane_fold<0>(w.colpart + ix, n, l, L, m, fac, valid && !row), L);
         } else {
-            cb.a = group_fold<0>(lane_fold<0>(w.rowpart + ix, n, l, L, m, nullptr, 0.0, valid && row), L);
-            cb.d = group_fold<0>(lane_fold<0>(w.rowpart2 + ix, n, l, L, m, nullptr, 0.0, valid && row), L);
-            cb.e = group_fold<0>(lane_fold<0>(w.rowpart3 + ix, n, l, L, m, nullptr, 0.0, valid && row), L);
+            cb.a = group_fold<0>(lane_fold<0>(w.rowpart + ix, n, l, L, m, nullptr, valid && row), L);
+            cb.d = group_fold<0>(lane_fold<0>(w.rowpart2 + ix, n, l, L, m, nullptr, valid && row), L);
+            cb.e = group_fold<0>(lane_fold<0>(w.rowpart3 + ix, n, l, L, m, nullptr, valid && row), L);
         }
     }
     return cb;
@@ -1605,9 +1605,10 @@ k_sweep(const Work* __restrict__ wp, int parity)
 // Reads state slot `parity` (the one this step's sweep used): stores the pending vector
 // update, combines the tile partials of every entry of the 2n-vectors and writes per-workgroup
 // dot products. The decide kernel that follows reduces them and writes the other slot.
+constexpr int kFacMax = (MDOT_MAX_N + kBR - 1) / kBR;  // row tiles at the largest n
 struct FinShared {
     double red[kNDot * 4];
-    double fac[256];  // exp(S_I - M) of the column partials (fast path, nrt <= 256)
+    double fac[kFacMax];  // exp(S_I - M) of the column partials of row tile I
 };
 
 // Raw inputs of entry k for entry_after and the finalizer, loaded without data-dependent
@@ -1768,12 +1769,16 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     double v[kNDot];
 #pragma unroll
     for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
-    // M = max_I S_I (every wave forms the same maximum) for the general path
+    // M = max_I S_I (every wave forms the same maximum) for the general path, and the factors
+    // exp(S_I - M) of the column partials, formed once per workgroup (instead of once per entry
+    // and partial: 2 x 10^8 FP64 exps per sweep at n = 10^5)
     double M = 0.0;
     if (!fast && active && (mode == SM_LSE || mode == SM_R1)) {
         double mx = -INFINITY;
         for (int I = tid & 63; I < wl.nrt; I += 64) mx = fmax(mx, wl.tshift[I]);
         M = wave_max(mx);
+        for (int I = tid; I < wl.nrt; I += kVecWG) sh.fac[I] = exp(wl.tshift[I] - M);
+        __syncthreads();
     }
     const int nvb = wl.fin_nvb;
     for (int vb = blk; vb < nvb; vb += nblk) {
@@ -1787,7 +1792,7 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         const int kc = valid ? k : 0;
         const EntryIn in = entry_load(wl, a, kc);
         Comb cb{};
-        if (active) cb = combine(wl, mode, k, valid, l, L, M);
+        if (active) cb = combine(wl, mode, k, valid, l, L, sh.fac);
         if (!valid || l != 0) continue;
         const Entry e = entry_from(in, a, n, k);
         const double g_cur = store_update(wl, a, e, in.g, k);

@@ -25,7 +25,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tuning.json")
 STAGE_DEFAULT = 2048  # the library's built-in staging threshold (tiles)
-MAX_N = 65536
+MAX_N = 131072  # MDOT_MAX_N of include/mdot.h
 
 
 def _problem(code: str, n: int, dev):

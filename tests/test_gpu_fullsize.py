@@ -8,7 +8,7 @@
   ragged last tiles) covers the other load path at scale.
 * Past n = 8192 (the finalize's other instance): point-cost sweeps at n = 12000 on sampled rows
   and columns, and an n = 9000 point-cost solve re-certified by the oracle.
-* The largest size (MDOT_MAX_N = 65536): point-cost sweeps in both precisions and a 16 GiB
+* The largest size (MDOT_MAX_N = 131072): point-cost sweeps in both precisions and a 64 GiB
   stored FP32 cost, on sampled rows and columns; one more is rejected.
 * Degenerate cases with closed forms: n = 1, identical marginals on a cost with zero
   diagonal (OT = 0), and a separable cost C_ij = a_i + b_j (every plan costs <a, r> + <b, c>).
@@ -197,13 +197,13 @@ def test_lse2_large_n_points_sampled(ctx, prec):
     np.testing.assert_allclose(lc.cpu().numpy()[cols], lc_o, rtol=0, atol=tol)
 
 
-MAX_N = 65536  # MDOT_MAX_N of include/mdot.h
+MAX_N = 131072  # MDOT_MAX_N of include/mdot.h
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_lse2_max_n_points_sampled(ctx, prec):
-    # the largest size the library takes: 1024 x 256 tiles, partial arrays past 2^31 bytes in
-    # total, and the finalize's general path (more row tiles than its fast path holds)
+    # the largest size the library takes: 2048 x 512 tiles, partial arrays of 9 GB in total, and
+    # the finalize's general path (more row tiles than its fast path holds)
     from scipy.special import logsumexp
 
     n, gamma, scale = MAX_N, 200.0, 0.5
@@ -228,7 +228,7 @@ def test_lse2_max_n_points_sampled(ctx, prec):
 
 
 def test_lse2_max_n_dense_sampled(ctx):
-    # a stored FP32 cost at the largest size (16 GiB): row offsets past 2^32 bytes, each tile's
+    # a stored FP32 cost at the largest size (64 GiB): row offsets past 2^32 bytes, each tile's
     # buffer range clamped below 2 GiB. Seeded uniform costs; the sampled rows and columns are
     # copied back as inputs and the log-sums formed from them by their definition.
     from scipy.special import logsumexp
@@ -254,6 +254,39 @@ def test_lse2_max_n_dense_sampled(ctx):
     lc_o = logsumexp(u[None, :] + v[cols, None] - gamma * Cc, axis=1)
     np.testing.assert_allclose(lr.cpu().numpy()[rows], lr_o, rtol=0, atol=2e-6)
     np.testing.assert_allclose(lc.cpu().numpy()[cols], lc_o, rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_lse2_n100k_points_d3_sampled(ctx, prec):
+    # the paper's largest size for costs computed on the fly (about 10^5 points): n = 100,000,
+    # ragged last tiles (1563 x 391), 3-D clouds from a Gaussian mixture, scale 1 / (max |x| +
+    # max |y|)^2, which keeps C in [0, 1] (the library's range pass checks it)
+    from scipy.special import logsumexp
+
+    from paper_2307_08507_amd import workloads as Wl
+
+    n, gamma = 100_000, 300.0
+    print(f"n=100000 lse2 points d=3 prec={prec}", flush=True)
+    rng = np.random.default_rng(91)
+    X = Wl.gmm_points(n, 3, 92).astype(np.float32)
+    Y = Wl.gmm_points(n, 3, 93).astype(np.float32)
+    u = rng.standard_normal(n) * 0.1 - np.log(n)
+    v = rng.standard_normal(n) * 0.1
+    XY = dev(np.concatenate([X, Y]).ravel(), torch.float32)
+    lr = torch.empty(n, dtype=torch.float64, device="cuda")
+    lc = torch.empty_like(lr)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    scale = 1.0 / (np.sqrt((X64 ** 2).sum(1).max()) + np.sqrt((Y64 ** 2).sum(1).max())) ** 2
+    assert ctx.lse2(M.point_cost(XY, n, 3, "sqeuclid", scale=scale), dev(u), dev(v), gamma, lr, lc,
+                    precision=prec) == 0
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([rng.choice(n, 20, replace=False), [0, n - 1]]))
+    cols = np.unique(np.concatenate([rng.choice(n, 20, replace=False), [0, n - 1]]))
+    lr_o = logsumexp(u[rows, None] + v[None, :] - gamma * _points_rows(X, Y, rows, scale, 0), axis=1)
+    lc_o = logsumexp(u[None, :] + v[cols, None] - gamma * _points_rows(X, Y, cols, scale, 1), axis=1)
+    tol = 1e-12 * gamma if prec == "f64" else 2e-6
+    np.testing.assert_allclose(lr.cpu().numpy()[rows], lr_o, rtol=0, atol=tol)
+    np.testing.assert_allclose(lc.cpu().numpy()[cols], lc_o, rtol=0, atol=tol)
 
 
 def test_size_past_max_rejected(ctx):
