@@ -55,7 +55,7 @@ enum {
     MDOT_E_BUSY = -6      /* no free serving slot */
 };
 
-/* How C is given. DENSE: data is an n*n row-major array of dtype. POINTS_*: data holds
+/* How C is given. DENSE: data is an n*n row-major array of dtype. POINTS_* (d = 1..8): data holds
  * X (n*d FP32, row-major) followed by Y (n*d FP32); C_ij = scale * dist(x_i, y_j), computed
  * on the fly in FP64 inside the sweep (paper Sec. 3: O(n) memory when entries of C can be
  * computed in O(1)). */
@@ -80,7 +80,7 @@ typedef enum { MDOT_PREC_F64 = 0, MDOT_PREC_F32 = 1, MDOT_PREC_MIXED = 2 } mdot_
 
 typedef struct {
     int32_t n;            /* problem size, 1..MDOT_MAX_N */
-    int32_t d;            /* point dimension for POINTS_* (1..3), ignored for DENSE */
+    int32_t d;            /* point dimension for POINTS_* (1..8), ignored for DENSE */
     mdot_cost_kind kind;
     mdot_dtype dtype;     /* DENSE only: element type of data (POINTS_* use FP32 coordinates) */
     const void* data;     /* device */

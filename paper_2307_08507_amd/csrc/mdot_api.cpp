@@ -249,7 +249,7 @@ static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n, hipStream_t s
 
 // Names of the base cost codes in the tuning file (the order of CostCode in the kernels).
 static const char* const kCodeNames[kCostCodes] = {"f64", "f32", "f16", "bf16", "pts_sq", "pts_l1", "pts_sq2",
-                                                   "pts_l12"};
+                                                   "pts_l12", "pts_sq8", "pts_l18"};
 
 // Read the tuning table: $MDOT_TUNING, else tuning.json in the package directory (the parent of
 // the directory holding libmdot.so). The file is JSON written one entry per line by the tuner:
@@ -305,7 +305,9 @@ static void load_tuning(mdot_ctx* ctx)
 // with n <= n_max (defaults if none), then the context's overrides.
 static void pick_variant(const mdot_ctx* ctx, int code, int n, int* occ2, int* stage_min_tiles)
 {
-    int occ = 4, st = kStageMinTilesDefault;
+    // the 8-coordinate point instances hold 4 x 8 FP64 column coordinates per lane: they take the
+    // 256-VGPR variant unless the table says otherwise
+    int occ = (code == kCostCodes - 2 || code == kCostCodes - 1) ? 2 : 4, st = kStageMinTilesDefault;
     for (const TuneEntry& e : ctx->tuning)
         if (e.code == code && n <= e.n_max) {
             occ = e.occ;
@@ -342,7 +344,7 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc
     w.d = cost ? cost->d : 0;
     {
         const int cc = cost_code_of(w.cost_kind, w.dtype);
-        pick_variant(ctx, w.d <= 2 ? cost_code_planar(cc) : cc, n, &w.occ2, &w.stage_min_tiles);
+        pick_variant(ctx, cost_code_dim(cc, w.d), n, &w.occ2, &w.stage_min_tiles);
     }
     w.cost = cost ? cost->data : nullptr;
     w.scale = scale;
@@ -395,8 +397,8 @@ static int check_cost_desc(mdot_ctx* ctx, const mdot_cost_desc* cost)
         return fail(ctx, MDOT_E_ARG, "unknown cost kind %d", (int)cost->kind);
     if (cost->kind == MDOT_COST_DENSE && (cost->dtype < MDOT_DT_F64 || cost->dtype > MDOT_DT_BF16))
         return fail(ctx, MDOT_E_ARG, "unknown dtype %d", (int)cost->dtype);
-    if (cost->kind != MDOT_COST_DENSE && (cost->d < 1 || cost->d > 3))
-        return fail(ctx, MDOT_E_ARG, "point dimension d=%d outside [1, 3]", cost->d);
+    if (cost->kind != MDOT_COST_DENSE && (cost->d < 1 || cost->d > 8))
+        return fail(ctx, MDOT_E_ARG, "point dimension d=%d outside [1, 8]", cost->d);
     if (!(cost->scale >= 0.0) || !std::isfinite(cost->scale) || (cost->kind == MDOT_COST_DENSE && cost->scale == 0.0))
         return fail(ctx, MDOT_E_ARG, "bad cost scale %g", cost->scale);
     return MDOT_OK;
@@ -881,7 +883,7 @@ int mdot_tune_variant(mdot_ctx* ctx, const mdot_cost_desc* cost, int* occ, int* 
     if (rc) return rc;
     const int cc = cost_code_of(cost->kind, cost->dtype);
     int o2 = 0;
-    pick_variant(ctx, cost->kind != MDOT_COST_DENSE && cost->d <= 2 ? cost_code_planar(cc) : cc, cost->n, &o2,
+    pick_variant(ctx, cost->kind != MDOT_COST_DENSE ? cost_code_dim(cc, cost->d) : cc, cost->n, &o2,
                  stage_min_tiles);
     *occ = o2 ? 2 : 4;
     return MDOT_OK;

@@ -175,9 +175,9 @@ struct Control {
 // one cost tile land on the same XCD (workgroups go round-robin over the 8 XCDs) at nearly the
 // same time, so the cost is read from HBM once per group and from that XCD's L2 by the rest.
 constexpr int kMaxBatch = 64;
-constexpr int kCostCodes = 8;            // cost types (dense dtypes, point metrics, planar point metrics)
-constexpr int kOccHi = 8;                // code bit: the same cost type at 2 waves per SIMD
-constexpr int kMaxCodes = 2 * kCostCodes;  // sweep kernel instances
+constexpr int kCostCodes = 10;           // cost types (dense dtypes; point metrics for d <= 3, d <= 2, d <= 8)
+constexpr int kOccHi = 16;               // code bit: the same cost type at 2 waves per SIMD
+constexpr int kMaxCodes = kOccHi + kCostCodes;  // sweep kernel instance codes (some unused)
 constexpr int kStageMinTilesDefault = 2048;
 struct BatchDesc {
     int32_t nitems, total_tiles, total_fin, ngroups;
@@ -252,8 +252,9 @@ int launch_to_f16(const void* src, int src_dtype, void* dst, size_t count, doubl
 // host copy hb (instance hb.code[c] over its tile range), then fin_grid = total_fin finalize
 // workgroups and the decisions.
 int cost_code_of(int cost_kind, int dtype);
-// The planar (d <= 2) instance of a point cost code; other codes are returned unchanged.
-int cost_code_planar(int cost_code);
+// The instance of a point cost code for dimension d (planar for d <= 2, the general one for
+// d = 3, the 8-coordinate one for 4 <= d <= 8); other codes are returned unchanged.
+int cost_code_dim(int cost_code, int d);
 // The sweep kernel instance a launch of hw takes (its cost code, planar for d <= 2, plus kOccHi
 // for the 2-waves-per-SIMD variant).
 int cost_code(const Work& hw);

@@ -223,7 +223,7 @@ struct DenseCost {
     __device__ __forceinline__ void row(int r, int j0, double c[4]) const { decode(load(r, j0), c); }
     // LSE exponent arguments (log2 units) of one row for this lane's 4 columns:
     // x_k = -g2 C_ik + V_k + A, with g2 = gamma * scale * log2(e).
-    __device__ __forceinline__ void bind_rows(void*) {}
+    __device__ __forceinline__ void bind_rows(void*, void*) {}
     __device__ __forceinline__ void row_setup(int, int, double, double&) {}
     __device__ __forceinline__ void prepare(double, const double*) {}
     __device__ __forceinline__ void args(const Raw& raw, double g2, const double V[4], double A, double x[4]) const
@@ -236,19 +236,23 @@ struct DenseCost {
 };
 
 // Point clouds: raw C_ij = sum_k (x_ik - y_jk)^2 (KIND 1) or sum_k |x_ik - y_jk| (KIND 2),
-// evaluated in FP64 from FP32 coordinates (d <= 3). In the LSE tile the rows' coordinates are
+// evaluated in FP64 from FP32 coordinates (d <= 8). In the LSE tile the rows' coordinates are
 // the same for every lane: row_setup() puts them in LDS once and "Raw" is just the tile row.
-// D is the number of coordinates the arithmetic carries: D = 3 serves every d <= 3; D = 2
-// (planar clouds, d <= 2) leaves out the third coordinate's operations. Coordinates past d are
-// zero in both, so every term D = 2 leaves out is an exact zero and the results are identical.
+// D is the number of coordinates the arithmetic carries: D = 3 serves every d <= 3, D = 2
+// (planar clouds, d <= 2) leaves out the third coordinate's operations, D = 8 serves 4 <= d <= 8.
+// Coordinates past d are zero, so every term a smaller D leaves out is an exact zero and the
+// instances give identical results on a cloud padded with zero coordinates.
 template <int KIND, int D = 3>
 struct PointCost {
+    static_assert(D == 2 || D == 3 || D == 8, "point instances carry 2, 3 or 8 coordinates");
+    static constexpr int kRowF = D <= 4 ? 4 : 8;  // floats per row in LDS (one or two float4)
     using Raw = int;
     const float* X;
     const float* Y;
     int n, d, i0;
     double y[4][D];
-    const float4* sX;
+    const float4* sX;   // row coordinates 0..3 of the tile's rows (LDS)
+    const float4* sX2;  // coordinates 4..7 (D = 8)
     __device__ __forceinline__ PointCost(const Work& w, int i0_)
         : X((const float*)w.cost), Y((const float*)w.cost + (size_t)w.n * w.d), n(w.n), d(w.d), i0(i0_) {}
     __device__ __forceinline__ void cols(int j0)
@@ -258,25 +262,25 @@ struct PointCost {
 #pragma unroll
             for (int e = 0; e < D; ++e) y[k][e] = (j0 + k < n && e < d) ? (double)Y[(size_t)(j0 + k) * d + e] : 0.0;
     }
-    __device__ __forceinline__ float4 xrow(int r) const
+    struct RowX {
+        float v[kRowF];
+    };
+    __device__ __forceinline__ RowX xrow(int r) const
     {
         const int i = i0 + r;
-        float4 v;
-        v.x = (i < n) ? X[(size_t)i * d] : 0.f;
-        v.y = (i < n && d > 1) ? X[(size_t)i * d + 1] : 0.f;
-        v.z = (D > 2 && i < n && d > 2) ? X[(size_t)i * d + 2] : 0.f;
-        v.w = 0.f;
-        return v;
+        RowX x;
+#pragma unroll
+        for (int e = 0; e < kRowF; ++e) x.v[e] = (e < D && i < n && e < d) ? X[(size_t)i * d + e] : 0.f;
+        return x;
     }
-    __device__ __forceinline__ void decode(const float4& x, double c[4]) const
+    __device__ __forceinline__ void decode(const RowX& x, double c[4]) const
     {
-        const double xs[3] = {x.x, x.y, x.z};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             double s = 0.0;
 #pragma unroll
             for (int e = 0; e < D; ++e) {
-                double t = xs[e] - y[k][e];
+                double t = (double)x.v[e] - y[k][e];
                 s = (KIND == 1) ? fma(t, t, s) : s + fabs(t);
             }
             c[k] = s;
@@ -284,21 +288,35 @@ struct PointCost {
     }
     __device__ __forceinline__ void row(int r, int, double c[4]) const { decode(xrow(r), c); }
     __device__ __forceinline__ Raw load(int r, int) const { return r; }
-    // LSE tile set-up: sX = kBR float4 rows of LDS; thread r < kBR stores row r's coordinates
-    // and, for squared distances, folds -g2 |x_r|^2 into the row term a.
-    __device__ __forceinline__ void bind_rows(void* lds) { sX = (const float4*)lds; }
+    // LSE tile set-up: sX (and sX2 for D = 8) = kBR float4 rows of LDS; thread r < kBR stores row
+    // r's coordinates and, for squared distances, folds -g2 |x_r|^2 into the row term a.
+    __device__ __forceinline__ void bind_rows(void* lds, void* lds_hi)
+    {
+        sX = (const float4*)lds;
+        sX2 = (const float4*)lds_hi;
+    }
     __device__ __forceinline__ void row_setup(int r, int i, double g2, double& a)
     {
-        const float4 v = xrow(r);
-        ((float4*)sX)[r] = v;
+        const RowX v = xrow(r);
+        ((float4*)sX)[r] = make_float4(v.v[0], v.v[1], v.v[2], v.v[3]);
+        if constexpr (kRowF == 8) ((float4*)sX2)[r] = make_float4(v.v[4], v.v[5], v.v[6], v.v[7]);
         if (KIND == 1 && i < n) {
-            const double x0 = v.x, x1 = v.y, x2 = v.z;
-            a = fma(-g2, fma(x0, x0, fma(x1, x1, D > 2 ? x2 * x2 : 0.0)), a);
+            double ss;
+            if constexpr (D > 2) {
+                ss = (double)v.v[D - 1] * (double)v.v[D - 1];
+#pragma unroll
+                for (int e = D - 2; e >= 0; --e) ss = fma((double)v.v[e], (double)v.v[e], ss);
+            } else {
+                ss = 0.0;
+#pragma unroll
+                for (int e = D - 1; e >= 0; --e) ss = fma((double)v.v[e], (double)v.v[e], ss);
+            }
+            a = fma(-g2, ss, a);
         }
     }
     // LSE exponent arguments, as DenseCost::args. For squared distances the expansion
     // |x - y|^2 = |x|^2 + |y|^2 - 2 <x, y> moves |y_k|^2 into W_k = V_k - g2 |y_k|^2 and |x|^2 into
-    // the row term, leaving 3 FMAs per element (prepare() turns y into 2 g2 y). The large
+    // the row term, leaving D FMAs per element (prepare() turns y into 2 g2 y). The large
     // terms cancel in FP64 to an absolute error ~1e-16 g2 |x|^2, far below the FP32 exp error.
     double W[4];
     __device__ __forceinline__ void prepare(double g2, const double V[4])
@@ -306,23 +324,36 @@ struct PointCost {
         if constexpr (KIND == 1) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const double y2 = D > 2 ? y[k][D - 1] * y[k][D - 1] : 0.0;
-                const double yy = fma(y[k][0], y[k][0], fma(y[k][1], y[k][1], y2));
+                double yy = D > 2 ? y[k][D - 1] * y[k][D - 1] : 0.0;
+#pragma unroll
+                for (int e = (D > 2 ? D - 2 : D - 1); e >= 0; --e) yy = fma(y[k][e], y[k][e], yy);
                 W[k] = fma(-g2, yy, V[k]);
 #pragma unroll
                 for (int e = 0; e < D; ++e) y[k][e] *= 2.0 * g2;
             }
         }
     }
+    __device__ __forceinline__ RowX lds_row(int r) const
+    {
+        RowX x;
+        const float4 a = sX[r];  // one address for the whole wave: an LDS broadcast
+        x.v[0] = a.x; x.v[1] = a.y; x.v[2] = a.z; x.v[3] = a.w;
+        if constexpr (kRowF == 8) {
+            const float4 b = sX2[r];
+            x.v[4] = b.x; x.v[5] = b.y; x.v[6] = b.z; x.v[7] = b.w;
+        }
+        return x;
+    }
     __device__ __forceinline__ void args(const Raw& r, double g2, const double V[4], double A, double x[4]) const
     {
-        const float4 xr = sX[r];  // one address for the whole wave: an LDS broadcast
+        const RowX xr = lds_row(r);
         if constexpr (KIND == 1) {
-            const double x0 = xr.x, x1 = xr.y, x2 = xr.z;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const double b = W[k] + A;
-                x[k] = fma(x0, y[k][0], fma(x1, y[k][1], D > 2 ? fma(x2, y[k][D - 1], b) : b));
+                double acc = W[k] + A;
+#pragma unroll
+                for (int e = D - 1; e >= 0; --e) acc = fma((double)xr.v[e], y[k][e], acc);
+                x[k] = acc;
             }
         } else {
             double c[4];
@@ -559,6 +590,7 @@ constexpr int kWaveRegion = 1024;                        // 8 KiB: 8 rows x 64 l
 constexpr int kRowBufD = (kRPW * kRowPad + 1) / 2;      // transpose buffer, in doubles
 static_assert(kRowBufD + kBC <= kWaveRegion, "wave region too small");
 constexpr int kSmem = 5 * kBR + kBC + 4 * kWaveRegion;
+constexpr int kSmemAll = kSmem + 2 * kBR;  // plus the upper coordinates of 8-D point rows
 static_assert(kSmem >= 5 * kBR + 4 * kBC, "LDS for the Round tiles");
 
 // Sum the per-lane FP32 row partials rp[r] of the wave's kRPW rows across the 64 lanes:
@@ -697,7 +729,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     }
     // per-row values: shift s_i (predicted log row sum) and A_i = (u_i - lz_i) log2 e;
     // per-column V_j = (v_j + alpha p_j) log2 e, one column per thread, through LDS
-    cost.bind_rows(sm + 3 * kBR);  // 2 kBR doubles, free in this tile
+    cost.bind_rows(sm + 3 * kBR, sm + kSmem);  // 2 kBR doubles, free in this tile, and 2 kBR past the rest
     if (t.tid < kBR) {
         const int i = t.i0 + t.tid;
         double sh = -INFINITY, aa = -INFINITY;
@@ -1527,8 +1559,11 @@ __device__ __forceinline__ void decide(State& S, const DevParams& P, const doubl
 // planar clouds take them, and so does the engine when every problem in flight is planar. Their
 // results are identical to the general instances'.
 enum CostCode { CC_F64 = 0, CC_F32 = 1, CC_F16 = 2, CC_BF16 = 3, CC_PTS_SQ = 4, CC_PTS_L1 = 5, CC_PTS_SQ2 = 6,
-                CC_PTS_L12 = 7 };
+                CC_PTS_L12 = 7, CC_PTS_SQ8 = 8, CC_PTS_L18 = 9 };
+static_assert(CC_PTS_L18 + 1 == kCostCodes, "one kernel instance per cost code");
 template <int CC> struct CostOf;
+// The cost type of a kernel instance code (kOccHi marks the 2-waves-per-SIMD variant).
+constexpr int base_code(int cc) { return cc >= kOccHi ? cc - kOccHi : cc; }
 template <> struct CostOf<CC_F64> { using T = DenseCost<MDOT_DT_F64>; };
 template <> struct CostOf<CC_F32> { using T = DenseCost<MDOT_DT_F32>; };
 template <> struct CostOf<CC_F16> { using T = DenseCost<MDOT_DT_F16>; };
@@ -1537,11 +1572,13 @@ template <> struct CostOf<CC_PTS_SQ> { using T = PointCost<1>; };
 template <> struct CostOf<CC_PTS_L1> { using T = PointCost<2>; };
 template <> struct CostOf<CC_PTS_SQ2> { using T = PointCost<1, 2>; };
 template <> struct CostOf<CC_PTS_L12> { using T = PointCost<2, 2>; };
+template <> struct CostOf<CC_PTS_SQ8> { using T = PointCost<1, 8>; };
+template <> struct CostOf<CC_PTS_L18> { using T = PointCost<2, 8>; };
 
 template <int CC, bool E64, bool ROUND>
 __device__ __forceinline__ void sweep_tiles(const Work& w, const SweepArgs& a, const TileCtx& t, int mode, double* smem)
 {
-    using Cost = typename CostOf<CC % kCostCodes>::T;
+    using Cost = typename CostOf<base_code(CC)>::T;
     if constexpr (!ROUND) {
         if (mode == SM_MAX) tile_max<Cost>(w, a, t, smem);
         else tile_lse<Cost, E64>(w, a, t, smem);
@@ -1597,7 +1634,7 @@ template <int CC>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CC >= kOccHi ? 2 : 4)))
 k_sweep(const Work* __restrict__ wp, int parity)
 {
-    __shared__ double smem[kSmem];
+    __shared__ double smem[kSmemAll];
     sweep_any<CC>(*wp, parity, blockIdx.x, smem);
 }
 
@@ -1894,7 +1931,7 @@ template <int CC>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(CC >= kOccHi ? 2 : 4)))
 k_sweep_batch(const BatchDesc* __restrict__ bd, int parity, int tile_begin, int tile_end)
 {
-    __shared__ double smem[kSmem];
+    __shared__ double smem[kSmemAll];
     const int g = tile_begin + (int)blockIdx.x;
     if (g >= tile_end) return;
     const int q = batch_item(bd->grp_prefix, bd->ngroups, g);
@@ -2035,7 +2072,7 @@ __global__ void __launch_bounds__(kWG) k_cost_range(const Work* __restrict__ wp,
 {
     const Work w = *wp;
     double lo, hi;
-    cost_range_body<typename CostOf<CC % kCostCodes>::T>(w, &lo, &hi);
+    cost_range_body<typename CostOf<base_code(CC)>::T>(w, &lo, &hi);
     __shared__ double s0[kWG], s1[kWG];
     const int t = threadIdx.x;
     s0[t] = lo;
@@ -2101,20 +2138,33 @@ int cost_code_of(int cost_kind, int dtype)
     }
 }
 
-int cost_code_planar(int cc)
+int cost_code_dim(int cc, int d)
 {
-    if (cc == CC_PTS_SQ) return CC_PTS_SQ2;
-    if (cc == CC_PTS_L1) return CC_PTS_L12;
+    if (cc == CC_PTS_SQ) return d <= 2 ? CC_PTS_SQ2 : (d <= 3 ? CC_PTS_SQ : CC_PTS_SQ8);
+    if (cc == CC_PTS_L1) return d <= 2 ? CC_PTS_L12 : (d <= 3 ? CC_PTS_L1 : CC_PTS_L18);
     return cc;
 }
 
-// Kernel instance of a launch: planar point clouds take the planar instance, and the tuning
-// table's 2-waves-per-SIMD variant adds kOccHi.
+// Kernel instance of a launch: point clouds take the instance for their dimension, and the
+// tuning table's 2-waves-per-SIMD variant adds kOccHi.
 int cost_code(const Work& w)
 {
-    const int cc = cost_code_of(w.cost_kind, w.dtype);
-    return (w.d <= 2 ? cost_code_planar(cc) : cc) + (w.occ2 ? kOccHi : 0);
+    return cost_code_dim(cost_code_of(w.cost_kind, w.dtype), w.d) + (w.occ2 ? kOccHi : 0);
 }
+
+#define MDOT_CC_SWITCH_BASE(cc, F)                                     \
+    switch (cc) {                                                      \
+        case CC_F64: F(CC_F64); break;                                 \
+        case CC_F32: F(CC_F32); break;                                 \
+        case CC_F16: F(CC_F16); break;                                 \
+        case CC_BF16: F(CC_BF16); break;                               \
+        case CC_PTS_SQ: F(CC_PTS_SQ); break;                           \
+        case CC_PTS_SQ2: F(CC_PTS_SQ2); break;                         \
+        case CC_PTS_L12: F(CC_PTS_L12); break;                         \
+        case CC_PTS_L1: F(CC_PTS_L1); break;                           \
+        case CC_PTS_SQ8: F(CC_PTS_SQ8); break;                         \
+        default: F(CC_PTS_L18); break;                                 \
+    }
 
 #define MDOT_CC_SWITCH(cc, F)                                          \
     switch (cc) {                                                      \
@@ -2126,6 +2176,8 @@ int cost_code(const Work& w)
         case CC_PTS_SQ2: F(CC_PTS_SQ2); break;                         \
         case CC_PTS_L12: F(CC_PTS_L12); break;                         \
         case CC_PTS_L1: F(CC_PTS_L1); break;                           \
+        case CC_PTS_SQ8: F(CC_PTS_SQ8); break;                         \
+        case CC_PTS_L18: F(CC_PTS_L18); break;                         \
         case kOccHi + CC_F64: F(CC_F64); break;                        \
         case kOccHi + CC_F32: F(CC_F32); break;                        \
         case kOccHi + CC_F16: F(CC_F16); break;                        \
@@ -2133,7 +2185,9 @@ int cost_code(const Work& w)
         case kOccHi + CC_PTS_SQ: F(kOccHi + CC_PTS_SQ); break;         \
         case kOccHi + CC_PTS_SQ2: F(kOccHi + CC_PTS_SQ2); break;       \
         case kOccHi + CC_PTS_L12: F(kOccHi + CC_PTS_L12); break;       \
-        default: F(kOccHi + CC_PTS_L1); break;                         \
+        case kOccHi + CC_PTS_SQ8: F(kOccHi + CC_PTS_SQ8); break;       \
+        case kOccHi + CC_PTS_L1: F(kOccHi + CC_PTS_L1); break;         \
+        default: F(kOccHi + CC_PTS_L18); break;                        \
     }
 
 int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
@@ -2202,7 +2256,7 @@ int launch_cost_range(const Work& hw, const Work* wd, double* part, void* stream
 {
     const int tiles = hw.nrt * hw.nct;
 #define L_(CC) hipLaunchKernelGGL(k_cost_range<CC>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, wd, part)
-    MDOT_CC_SWITCH(cost_code(hw) % kCostCodes, L_)
+    MDOT_CC_SWITCH_BASE(base_code(cost_code(hw)), L_)
 #undef L_
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

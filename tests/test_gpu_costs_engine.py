@@ -81,7 +81,8 @@ def _points(n, d, seed, kind):
 
 
 @pytest.mark.parametrize("n,d,kind", [(300, 3, "sqeuclid"), (600, 2, "sqeuclid"), (512, 2, "l1"),
-                                      (257, 1, "sqeuclid")])
+                                      (257, 1, "sqeuclid"), (350, 5, "sqeuclid"), (333, 8, "l1"),
+                                      (400, 4, "sqeuclid"), (290, 7, "l1")])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_lse2_point_costs(ctx, n, d, kind, prec):
     print(f"lse2 points n={n} d={d} {kind} prec={prec}", flush=True)
@@ -125,6 +126,35 @@ def test_planar_points_match_padded_3d(kind, prec):
 
 
 @pytest.mark.parametrize("kind", ["sqeuclid", "l1"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_3d_points_match_padded_8d(kind, prec):
+    # Clouds with 4 <= d <= 8 take the 8-coordinate instance. A d = 3 cloud padded with five zero
+    # coordinates takes it too, and every extra term is an exact zero: sweeps and Round/certificate
+    # must agree bit for bit with the d = 3 instance (fresh contexts: no shared step graph).
+    n = 520
+    print(f"3-D vs padded 8-D points n={n} {kind} prec={prec}", flush=True)
+    XY3, C64, scale = _points(n, 3, 57, kind)
+    XY8 = torch.cat([XY3.view(2 * n, 3), torch.zeros(2 * n, 5, device="cuda")], 1).contiguous().view(-1)
+    gamma = 300.0
+    u, v = _potentials(n, 6, C64, gamma)
+    r = W.dirichlet_marginal(n, 8)
+    cc = W.dirichlet_marginal(n, 9)
+    out = []
+    for XY, d in ((XY3, 3), (XY8, 8)):
+        c = M.Context(0)
+        try:
+            desc = M.point_cost(XY, n, d, kind, scale=scale)
+            lr, lc = _lse2(c, desc, u, v, gamma, prec)
+            out.append((lr, lc, c.round_certify(desc, dev(u), dev(v), gamma, dev(r), dev(cc))))
+        finally:
+            c.close()
+    (lr3, lc3, rc3), (lr8, lc8, rc8) = out
+    np.testing.assert_array_equal(lr3, lr8)
+    np.testing.assert_array_equal(lc3, lc8)
+    assert rc3 == rc8
+
+
+@pytest.mark.parametrize("kind", ["sqeuclid", "l1"])
 def test_point_dimension_change_on_one_context(kind):
     # Regression: a context caches its captured step graph, whose sweep kernel instance depends
     # on the point dimension (planar for d <= 2). Interleaving planar and d = 3 clouds of the
@@ -135,10 +165,10 @@ def test_point_dimension_change_on_one_context(kind):
     c = M.Context(0)
     try:
         for rep in range(2):
-            for d in (2, 3, 2, 3):
+            for d in (2, 3, 6, 2, 3, 6):
                 XY, C64, scale = _points(n, d, 90 + 7 * d + rep, kind)
-                if d == 3:
-                    assert float(XY.view(2 * n, 3)[:, 2].abs().max()) > 0.1
+                if d >= 3:
+                    assert float(XY.view(2 * n, d)[:, d - 1].abs().max()) > 0.1
                 gamma = 250.0
                 u, v = _potentials(n, 5 + d, C64, gamma)
                 lr, lc = _lse2(c, M.point_cost(XY, n, d, kind, scale=scale), u, v, gamma, "f32")
@@ -168,10 +198,11 @@ def test_point_cost_default_scale(ctx):
     np.testing.assert_allclose(lc, lc_o, rtol=0, atol=1e-9)
 
 
-def test_solve_point_cloud_brackets_exact_ot(ctx):
+@pytest.mark.parametrize("d", [3, 6])
+def test_solve_point_cloud_brackets_exact_ot(ctx, d):
     from tests.exact_ot import exact_lp
 
-    n, d = 256, 3
+    n = 256
     XY, C64, scale = _points(n, d, 21, "sqeuclid")
     r = W.dirichlet_marginal(n, 1)
     c = W.dirichlet_marginal(n, 2)
@@ -289,11 +320,11 @@ def test_engine_results_against_oracle_and_exact_lp(prec):
         assert abs(res.primal_cost - ref["primal_cost"]) <= 1e-5
 
 
-@pytest.mark.parametrize("mix", ["planar", "mixed"])
+@pytest.mark.parametrize("mix", ["planar", "mixed", "high_d"])
 def test_engine_point_clouds_bitwise_equals_solve(ctx, mix):
     # Planar clouds run the planar point instance, d = 3 clouds the general one: a mixed batch
     # launches both sweeps in every step. Each result must equal its solve alone bit for bit.
-    dims = [2, 2, 2] if mix == "planar" else [2, 3, 2]
+    dims = {"planar": [2, 2, 2], "mixed": [2, 3, 2], "high_d": [2, 7, 3]}[mix]
     print(f"engine point clouds {mix} d={dims}", flush=True)
     probs = []
     for j, (n, d) in enumerate(zip([300, 520, 260], dims)):
