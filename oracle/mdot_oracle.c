@@ -32,7 +32,9 @@
  *     removes the O(1/gamma) entropic offset of u/gamma (u ~ gamma f* + a).
  *
  * Conventions: gamma is the inverse temperature (the paper's convention), u, v are
- * in nats, C is dense row-major n x n with entries in [0,1]. All arithmetic is FP64
+ * in nats, C is dense row-major m x n (m rows = sources with marginal r, n columns =
+ * targets with marginal c; the paper's problems are square, m = n) with entries in [0,1].
+ * The potentials are one vector z of length m + n: u = z[0..m), v = z[m..m+n). All arithmetic is FP64
  * with libm exp/log; LSEs are two-pass (max, then sum of exp(x - max)) in ascending
  * index order. Independent rows (or columns) may run on different OpenMP threads;
  * that does not change any value.
@@ -50,7 +52,8 @@
  *     Delta gamma^0 = gamma_i; later steps use the actual (clipped) Delta gamma.
  *   - Round: r(P)_i = 0 gives x_i = 1, c(F)_j = 0 gives y_j = 1, ||err_r||_1 = 0
  *     gives G = F'.
- *   - the PNCG tolerance is floored at 1e-14 (a point-mass marginal has H_min = 0).
+ *   - the PNCG tolerance is floored at 1e-14 (a point-mass marginal has H_min = 0), and an
+ *     adaptive solve with H_min = 0 runs a single stage at gamma_i (the gamma cap is 0).
  *   - sweep budget (max_sweeps, whole solve): the solve stops after the sweep that spends
  *     it, keeps the last accepted iterate, rounds and certifies it, and reports a warning.
  *   - adaptive mode reports OK exactly when the certified gap is at most the target.
@@ -59,7 +62,10 @@
  *     direction replaces s everywhere, in p and in the numerator of beta (the preconditioned
  *     Hestenes-Stiefel formula with M = D(diag(Hessian))).
  *   - log n variant: log n replaces H_min wherever eps_d is formed (tolerance and smoothing);
- *     the adaptive gamma cap keeps H_min (Remark 1).
+ *     the adaptive gamma cap keeps H_min (Remark 1). For m != n, log min(m, n), the upper
+ *     bound of H_min that log n is for square problems.
+ *   - rectangular problems (m != n): the smoothing mixes each marginal with the uniform
+ *     distribution on its own support, r~ = (1 - w) r + w/m, c~ = (1 - w) c + w/n.
  *   - fixed smoothing in adaptive mode uses the gamma cap as gamma_f.
  */
 #include <math.h>
@@ -195,101 +201,100 @@ double orc_entropy(int n, const double* r)
 /* Two-sided LogSumExp of X_ij = u_i + v_j - gamma C_ij:
  *   lr_i = log sum_j exp(X_ij) = log r(P)_i,   lc_j = log sum_i exp(X_ij) = log c(P)_j
  * (Alg. 2, the lines that form log r(P) and log c(P); LSE_r, LSE_c as defined in Sec. 2). */
-void orc_lse2(int n, const double* C, const double* u, const double* v, double gamma,
+void orc_lse2(int m, int n, const double* C, const double* u, const double* v, double gamma,
               double* lr, double* lc)
 {
 #pragma omp parallel for schedule(static)
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < m; ++i) {
         const double* Ci = C + (size_t)i * n;
-        double m = -INFINITY;
+        double mx = -INFINITY;
         for (int j = 0; j < n; ++j) {
             double x = u[i] + v[j] - gamma * Ci[j];
-            if (x > m) m = x;
+            if (x > mx) mx = x;
         }
         double s = 0.0;
-        for (int j = 0; j < n; ++j) s += exp(u[i] + v[j] - gamma * Ci[j] - m);
-        lr[i] = m + log(s);
+        for (int j = 0; j < n; ++j) s += exp(u[i] + v[j] - gamma * Ci[j] - mx);
+        lr[i] = mx + log(s);
     }
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < n; ++j) {
-        double m = -INFINITY;
-        for (int i = 0; i < n; ++i) {
+        double mx = -INFINITY;
+        for (int i = 0; i < m; ++i) {
             double x = u[i] + v[j] - gamma * C[(size_t)i * n + j];
-            if (x > m) m = x;
+            if (x > mx) mx = x;
         }
         double s = 0.0;
-        for (int i = 0; i < n; ++i) s += exp(u[i] + v[j] - gamma * C[(size_t)i * n + j] - m);
-        lc[j] = m + log(s);
+        for (int i = 0; i < m; ++i) s += exp(u[i] + v[j] - gamma * C[(size_t)i * n + j] - mx);
+        lc[j] = mx + log(s);
     }
 }
 
 /* Row LSE only: lr_i = log sum_j exp(u_i + v_j - gamma C_ij) (Alg. 4). */
-static void lse_rows(int n, const double* C, const double* u, const double* v, double gamma, double* lr)
+static void lse_rows(int m, int n, const double* C, const double* u, const double* v, double gamma, double* lr)
 {
 #pragma omp parallel for schedule(static)
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < m; ++i) {
         const double* Ci = C + (size_t)i * n;
-        double m = -INFINITY;
+        double mx = -INFINITY;
         for (int j = 0; j < n; ++j) {
             double x = u[i] + v[j] - gamma * Ci[j];
-            if (x > m) m = x;
+            if (x > mx) mx = x;
         }
         double s = 0.0;
-        for (int j = 0; j < n; ++j) s += exp(u[i] + v[j] - gamma * Ci[j] - m);
-        lr[i] = m + log(s);
+        for (int j = 0; j < n; ++j) s += exp(u[i] + v[j] - gamma * Ci[j] - mx);
+        lr[i] = mx + log(s);
     }
 }
 
 /* Column LSE only: lc_j = log sum_i exp(u_i + v_j - gamma C_ij) (Alg. 4). */
-static void lse_cols(int n, const double* C, const double* u, const double* v, double gamma, double* lc)
+static void lse_cols(int m, int n, const double* C, const double* u, const double* v, double gamma, double* lc)
 {
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < n; ++j) {
-        double m = -INFINITY;
-        for (int i = 0; i < n; ++i) {
+        double mx = -INFINITY;
+        for (int i = 0; i < m; ++i) {
             double x = u[i] + v[j] - gamma * C[(size_t)i * n + j];
-            if (x > m) m = x;
+            if (x > mx) mx = x;
         }
         double s = 0.0;
-        for (int i = 0; i < n; ++i) s += exp(u[i] + v[j] - gamma * C[(size_t)i * n + j] - m);
-        lc[j] = m + log(s);
+        for (int i = 0; i < m; ++i) s += exp(u[i] + v[j] - gamma * C[(size_t)i * n + j] - mx);
+        lc[j] = mx + log(s);
     }
 }
 
 /* Dual objective g(u,v; gamma, r, c) = sum_ij P_ij - <u,r> - <v,c> (Sec. 2.1, eq. (sinkhorn-dual)). */
-double orc_dual_objective(int n, const double* C, const double* u, const double* v, double gamma,
+double orc_dual_objective(int m, int n, const double* C, const double* u, const double* v, double gamma,
                           const double* r, const double* c)
 {
     double s = 0.0;
 #pragma omp parallel for reduction(+ : s) schedule(static)
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < m; ++i)
         for (int j = 0; j < n; ++j) s += exp(u[i] + v[j] - gamma * C[(size_t)i * n + j]);
     double ur = 0.0, vc = 0.0;
-    for (int i = 0; i < n; ++i) {
-        ur += u[i] * r[i];
-        vc += v[i] * c[i];
-    }
+    for (int i = 0; i < m; ++i) ur += u[i] * r[i];
+    for (int j = 0; j < n; ++j) vc += v[j] * c[j];
     return s - ur - vc;
 }
 
-/* Gradient of g: (r(P) - r, c(P) - c) (Sec. 4.3, eq. (hessian)); written into g[0..2n). */
-static void gradient(int n, const double* lr, const double* lc, const double* rt, const double* ct, double* g)
+/* Gradient of g: (r(P) - r, c(P) - c) (Sec. 4.3, eq. (hessian)); written into g[0..m+n). */
+static void gradient(int m, int n, const double* lr, const double* lc, const double* rt, const double* ct,
+                     double* g)
 {
-    for (int i = 0; i < n; ++i) g[i] = exp(lr[i]) - rt[i];
-    for (int j = 0; j < n; ++j) g[n + j] = exp(lc[j]) - ct[j];
+    for (int i = 0; i < m; ++i) g[i] = exp(lr[i]) - rt[i];
+    for (int j = 0; j < n; ++j) g[m + j] = exp(lc[j]) - ct[j];
 }
 
-static double dot(int m, const double* a, const double* b)
+static double dot(int len, const double* a, const double* b)
 {
     double s = 0.0;
-    for (int k = 0; k < m; ++k) s += a[k] * b[k];
+    for (int k = 0; k < len; ++k) s += a[k] * b[k];
     return s;
 }
 
-static double norm1(int m, const double* a)
+static double norm1(int len, const double* a)
 {
     double s = 0.0;
-    for (int k = 0; k < m; ++k) s += fabs(a[k]);
+    for (int k = 0; k < len; ++k) s += fabs(a[k]);
     return s;
 }
 
@@ -303,12 +308,12 @@ static int budget_left(const orc_params* prm, const counters* cn)
 }
 
 /* phi'(alpha) = <p_u, r(P_alpha) - r~> + <p_v, c(P_alpha) - c~> (App. B, eq. (phiprime)). */
-static double phi_prime(int n, const double* lr, const double* lc, const double* rt, const double* ct,
+static double phi_prime(int m, int n, const double* lr, const double* lc, const double* rt, const double* ct,
                         const double* p)
 {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += p[i] * (exp(lr[i]) - rt[i]);
-    for (int j = 0; j < n; ++j) s += p[n + j] * (exp(lc[j]) - ct[j]);
+    for (int i = 0; i < m; ++i) s += p[i] * (exp(lr[i]) - rt[i]);
+    for (int j = 0; j < n; ++j) s += p[m + j] * (exp(lc[j]) - ct[j]);
     return s;
 }
 
@@ -318,7 +323,7 @@ static double phi_prime(int n, const double* lr, const double* lc, const double*
  * next Sinkhorn direction needs no extra sweep (App. B).
  * Returns 0 on acceptance, 1 when the trial cap hit and alpha_lo > 0 was taken,
  * -1 when no step was found, -2 when the sweep budget ran out (no step). */
-static int line_search(int n, const double* C, double gamma, const double* rt, const double* ct,
+static int line_search(int m, int n, const double* C, double gamma, const double* rt, const double* ct,
                        const double* z, const double* p, double dphi0, double alpha0,
                        const orc_params* prm, double* zt, double* lr, double* lc, double* alpha_out,
                        counters* cn)
@@ -328,11 +333,11 @@ static int line_search(int n, const double* C, double gamma, const double* rt, c
     double a = alpha0;
     for (int t = 0; t < prm->max_ls_trials; ++t) {
         if (!budget_left(prm, cn)) return -2; /* sweep budget spent: no step */
-        for (int k = 0; k < 2 * n; ++k) zt[k] = z[k] + a * p[k];
-        orc_lse2(n, C, zt, zt + n, gamma, lr, lc);
+        for (int k = 0; k < m + n; ++k) zt[k] = z[k] + a * p[k];
+        orc_lse2(m, n, C, zt, zt + m, gamma, lr, lc);
         cn->sweeps++;
         cn->ls_trials++;
-        double d = phi_prime(n, lr, lc, rt, ct, p);
+        double d = phi_prime(m, n, lr, lc, rt, ct, p);
         if ((2.0 * c1 - 1.0) * dphi0 >= d && d >= c2 * dphi0) {
             ls_record(dphi0, d, a, 0.0);
             *alpha_out = a;
@@ -357,8 +362,8 @@ static int line_search(int n, const double* C, double gamma, const double* rt, c
     }
     cn->ls_failures++;
     if (alo > 0.0) {
-        for (int k = 0; k < 2 * n; ++k) zt[k] = z[k] + alo * p[k];
-        orc_lse2(n, C, zt, zt + n, gamma, lr, lc);
+        for (int k = 0; k < m + n; ++k) zt[k] = z[k] + alo * p[k];
+        orc_lse2(m, n, C, zt, zt + m, gamma, lr, lc);
         cn->sweeps++;
         ls_record(dphi0, dlo, alo, 1.0);
         *alpha_out = alo;
@@ -370,33 +375,31 @@ static int line_search(int n, const double* C, double gamma, const double* rt, c
 
 /* PNCG (Alg. 2): minimise g(., .; gamma, r~, c~) from z = (u, v) until ||grad g||_1 <= tol.
  * z is updated in place. Returns ORC_OK or ORC_W_NOT_CONVERGED. */
-static int pncg(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
+static int pncg(int m, int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
                 double* z, const orc_params* prm, counters* cn, double* gnorm_out, double* gnorm0_out)
 {
-    const int m = 2 * n;
-    double* lr = (double*)malloc(sizeof(double) * m); /* lr = log r(P), lr + n = log c(P) */
-    double* g = (double*)malloc(sizeof(double) * m);
-    double* gprev = (double*)malloc(sizeof(double) * m);
-    double* s = (double*)malloc(sizeof(double) * m);
-    double* p = (double*)malloc(sizeof(double) * m);
-    double* zt = (double*)malloc(sizeof(double) * m);
-    double* lrt = (double*)malloc(sizeof(double) * m);
-    double* logt = (double*)malloc(sizeof(double) * m);
+    const int len = m + n;
+    double* lr = (double*)malloc(sizeof(double) * len); /* lr = log r(P), lr + m = log c(P) */
+    double* g = (double*)malloc(sizeof(double) * len);
+    double* gprev = (double*)malloc(sizeof(double) * len);
+    double* s = (double*)malloc(sizeof(double) * len);
+    double* p = (double*)malloc(sizeof(double) * len);
+    double* zt = (double*)malloc(sizeof(double) * len);
+    double* lrt = (double*)malloc(sizeof(double) * len);
+    double* logt = (double*)malloc(sizeof(double) * len);
     int status = ORC_OK;
     if (!lr || !g || !gprev || !s || !p || !zt || !lrt || !logt) {
         status = ORC_E_NOMEM;
         goto out;
     }
-    for (int i = 0; i < n; ++i) {
-        logt[i] = log(rt[i]);
-        logt[n + i] = log(ct[i]);
-    }
+    for (int i = 0; i < m; ++i) logt[i] = log(rt[i]);
+    for (int j = 0; j < n; ++j) logt[m + j] = log(ct[j]);
     /* initial log r(P), log c(P) and gradient */
-    orc_lse2(n, C, z, z + n, gamma, lr, lr + n);
+    orc_lse2(m, n, C, z, z + m, gamma, lr, lr + m);
     cn->sweeps++;
-    gradient(n, lr, lr + n, rt, ct, g);
-    memset(p, 0, sizeof(double) * m);
-    double gnorm = norm1(m, g);
+    gradient(m, n, lr, lr + m, rt, ct, g);
+    memset(p, 0, sizeof(double) * len);
+    double gnorm = norm1(len, g);
     if (gnorm0_out) *gnorm0_out = gnorm;
     double beta = 0.0, alpha_prev = 1.0;
     int64_t k = 1;
@@ -406,18 +409,17 @@ static int pncg(int n, const double* C, double gamma, const double* rt, const do
             break;
         }
         /* Sinkhorn direction s = (log r~ - log r(P), log c~ - log c(P)) (eq. (sinkhorn-direction)) */
-        for (int t = 0; t < m; ++t) s[t] = logt[t] - lr[t];
+        for (int t = 0; t < len; ++t) s[t] = logt[t] - lr[t];
         if (prm->precond == 1) {
             /* diagonal-Hessian direction s~ = (r~ / r(P), c~ / c(P)) - 1 (eq. (s-tilde)), taken only
              * when every ratio lies in [0.01, 100]; otherwise s stays (Sec. 4.3) */
-            const double* tgt[2] = {rt, ct};
             int inrange = 1;
-            for (int t = 0; t < m; ++t) {
-                double ratio = tgt[t / n][t % n] / exp(lr[t]);
+            for (int t = 0; t < len; ++t) {
+                double ratio = (t < m ? rt[t] : ct[t - m]) / exp(lr[t]);
                 if (!(ratio >= 0.01 && ratio <= 100.0)) inrange = 0;
             }
             if (inrange) {
-                for (int t = 0; t < m; ++t) s[t] = tgt[t / n][t % n] / exp(lr[t]) - 1.0;
+                for (int t = 0; t < len; ++t) s[t] = (t < m ? rt[t] : ct[t - m]) / exp(lr[t]) - 1.0;
                 cn->tilde_iters++;
             }
         }
@@ -426,18 +428,18 @@ static int pncg(int n, const double* C, double gamma, const double* rt, const do
             beta = 0.0;
         } else {
             double num = 0.0, den = 0.0;
-            for (int t = 0; t < m; ++t) {
+            for (int t = 0; t < len; ++t) {
                 double y = g[t] - gprev[t];
                 num += y * (-s[t]);
                 den += y * p[t];
             }
             beta = (den != 0.0) ? num / den : 0.0;
         }
-        for (int t = 0; t < m; ++t) p[t] = s[t] + beta * p[t];
-        double dphi0 = dot(m, p, g);
+        for (int t = 0; t < len; ++t) p[t] = s[t] + beta * p[t];
+        double dphi0 = dot(len, p, g);
         if (dphi0 >= 0.0) { /* reset CG when p is not a descent direction (Alg. 2) */
-            memcpy(p, s, sizeof(double) * m);
-            dphi0 = dot(m, p, g);
+            memcpy(p, s, sizeof(double) * len);
+            dphi0 = dot(len, p, g);
             if (k > 1) cn->cg_resets++;
         }
         if (!(dphi0 < 0.0)) { /* even s is not a descent direction: numerical floor */
@@ -445,18 +447,18 @@ static int pncg(int n, const double* C, double gamma, const double* rt, const do
             break;
         }
         double alpha;
-        int ls = line_search(n, C, gamma, rt, ct, z, p, dphi0, alpha_prev, prm, zt, lrt, lrt + n,
+        int ls = line_search(m, n, C, gamma, rt, ct, z, p, dphi0, alpha_prev, prm, zt, lrt, lrt + m,
                              &alpha, cn);
         if (ls < 0) { /* no step (line search failed or budget spent): keep the last iterate */
             status = ORC_W_NOT_CONVERGED;
             break;
         }
         /* step: z <- z + alpha p; the accepted trial's LSEs become the new log r(P), log c(P) */
-        memcpy(gprev, g, sizeof(double) * m);
-        memcpy(z, zt, sizeof(double) * m);
-        memcpy(lr, lrt, sizeof(double) * m);
-        gradient(n, lr, lr + n, rt, ct, g);
-        gnorm = norm1(m, g);
+        memcpy(gprev, g, sizeof(double) * len);
+        memcpy(z, zt, sizeof(double) * len);
+        memcpy(lr, lrt, sizeof(double) * len);
+        gradient(m, n, lr, lr + m, rt, ct, g);
+        gnorm = norm1(len, g);
         alpha_prev = alpha;
         cn->pncg_iters++;
         ++k;
@@ -470,22 +472,22 @@ out:
 /* Log-domain Sinkhorn projector (Alg. 4): row scaling then column scaling until the row
  * residual ||r~ - r(P)||_1 (the whole gradient, since c(P) = c~ after each column update)
  * is at most tol. */
-static int sinkhorn(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
+static int sinkhorn(int m, int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
                     double* z, const orc_params* prm, counters* cn, double* gnorm_out, double* gnorm0_out)
 {
     double* u = z;
-    double* v = z + n;
-    double* lr = (double*)malloc(sizeof(double) * n);
+    double* v = z + m;
+    double* lr = (double*)malloc(sizeof(double) * m);
     double* lc = (double*)malloc(sizeof(double) * n);
     if (!lr || !lc) {
         free(lr); free(lc);
         return ORC_E_NOMEM;
     }
     int status = ORC_OK;
-    lse_rows(n, C, u, v, gamma, lr);
+    lse_rows(m, n, C, u, v, gamma, lr);
     cn->sweeps++;
     double res = 0.0;
-    for (int i = 0; i < n; ++i) res += fabs(rt[i] - exp(lr[i]));
+    for (int i = 0; i < m; ++i) res += fabs(rt[i] - exp(lr[i]));
     if (gnorm0_out) *gnorm0_out = res;
     int64_t it = 0;
     while (res > tol) {
@@ -493,14 +495,14 @@ static int sinkhorn(int n, const double* C, double gamma, const double* rt, cons
             status = ORC_W_NOT_CONVERGED;
             break;
         }
-        for (int i = 0; i < n; ++i) u[i] = u[i] + log(rt[i]) - lr[i];
+        for (int i = 0; i < m; ++i) u[i] = u[i] + log(rt[i]) - lr[i];
         /* v <- log c~ - LSE_c(u 1^T - gamma C): evaluate with the current v, then shift */
-        lse_cols(n, C, u, v, gamma, lc);
+        lse_cols(m, n, C, u, v, gamma, lc);
         for (int j = 0; j < n; ++j) v[j] = v[j] + log(ct[j]) - lc[j];
-        lse_rows(n, C, u, v, gamma, lr);
+        lse_rows(m, n, C, u, v, gamma, lr);
         cn->sweeps += 2;
         res = 0.0;
-        for (int i = 0; i < n; ++i) res += fabs(rt[i] - exp(lr[i]));
+        for (int i = 0; i < m; ++i) res += fabs(rt[i] - exp(lr[i]));
         cn->pncg_iters++;
         ++it;
     }
@@ -509,40 +511,40 @@ static int sinkhorn(int n, const double* C, double gamma, const double* rt, cons
     return status;
 }
 
-/* Round (Alg. 3, Altschuler et al.): project P onto U(r, c). G must hold n*n doubles. */
-void orc_round(int n, const double* P, const double* r, const double* c, double* G)
+/* Round (Alg. 3, Altschuler et al.): project P (m x n) onto U(r, c). G must hold m*n doubles. */
+void orc_round(int m, int n, const double* P, const double* r, const double* c, double* G)
 {
-    double* x = (double*)malloc(sizeof(double) * n);
+    double* x = (double*)malloc(sizeof(double) * m);
     double* y = (double*)malloc(sizeof(double) * n);
     double* cF = (double*)malloc(sizeof(double) * n);
-    double* er = (double*)malloc(sizeof(double) * n);
+    double* er = (double*)malloc(sizeof(double) * m);
     double* ec = (double*)malloc(sizeof(double) * n);
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < m; ++i) {
         double rs = 0.0;
         for (int j = 0; j < n; ++j) rs += P[(size_t)i * n + j];
         x[i] = (rs > 0.0) ? fmin(r[i] / rs, 1.0) : 1.0; /* x = r / r(P) ^ 1 */
     }
     /* F = D(x) P; y = c / c(F) ^ 1 */
     for (int j = 0; j < n; ++j) cF[j] = 0.0;
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < m; ++i)
         for (int j = 0; j < n; ++j) cF[j] += x[i] * P[(size_t)i * n + j];
     for (int j = 0; j < n; ++j) y[j] = (cF[j] > 0.0) ? fmin(c[j] / cF[j], 1.0) : 1.0;
     /* F' = F D(y) */
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < m; ++i)
         for (int j = 0; j < n; ++j) G[(size_t)i * n + j] = x[i] * P[(size_t)i * n + j] * y[j];
     /* err_r = r - r(F'), err_c = c - c(F') */
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < m; ++i) {
         double rs = 0.0;
         for (int j = 0; j < n; ++j) rs += G[(size_t)i * n + j];
         er[i] = r[i] - rs;
     }
     for (int j = 0; j < n; ++j) ec[j] = c[j];
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < m; ++i)
         for (int j = 0; j < n; ++j) ec[j] -= G[(size_t)i * n + j];
-    double l1 = norm1(n, er);
+    double l1 = norm1(m, er);
     /* G = F' + err_r err_c^T / ||err_r||_1 */
     if (l1 > 0.0)
-        for (int i = 0; i < n; ++i)
+        for (int i = 0; i < m; ++i)
             for (int j = 0; j < n; ++j) G[(size_t)i * n + j] += er[i] * ec[j] / l1;
     free(x); free(y); free(cF); free(er); free(ec);
 }
@@ -553,35 +555,35 @@ void orc_round(int n, const double* P, const double* r, const double* c, double*
  * Both orders (starting from f, and starting from g) are evaluated and the larger bound
  * is returned. Not part of the paper; it certifies the gap the paper measures against an
  * exact solver. */
-double orc_ctransform_bound(int n, const double* C, const double* f, const double* g, const double* r,
+double orc_ctransform_bound(int m, int n, const double* C, const double* f, const double* g, const double* r,
                             const double* c)
 {
-    double* a = (double*)malloc(sizeof(double) * n);
+    double* a = (double*)malloc(sizeof(double) * m);
     double* b = (double*)malloc(sizeof(double) * n);
     /* start from f */
     for (int j = 0; j < n; ++j) {
-        double m = INFINITY;
-        for (int i = 0; i < n; ++i) m = fmin(m, C[(size_t)i * n + j] - f[i]);
-        b[j] = m;
+        double mn = INFINITY;
+        for (int i = 0; i < m; ++i) mn = fmin(mn, C[(size_t)i * n + j] - f[i]);
+        b[j] = mn;
     }
-    for (int i = 0; i < n; ++i) {
-        double m = INFINITY;
-        for (int j = 0; j < n; ++j) m = fmin(m, C[(size_t)i * n + j] - b[j]);
-        a[i] = m;
+    for (int i = 0; i < m; ++i) {
+        double mn = INFINITY;
+        for (int j = 0; j < n; ++j) mn = fmin(mn, C[(size_t)i * n + j] - b[j]);
+        a[i] = mn;
     }
-    double lb1 = dot(n, a, r) + dot(n, b, c);
+    double lb1 = dot(m, a, r) + dot(n, b, c);
     /* start from g */
-    for (int i = 0; i < n; ++i) {
-        double m = INFINITY;
-        for (int j = 0; j < n; ++j) m = fmin(m, C[(size_t)i * n + j] - g[j]);
-        a[i] = m;
+    for (int i = 0; i < m; ++i) {
+        double mn = INFINITY;
+        for (int j = 0; j < n; ++j) mn = fmin(mn, C[(size_t)i * n + j] - g[j]);
+        a[i] = mn;
     }
     for (int j = 0; j < n; ++j) {
-        double m = INFINITY;
-        for (int i = 0; i < n; ++i) m = fmin(m, C[(size_t)i * n + j] - a[i]);
-        b[j] = m;
+        double mn = INFINITY;
+        for (int i = 0; i < m; ++i) mn = fmin(mn, C[(size_t)i * n + j] - a[i]);
+        b[j] = mn;
     }
-    double lb2 = dot(n, a, r) + dot(n, b, c);
+    double lb2 = dot(m, a, r) + dot(n, b, c);
     free(a); free(b);
     return fmax(lb1, lb2);
 }
@@ -590,51 +592,47 @@ double orc_ctransform_bound(int n, const double* C, const double* f, const doubl
  * UB = <G, C> and the marginal error of G. The lower bound is the larger double
  * c-transform bound of f = u/gamma (g = v/gamma) and, when u_prev is given, of the
  * finite difference f = (u - u_prev)/(gamma - gamma_prev), g likewise.
- * G_out (n*n) may be NULL. Returns ORC_OK or ORC_E_NOMEM. */
-int orc_round_certify(int n, const double* C, const double* u, const double* v, double gamma,
+ * G_out (m*n) may be NULL. Returns ORC_OK or ORC_E_NOMEM. */
+int orc_round_certify(int m, int n, const double* C, const double* u, const double* v, double gamma,
                       const double* u_prev, const double* v_prev, double gamma_prev,
                       const double* r, const double* c, double* ub, double* lb, double* marg_err,
                       double* G_out)
 {
-    size_t nn = (size_t)n * n;
-    double* P = (double*)malloc(sizeof(double) * nn);
-    double* G = G_out ? G_out : (double*)malloc(sizeof(double) * nn);
-    double* f = (double*)malloc(sizeof(double) * n);
+    size_t mn = (size_t)m * n;
+    double* P = (double*)malloc(sizeof(double) * mn);
+    double* G = G_out ? G_out : (double*)malloc(sizeof(double) * mn);
+    double* f = (double*)malloc(sizeof(double) * m);
     double* g = (double*)malloc(sizeof(double) * n);
     if (!P || !G || !f || !g) {
         free(P); if (!G_out) free(G); free(f); free(g);
         return ORC_E_NOMEM;
     }
 #pragma omp parallel for schedule(static)
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < m; ++i)
         for (int j = 0; j < n; ++j) P[(size_t)i * n + j] = exp(u[i] + v[j] - gamma * C[(size_t)i * n + j]);
-    orc_round(n, P, r, c, G);
+    orc_round(m, n, P, r, c, G);
     double s = 0.0;
-    for (size_t k = 0; k < nn; ++k) s += G[k] * C[k];
+    for (size_t k = 0; k < mn; ++k) s += G[k] * C[k];
     *ub = s;
     double e = 0.0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < m; ++i) {
         double rs = 0.0;
         for (int j = 0; j < n; ++j) rs += G[(size_t)i * n + j];
         e += fabs(rs - r[i]);
     }
     for (int j = 0; j < n; ++j) {
         double cs = 0.0;
-        for (int i = 0; i < n; ++i) cs += G[(size_t)i * n + j];
+        for (int i = 0; i < m; ++i) cs += G[(size_t)i * n + j];
         e += fabs(cs - c[j]);
     }
     *marg_err = e;
-    for (int i = 0; i < n; ++i) {
-        f[i] = u[i] / gamma;
-        g[i] = v[i] / gamma;
-    }
-    double b = orc_ctransform_bound(n, C, f, g, r, c);
+    for (int i = 0; i < m; ++i) f[i] = u[i] / gamma;
+    for (int j = 0; j < n; ++j) g[j] = v[j] / gamma;
+    double b = orc_ctransform_bound(m, n, C, f, g, r, c);
     if (u_prev && v_prev && gamma > gamma_prev) {
-        for (int i = 0; i < n; ++i) {
-            f[i] = (u[i] - u_prev[i]) / (gamma - gamma_prev);
-            g[i] = (v[i] - v_prev[i]) / (gamma - gamma_prev);
-        }
-        b = fmax(b, orc_ctransform_bound(n, C, f, g, r, c));
+        for (int i = 0; i < m; ++i) f[i] = (u[i] - u_prev[i]) / (gamma - gamma_prev);
+        for (int j = 0; j < n; ++j) g[j] = (v[j] - v_prev[j]) / (gamma - gamma_prev);
+        b = fmax(b, orc_ctransform_bound(m, n, C, f, g, r, c));
     }
     *lb = b;
     free(P); if (!G_out) free(G); free(f); free(g);
@@ -642,12 +640,12 @@ int orc_round_certify(int n, const double* C, const double* u, const double* v, 
 }
 
 /* KL projection at fixed gamma from z (PNCG or Sinkhorn), as called by the inner solve of Alg. 1. */
-int orc_project(int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
+int orc_project(int m, int n, const double* C, double gamma, const double* rt, const double* ct, double tol,
                 double* z, const orc_params* prm, int64_t* counts /* [6] or NULL */, double* gnorm)
 {
     counters cn = {0, 0, 0, 0, 0, 0};
-    int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm, NULL)
-                                 : pncg(n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm, NULL);
+    int st = prm->projector == 1 ? sinkhorn(m, n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm, NULL)
+                                 : pncg(m, n, C, gamma, rt, ct, tol, z, prm, &cn, gnorm, NULL);
     if (counts) {
         counts[0] = cn.pncg_iters; counts[1] = cn.ls_trials; counts[2] = cn.sweeps;
         counts[3] = cn.cg_resets; counts[4] = cn.ls_failures; counts[5] = cn.tilde_iters;
@@ -660,24 +658,27 @@ int orc_project(int n, const double* C, double gamma, const double* rt, const do
  * gamma_f and the final plan is rounded and certified once; with gamma_f == 0 the loop
  * rounds and certifies after every stage and stops when the certified gap is at most
  * target_gap, or at gamma_cap. log (capacity log_cap) receives one entry per stage. */
-int orc_mdot(int n, const double* C, const double* r, const double* c, const orc_params* prm,
+int orc_mdot(int m, int n, const double* C, const double* r, const double* c, const orc_params* prm,
              double* u_out, double* v_out, orc_result* res, orc_stage_log* log_, int log_cap)
 {
-    if (n < 1 || !C || !r || !c || !prm || !res) return ORC_E_ARG;
+    if (m < 1 || n < 1 || !C || !r || !c || !prm || !res) return ORC_E_ARG;
     memset(res, 0, sizeof(*res));
-    const int m = 2 * n;
+    const int len = m + n;
     const int adaptive = !(prm->gamma_f > 0.0);
-    const double hmin = fmin(orc_entropy(n, r), orc_entropy(n, c)); /* H_min (Prop. 1.3) */
+    const double hmin = fmin(orc_entropy(m, r), orc_entropy(n, c)); /* H_min (Prop. 1.3) */
     double gf;
     if (!adaptive) gf = prm->gamma_f;
     else gf = prm->gamma_cap > 0.0 ? prm->gamma_cap : 5.0 * hmin / (2.0 * prm->target_gap); /* Remark 1 */
+    /* H_min = 0 (a point-mass marginal, e.g. m = 1 or n = 1) gives a zero cap: U(r, c) then holds
+     * a single plan, which Round recovers from any P, so a single stage at gamma_i suffices */
+    if (!(gf > 0.0)) gf = prm->gamma_i;
     /* the entropy term of eps_d: H_min (Alg. 1), or log n (App. C) */
-    const double hterm = prm->tol_log_n ? log((double)n) : hmin;
+    const double hterm = prm->tol_log_n ? log((double)(m < n ? m : n)) : hmin;
 
-    double* z = (double*)malloc(sizeof(double) * m);      /* current (u, v) */
-    double* zprev = (double*)malloc(sizeof(double) * m);  /* solution at the previous gamma */
-    double* zbest = (double*)malloc(sizeof(double) * m);
-    double* rt = (double*)malloc(sizeof(double) * n);
+    double* z = (double*)malloc(sizeof(double) * len);      /* current (u, v) */
+    double* zprev = (double*)malloc(sizeof(double) * len);  /* solution at the previous gamma */
+    double* zbest = (double*)malloc(sizeof(double) * len);
+    double* rt = (double*)malloc(sizeof(double) * m);
     double* ct = (double*)malloc(sizeof(double) * n);
     if (!z || !zprev || !zbest || !rt || !ct) {
         free(z); free(zprev); free(zbest); free(rt); free(ct);
@@ -692,22 +693,18 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
         double eps_d = hterm / pow(gamma, prm->p); /* entropy-aware tolerance (Alg. 1) */
         double w = fmin(eps_d / 4.0, 0.5);         /* variable smoothing weight (Alg. 1) */
         if (prm->smoothing == 1) w = fmin(hterm / pow(gf, prm->p) / 4.0, 0.5); /* fixed (App. D) */
-        for (int i = 0; i < n; ++i) {
-            rt[i] = (1.0 - w) * r[i] + w / n;
-            ct[i] = (1.0 - w) * c[i] + w / n;
-        }
+        for (int i = 0; i < m; ++i) rt[i] = (1.0 - w) * r[i] + w / m;
+        for (int j = 0; j < n; ++j) ct[j] = (1.0 - w) * c[j] + w / n;
         if (t == 1) { /* rank-1 initial guess (Alg. 1); also z^0 for the first warm start */
-            for (int i = 0; i < n; ++i) {
-                z[i] = log(rt[i]);
-                z[n + i] = log(ct[i]);
-            }
-            memcpy(zprev, z, sizeof(double) * m);
+            for (int i = 0; i < m; ++i) z[i] = log(rt[i]);
+            for (int j = 0; j < n; ++j) z[m + j] = log(ct[j]);
+            memcpy(zprev, z, sizeof(double) * len);
         }
         counters before = tot; /* the projector counts into the solve totals (one sweep budget) */
         double tol = fmax(eps_d / 2.0, TOL_FLOOR);
         double gnorm0 = 0.0;
-        int st = prm->projector == 1 ? sinkhorn(n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm, &gnorm0)
-                                     : pncg(n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm, &gnorm0);
+        int st = prm->projector == 1 ? sinkhorn(m, n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm, &gnorm0)
+                                     : pncg(m, n, C, gamma, rt, ct, tol, z, prm, &tot, &gnorm, &gnorm0);
         if (st < 0) { status = st; break; }
         if (st == ORC_W_NOT_CONVERGED) inner_warn = 1;
         counters cn = {tot.pncg_iters - before.pncg_iters, tot.ls_trials - before.ls_trials,
@@ -718,12 +715,12 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
         const int budget_stop = !budget_left(prm, &tot);
         if (adaptive || last || budget_stop) {
             double me;
-            int rc = orc_round_certify(n, C, z, z + n, gamma, zprev, zprev + n, gamma_prev, r, c, &ub,
+            int rc = orc_round_certify(m, n, C, z, z + m, gamma, zprev, zprev + m, gamma_prev, r, c, &ub,
                                        &lb, &me, NULL);
             if (rc != ORC_OK) { status = rc; break; }
             if (ub < best_ub) {
                 best_ub = ub; best_gamma = gamma; best_me = me;
-                memcpy(zbest, z, sizeof(double) * m);
+                memcpy(zbest, z, sizeof(double) * len);
             }
             if (lb > best_lb) best_lb = lb;
         }
@@ -747,7 +744,7 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
         /* warm start, eq. (approx-znext): z' = z^t + (dg^t / dg^{t-1}) (z^t - z^{t-1});
          * the epsilon-scaling variant predicts z' = (gamma^{t+1} / gamma^t) z^t (Sec. 4.2.1) */
         double ratio = prm->warm_start == 1 ? dg / dg_prev : 0.0;
-        for (int k = 0; k < m; ++k) {
+        for (int k = 0; k < len; ++k) {
             double zt = z[k];
             z[k] = prm->warm_start == 2 ? (gnew / gamma) * zt : zt + ratio * (zt - zprev[k]);
             zprev[k] = zt;
@@ -766,8 +763,8 @@ int orc_mdot(int n, const double* C, const double* r, const double* c, const orc
     res->pncg_iters = tot.pncg_iters; res->ls_trials = tot.ls_trials; res->sweeps = tot.sweeps;
     res->cg_resets = tot.cg_resets; res->ls_failures = tot.ls_failures;
     if (u_out && v_out && isfinite(best_ub)) {
-        memcpy(u_out, zbest, sizeof(double) * n);
-        memcpy(v_out, zbest + n, sizeof(double) * n);
+        memcpy(u_out, zbest, sizeof(double) * m);
+        memcpy(v_out, zbest + m, sizeof(double) * n);
     }
     free(z); free(zprev); free(zbest); free(rt); free(ct);
     return status;

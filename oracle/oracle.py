@@ -102,20 +102,20 @@ def lib():
         L.orc_default_params.argtypes = [ct.POINTER(Params)]
         L.orc_entropy.restype = ct.c_double
         L.orc_entropy.argtypes = [ct.c_int, _dp]
-        L.orc_lse2.argtypes = [ct.c_int, _dp, _dp, _dp, ct.c_double, _dp, _dp]
+        L.orc_lse2.argtypes = [ct.c_int, ct.c_int, _dp, _dp, _dp, ct.c_double, _dp, _dp]
         L.orc_dual_objective.restype = ct.c_double
-        L.orc_dual_objective.argtypes = [ct.c_int, _dp, _dp, _dp, ct.c_double, _dp, _dp]
-        L.orc_round.argtypes = [ct.c_int, _dp, _dp, _dp, _dp]
+        L.orc_dual_objective.argtypes = [ct.c_int, ct.c_int, _dp, _dp, _dp, ct.c_double, _dp, _dp]
+        L.orc_round.argtypes = [ct.c_int, ct.c_int, _dp, _dp, _dp, _dp]
         L.orc_ctransform_bound.restype = ct.c_double
-        L.orc_ctransform_bound.argtypes = [ct.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.orc_ctransform_bound.argtypes = [ct.c_int, ct.c_int, _dp, _dp, _dp, _dp, _dp]
         L.orc_round_certify.restype = ct.c_int
-        L.orc_round_certify.argtypes = [ct.c_int, _dp, _dp, _dp, ct.c_double, _dp, _dp, ct.c_double,
+        L.orc_round_certify.argtypes = [ct.c_int, ct.c_int, _dp, _dp, _dp, ct.c_double, _dp, _dp, ct.c_double,
                                         _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_project.restype = ct.c_int
-        L.orc_project.argtypes = [ct.c_int, _dp, ct.c_double, _dp, _dp, ct.c_double, _dp,
+        L.orc_project.argtypes = [ct.c_int, ct.c_int, _dp, ct.c_double, _dp, _dp, ct.c_double, _dp,
                                   ct.POINTER(Params), ct.POINTER(ct.c_int64), _dp]
         L.orc_mdot.restype = ct.c_int
-        L.orc_mdot.argtypes = [ct.c_int, _dp, _dp, _dp, ct.POINTER(Params), _dp, _dp,
+        L.orc_mdot.argtypes = [ct.c_int, ct.c_int, _dp, _dp, _dp, ct.POINTER(Params), _dp, _dp,
                                ct.POINTER(Result), ct.POINTER(StageLog), ct.c_int]
         L.orc_num_threads.restype = ct.c_int
         L.orc_set_num_threads.argtypes = [ct.c_int]
@@ -174,44 +174,56 @@ def entropy(r) -> float:
     return lib().orc_entropy(r.size, _d(r))
 
 
+def _shape(C, r=None, c=None):
+    """(m, n) of an m x n cost (rows follow r, columns follow c)."""
+    if C.ndim != 2:
+        raise ValueError("C must be a matrix")
+    m, n = C.shape
+    if (r is not None and r.size != m) or (c is not None and c.size != n):
+        raise ValueError("marginal sizes do not match the cost")
+    return m, n
+
+
 def lse2(C, u, v, gamma: float):
-    """(log r(P), log c(P)) of P = exp(u_i + v_j - gamma C_ij), FP64 two-pass."""
+    """(log r(P), log c(P)) of P = exp(u_i + v_j - gamma C_ij), FP64 two-pass; C is m x n."""
     C, u, v = _f64(C), _f64(u), _f64(v)
-    n = u.size
-    lr = np.empty(n)
+    m, n = _shape(C, u, v)
+    lr = np.empty(m)
     lc = np.empty(n)
-    lib().orc_lse2(n, _d(C), _d(u), _d(v), float(gamma), _d(lr), _d(lc))
+    lib().orc_lse2(m, n, _d(C), _d(u), _d(v), float(gamma), _d(lr), _d(lc))
     return lr, lc
 
 
 def dual_objective(C, u, v, gamma, r, c) -> float:
     C, u, v, r, c = map(_f64, (C, u, v, r, c))
-    return lib().orc_dual_objective(u.size, _d(C), _d(u), _d(v), float(gamma), _d(r), _d(c))
+    m, n = _shape(C, r, c)
+    return lib().orc_dual_objective(m, n, _d(C), _d(u), _d(v), float(gamma), _d(r), _d(c))
 
 
 def round_plan(P, r, c) -> np.ndarray:
     P, r, c = _f64(P), _f64(r), _f64(c)
-    n = r.size
-    G = np.empty((n, n))
-    lib().orc_round(n, _d(P), _d(r), _d(c), _d(G))
+    m, n = _shape(P, r, c)
+    G = np.empty((m, n))
+    lib().orc_round(m, n, _d(P), _d(r), _d(c), _d(G))
     return G
 
 
 def ctransform_bound(C, f, g, r, c) -> float:
     C, f, g, r, c = map(_f64, (C, f, g, r, c))
-    return lib().orc_ctransform_bound(r.size, _d(C), _d(f), _d(g), _d(r), _d(c))
+    m, n = _shape(C, r, c)
+    return lib().orc_ctransform_bound(m, n, _d(C), _d(f), _d(g), _d(r), _d(c))
 
 
 def round_certify(C, u, v, gamma, r, c, want_plan: bool = False, u_prev=None, v_prev=None,
                   gamma_prev: float = 0.0):
     """(UB, LB, marginal error, G or None) for the plan P(u, v; gamma)."""
     C, u, v, r, c = map(_f64, (C, u, v, r, c))
-    n = r.size
+    m, n = _shape(C, r, c)
     ub, lb, me = ct.c_double(), ct.c_double(), ct.c_double()
-    G = np.empty((n, n)) if want_plan else None
+    G = np.empty((m, n)) if want_plan else None
     up = _f64(u_prev) if u_prev is not None else None
     vp = _f64(v_prev) if v_prev is not None else None
-    rc = lib().orc_round_certify(n, _d(C), _d(u), _d(v), float(gamma), _d(up) if up is not None else None,
+    rc = lib().orc_round_certify(m, n, _d(C), _d(u), _d(v), float(gamma), _d(up) if up is not None else None,
                                  _d(vp) if vp is not None else None, float(gamma_prev), _d(r), _d(c), ct.byref(ub),
                                  ct.byref(lb), ct.byref(me), _d(G) if want_plan else None)
     if rc != 0:
@@ -223,14 +235,14 @@ def project(C, gamma, rt, ct_, tol, u, v, params: Params | None = None):
     """KL projection at fixed gamma (PNCG, or Sinkhorn with params.projector=1).
     Returns (u, v, status, counts[pncg_iters, ls_trials, sweeps, cg_resets, ls_failures, tilde_iters], gnorm)."""
     C, rt, ct_ = _f64(C), _f64(rt), _f64(ct_)
-    n = rt.size
+    m, n = _shape(C, rt, ct_)
     z = np.concatenate([_f64(u), _f64(v)])
     prm = params or default_params()
     counts = (ct.c_int64 * 6)()
     gn = ct.c_double()
-    st = lib().orc_project(n, _d(C), float(gamma), _d(rt), _d(ct_), float(tol), _d(z), ct.byref(prm),
+    st = lib().orc_project(m, n, _d(C), float(gamma), _d(rt), _d(ct_), float(tol), _d(z), ct.byref(prm),
                            counts, ct.byref(gn))
-    return z[:n].copy(), z[n:].copy(), st, list(counts), gn.value
+    return z[:m].copy(), z[m:].copy(), st, list(counts), gn.value
 
 
 @dataclass
@@ -243,15 +255,15 @@ class Solve:
 
 
 def mdot(C, r, c, params: Params | None = None, max_stages: int = 256) -> Solve:
-    """Run MDOT (Alg. 1) with the PNCG projector; returns potentials, status, result, stage log."""
+    """Run MDOT (Alg. 1) on an m x n cost; returns potentials, status, result, stage log."""
     C, r, c = _f64(C), _f64(r), _f64(c)
-    n = r.size
+    m, n = _shape(C, r, c)
     prm = params or default_params()
-    u = np.zeros(n)
+    u = np.zeros(m)
     v = np.zeros(n)
     res = Result()
     logs = (StageLog * max_stages)()
-    st = lib().orc_mdot(n, _d(C), _d(r), _d(c), ct.byref(prm), _d(u), _d(v), ct.byref(res), logs,
+    st = lib().orc_mdot(m, n, _d(C), _d(r), _d(c), ct.byref(prm), _d(u), _d(v), ct.byref(res), logs,
                         max_stages)
     rd = {f: getattr(res, f) for f, _ in Result._fields_}
     stages = [{f: getattr(logs[k], f) for f, _ in StageLog._fields_} for k in range(min(res.stages, max_stages))]

@@ -20,6 +20,10 @@ transposed operand, a dropped term) breaks at least one of them:
   wrong smoothing / schedule / stop test ..... test_schedule_and_stage_tolerances, test_fixed_smoothing,
                                                test_log_n_tolerance
   whole-solve errors ......................... exact LP, Birkhoff and 1-D closed-form tests
+  swapped m / n, wrong side of a rectangular
+  problem, wrong per-side smoothing ........... test_rectangular_* (LSE by definition, finite
+                                               differences, transpose symmetry, exact LP, 1-D
+                                               monotone coupling, separable cost)
 """
 from __future__ import annotations
 
@@ -569,3 +573,102 @@ def test_log_n_tolerance():
     ot = exact_lp(C, r, c)
     s2 = O.mdot(C, r, c, O.default_params(target_gap=1e-6, tol_log_n=1))
     assert s2.status == 0 and s2.result["dual_bound"] <= ot + 1e-12 <= s2.result["primal_cost"] + 2e-12
+
+
+# ---------------------------------------------------------------- rectangular problems (m != n)
+def _rect_problem(m, n, seed):
+    rng = np.random.default_rng(seed)
+    C = rng.random((m, n))
+    r = rng.random(m) + 0.05
+    c = rng.random(n) + 0.05
+    return C, r / r.sum(), c / c.sum()
+
+
+def test_rectangular_lse_and_gradient_against_definitions():
+    # m x n LSEs by their definition (scipy), and the gradient (r(P) - r, c(P) - c) against
+    # central differences of the dual objective: a swapped m / n or a transposed C fails here
+    m, n, gamma = 7, 11, 3.0
+    C, r, c = _rect_problem(m, n, 1)
+    rng = np.random.default_rng(2)
+    u, v = rng.standard_normal(m) * 0.3, rng.standard_normal(n) * 0.3
+    lr, lc = O.lse2(C, u, v, gamma)
+    X = u[:, None] + v[None, :] - gamma * C
+    np.testing.assert_allclose(lr, logsumexp(X, axis=1), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(lc, logsumexp(X, axis=0), rtol=0, atol=1e-14)
+    h = 1e-6
+    fd_u = [(O.dual_objective(C, u + h * e, v, gamma, r, c) - O.dual_objective(C, u - h * e, v, gamma, r, c)) / (2 * h)
+            for e in np.eye(m)]
+    fd_v = [(O.dual_objective(C, u, v + h * e, gamma, r, c) - O.dual_objective(C, u, v - h * e, gamma, r, c)) / (2 * h)
+            for e in np.eye(n)]
+    np.testing.assert_allclose(fd_u, np.exp(lr) - r, rtol=0, atol=1e-8)
+    np.testing.assert_allclose(fd_v, np.exp(lc) - c, rtol=0, atol=1e-8)
+
+
+def test_rectangular_transpose_swaps_sides():
+    # OT(r, c, C) = OT(c, r, C^T); the LSEs of C^T are those of C with the sides swapped, bit for
+    # bit (each is the same ascending sum)
+    m, n, gamma = 9, 14, 40.0
+    C, r, c = _rect_problem(m, n, 3)
+    rng = np.random.default_rng(4)
+    u, v = rng.standard_normal(m) * 0.2, rng.standard_normal(n) * 0.2
+    lr, lc = O.lse2(C, u, v, gamma)
+    lr_t, lc_t = O.lse2(np.ascontiguousarray(C.T), v, u, gamma)
+    assert np.array_equal(lr, lc_t) and np.array_equal(lc, lr_t)
+    a = O.mdot(C, r, c, O.default_params(target_gap=1e-7)).result
+    b = O.mdot(np.ascontiguousarray(C.T), c, r, O.default_params(target_gap=1e-7)).result
+    ot = exact_lp(C, r, c)
+    for R in (a, b):
+        assert R["gap"] <= 1e-7 and R["dual_bound"] <= ot + 1e-12 <= R["primal_cost"] + 2e-12
+
+
+@pytest.mark.parametrize("m,n,seed", [(12, 20, 5), (31, 8, 6), (1, 5, 7), (6, 1, 8)])
+@pytest.mark.parametrize("variant", [{}, dict(projector=1), dict(precond=1)])
+def test_rectangular_certificate_brackets_exact_lp(m, n, seed, variant):
+    C, r, c = _rect_problem(m, n, seed)
+    ot = exact_lp(C, r, c)
+    s = O.mdot(C, r, c, O.default_params(target_gap=1e-6, **variant))
+    R = s.result
+    assert s.status == 0 and s.u.size == m and s.v.size == n
+    assert R["dual_bound"] <= ot + 1e-12 <= R["primal_cost"] + 2e-12
+    assert R["primal_cost"] - ot <= 1e-6
+    assert R["marg_err_l1"] <= 1e-12
+    # the rounded plan is feasible for the rectangular marginals
+    ub, lb, me, G = O.round_certify(C, s.u, s.v, R["gamma_final"], r, c, want_plan=True)
+    assert G.shape == (m, n) and G.min() >= -1e-15  # err_c >= 0 up to rounding
+    np.testing.assert_allclose(G.sum(1), r, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(G.sum(0), c, rtol=0, atol=1e-14)
+
+
+def test_rectangular_one_dimensional_closed_form():
+    # 1-D OT between m and n points with |x - y|: the monotone coupling (sorted north-west
+    # corner) is optimal for supports of different sizes too
+    m, n = 40, 70
+    rng = np.random.default_rng(9)
+    x = np.sort(rng.random(m))
+    y = np.sort(rng.random(n))
+    r = W.dirichlet_marginal(m, 3) * 0.5 + 0.5 / m
+    c = W.dirichlet_marginal(n, 4) * 0.5 + 0.5 / n
+    C = np.abs(x[:, None] - y[None, :])
+    scale = C.max()
+    ot = monotone_1d(x, r, y, c, 1.0) / scale
+    assert exact_lp(C / scale, r, c) == pytest.approx(ot, abs=1e-12)
+    R = O.mdot(C / scale, r, c, O.default_params(target_gap=1e-6)).result
+    assert R["dual_bound"] <= ot + 1e-12 <= R["primal_cost"] + 2e-12
+    assert R["primal_cost"] - ot <= 1e-6
+
+
+def test_rectangular_separable_cost_and_smoothing():
+    # C_ij = a_i + b_j: every plan in U(r, c) costs <a, r> + <b, c>, and the EOT plan is the
+    # product of the smoothed marginals r~ c~^T with r~ = (1 - w) r + w/m, c~ = (1 - w) c + w/n
+    m, n, gamma = 5, 9, 64.0
+    rng = np.random.default_rng(10)
+    a, b = rng.random(m) * 0.5, rng.random(n) * 0.5
+    C = a[:, None] + b[None, :]
+    _, r, c = _rect_problem(m, n, 11)
+    w = 0.01
+    rt, ct_ = (1 - w) * r + w / m, (1 - w) * c + w / n
+    u, v, st, counts, gn = O.project(C, gamma, rt, ct_, 1e-13, np.log(rt), np.log(ct_))
+    P = np.exp(u[:, None] + v[None, :] - gamma * C)
+    np.testing.assert_allclose(P, np.outer(rt, ct_), rtol=1e-10, atol=1e-15)
+    R = O.mdot(C, r, c, O.default_params(target_gap=1e-9)).result
+    assert R["primal_cost"] == pytest.approx(a @ r + b @ c, abs=1e-12)
