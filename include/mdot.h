@@ -48,17 +48,20 @@ enum {
     MDOT_W_NOT_CONVERGED = 1,
     MDOT_W_RANGE = 2,
     MDOT_E_ARG = -1,      /* bad size, NULL pointer, bad enum or parameter */
-    MDOT_E_MARGINAL = -2, /* r or c negative, non-finite, or |sum - 1| > 1e-9 n */
+    MDOT_E_MARGINAL = -2, /* r or c negative, non-finite, or |sum - 1| > 1e-9 max(m, n) */
     MDOT_E_COST = -3,     /* scaled cost outside [0, 1] or non-finite */
     MDOT_E_NOMEM = -4,    /* device allocation failed, or the request exceeds the HBM budget */
     MDOT_E_DEVICE = -5,   /* a HIP call failed */
     MDOT_E_BUSY = -6      /* no free serving slot */
 };
 
-/* How C is given. DENSE: data is an n*n row-major array of dtype. POINTS_* (d = 1..8): data holds
- * X (n*d FP32, row-major) followed by Y (n*d FP32); C_ij = scale * dist(x_i, y_j), computed
- * on the fly in FP64 inside the sweep (paper Sec. 3: O(n) memory when entries of C can be
- * computed in O(1)). */
+/* How C is given. C is m x n: row i is source i (marginal r_i), column j is target j (marginal
+ * c_j); the paper's problems are square (m = n), rectangular ones take the same path.
+ * DENSE: data is an m*n row-major array of dtype. POINTS_* (d = 1..8): data holds X (m*d FP32,
+ * row-major) followed by Y (n*d FP32); C_ij = scale * dist(x_i, y_j), computed on the fly in
+ * FP64 inside the sweep (paper Sec. 3: O(n) memory when entries of C can be computed in O(1)).
+ * Everywhere below, vectors indexed by rows (r, u, log r(P), shift) have m entries and vectors
+ * indexed by columns (c, v, log c(P)) have n. */
 typedef enum { MDOT_COST_DENSE = 0, MDOT_COST_POINTS_SQEUCLID = 1, MDOT_COST_POINTS_L1 = 2 } mdot_cost_kind;
 typedef enum { MDOT_DT_F64 = 0, MDOT_DT_F32 = 1, MDOT_DT_F16 = 2, MDOT_DT_BF16 = 3 } mdot_dtype;
 
@@ -79,12 +82,14 @@ typedef enum { MDOT_PREC_F64 = 0, MDOT_PREC_F32 = 1, MDOT_PREC_MIXED = 2 } mdot_
 #define MDOT_NOALLOC_MAX_N 4096 /* largest n of mdot_lse2_noalloc */
 
 typedef struct {
-    int32_t n;            /* problem size, 1..MDOT_MAX_N */
+    int32_t n;            /* columns (targets, marginal c), 1..MDOT_MAX_N */
     int32_t d;            /* point dimension for POINTS_* (1..8), ignored for DENSE */
     mdot_cost_kind kind;
     mdot_dtype dtype;     /* DENSE only: element type of data (POINTS_* use FP32 coordinates) */
     const void* data;     /* device */
     double scale;         /* C = scale * raw; > 0. For POINTS_*, 0 means 1 / max_ij raw. */
+    int32_t m;            /* rows (sources, marginal r), 1..MDOT_MAX_N; 0 means m = n (square) */
+    int32_t reserved;     /* must be 0 */
 } mdot_cost_desc;
 
 typedef struct {
@@ -155,11 +160,12 @@ void mdot_default_params(mdot_params* out);
 /* Solve OT(r, c, C) to a certified gap <= target_gap (adaptive mode), or run the paper's
  * schedule to params->gamma_f (schedule mode).
  *   cost       : cost descriptor (device data)
- *   r, c       : device FP64[n], on the simplex: non-negative, finite, |sum - 1| <= 1e-9 n
+ *   r, c       : device FP64[m] and FP64[n], on the simplex: non-negative, finite,
+ *                |sum - 1| <= 1e-9 max(m, n)
  *   target_gap : > 0 in adaptive mode (ignored in schedule mode)
  *   params     : NULL = mdot_default_params()
- *   u_out,v_out: device FP64[n] or NULL: potentials (nats) of the reported stage, gauge
- *                fixed so that sum(u) = sum(v)
+ *   u_out,v_out: device FP64[m] / FP64[n] or NULL: potentials (nats) of the reported stage,
+ *                gauge fixed so that sum(u) = sum(v)
  *   res        : host, required
  * Synchronous. Returns MDOT_OK, MDOT_W_NOT_CONVERGED or an error. */
 int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const double* c,
@@ -168,8 +174,8 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
 
 /* One fused two-sided LogSumExp sweep (Alg. 2, the lines forming log r(P) and log c(P)):
  *   lr_i = log sum_j exp(u_i + v_j - gamma C_ij),   lc_j = log sum_i exp(u_i + v_j - gamma C_ij)
- * in one pass over C. u, v: device FP64[n]; lr_out, lc_out: device FP64[n].
- * shift: device FP64[n] prediction of lr used as the per-row exponent shift, or NULL, in
+ * in one pass over C. u, lr_out: device FP64[m]; v, lc_out: device FP64[n].
+ * shift: device FP64[m] prediction of lr used as the per-row exponent shift, or NULL, in
  * which case the library first runs a row-max pass. Columns are exact to FP32/FP64 range
  * when their log-sum lies within ~60 (F32) / ~700 (F64) nats of the largest row shift of
  * each 64-row tile; otherwise MDOT_W_RANGE is returned (values then may be -inf).
@@ -181,7 +187,7 @@ int mdot_lse2(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const 
  * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
  * Same arguments, results and return values as mdot_lse2 (the same kernels run; lr_out and
  * lc_out are bit-identical to mdot_lse2's), with these limits:
- *   - n <= MDOT_NOALLOC_MAX_N (4096), else MDOT_E_ARG;
+ *   - m, n <= MDOT_NOALLOC_MAX_N (4096), else MDOT_E_ARG;
  *   - cost->scale > 0 for point costs too (scale 0 asks for a max pass, which this call does
  *     not run), else MDOT_E_ARG.
  * Its partials, state and control block live in one static device array per GPU (about
@@ -200,7 +206,7 @@ int mdot_lse2_noalloc(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u
  * give UB = <G, C> with G = Round(P, r, c), and LB = the larger double c-transform bound of
  * (u/gamma, v/gamma) and, when u_prev/v_prev are non-NULL, of
  * ((u - u_prev)/(gamma - gamma_prev), (v - v_prev)/(gamma - gamma_prev)).
- * u, v, u_prev, v_prev, r, c: device FP64[n]. ub, lb, marg_err: host. Synchronous. */
+ * u, u_prev, r: device FP64[m]; v, v_prev, c: device FP64[n]. ub, lb, marg_err: host. Synchronous. */
 int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v,
                        double gamma, const double* u_prev, const double* v_prev, double gamma_prev,
                        const double* r, const double* c, double* ub, double* lb, double* marg_err);
@@ -247,7 +253,7 @@ int mdot_inflight(mdot_ctx* ctx, int* n_active, size_t* bytes_in_use);
 /* Measurement hook: run the solver's fused LSE sweep kernel `iters` times back-to-back on the
  * context stream at the potentials (u, v) and gamma (shifts set to the exact log-sums first,
  * as in a line-search trial near the solution) and return the mean duration per sweep in
- * milliseconds, taken with HIP events on that stream. u, v: device FP64[n]; ms_per_sweep: host.
+ * milliseconds, taken with HIP events on that stream. u, v: device FP64[m], FP64[n]; ms_per_sweep: host.
  * Synchronous. */
 int mdot_bench_sweep(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const double* v, double gamma,
                      mdot_precision precision, int iters, double* ms_per_sweep);

@@ -41,7 +41,7 @@ struct ProblemBufs {
     bool borrowed = false;  // the buffers live in memory the context does not own (never freed)
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    int cap_n = 0;
+    int cap_n = 0;  // largest of m and n the workspace was bound for (pool ordering only)
     Work* d_work = nullptr;  // the Control block (Work, State[2], DevParams, dots)
     DevParams* d_prm = nullptr;  // inside the Control block
     Work host_work{};
@@ -114,9 +114,9 @@ struct mdot_ctx {
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipGraphExec_t graph = nullptr;  // captured chunk of solver steps for `main`
-    // what the graph was captured with: n and the sweep kernel instance (cost code, which also
-    // tells planar point clouds from d = 3 ones)
-    int graph_n = 0, graph_code = -1;
+    // what the graph was captured with: m, n and the sweep kernel instance (cost code, which also
+    // tells the point dimension classes apart)
+    int graph_m = 0, graph_n = 0, graph_code = -1;
     // serving engine
     hipStream_t side = nullptr;     // intake of admitted solves (does not wait for the chunk in flight)
     Slot slots[kMaxBatch];
@@ -176,18 +176,21 @@ static int fail(mdot_ctx* ctx, int code, const char* fmt, ...)
 static inline int tiles_r(int n) { return (n + kBR - 1) / kBR; }
 static inline int tiles_c(int n) { return (n + kBC - 1) / kBC; }
 
-// Bytes of workspace for size n (see Work and ws_offset in mdot_internal.h); out_offsets, if
-// given, receives the kWsBuffers + 1 buffer offsets.
-static size_t workspace_bytes(int n, size_t* out_offsets = nullptr)
+// Rows of a cost (m = 0 in the descriptor means square).
+static inline int rows_of(const mdot_cost_desc* c) { return c->m > 0 ? c->m : c->n; }
+
+// Bytes of workspace for m rows and n columns (see Work and ws_offset in mdot_internal.h);
+// out_offsets, if given, receives the kWsBuffers + 1 buffer offsets.
+static size_t workspace_bytes(int m, int n, size_t* out_offsets = nullptr)
 {
     if (out_offsets)
-        for (int i = 0; i <= kWsBuffers; ++i) out_offsets[i] = ws_offset(i, (size_t)n);
-    return ws_offset(kWsBuffers, (size_t)n);
+        for (int i = 0; i <= kWsBuffers; ++i) out_offsets[i] = ws_offset(i, (size_t)m, (size_t)n);
+    return ws_offset(kWsBuffers, (size_t)m, (size_t)n);
 }
 
-static size_t problem_footprint(int n)
+static size_t problem_footprint(int m, int n)
 {
-    return workspace_bytes(n) + sizeof(Control);
+    return workspace_bytes(m, n) + sizeof(Control);
 }
 
 static void free_bufs(ProblemBufs& pb)
@@ -202,9 +205,9 @@ static void free_bufs(ProblemBufs& pb)
     pb = ProblemBufs{};
 }
 
-static int ensure_scratch(mdot_ctx* ctx, int n)
+static int ensure_scratch(mdot_ctx* ctx, int m, int n)
 {
-    const size_t scr = std::max<size_t>(kConvBlocks, 2 * (size_t)tiles_r(n) * tiles_c(n));
+    const size_t scr = std::max<size_t>(kConvBlocks, 2 * (size_t)tiles_r(m) * tiles_c(n));
     if (scr <= ctx->scratch_doubles) return MDOT_OK;
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
     if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
@@ -217,24 +220,25 @@ static int ensure_scratch(mdot_ctx* ctx, int n)
     return MDOT_OK;
 }
 
-// Make pb hold a workspace for size n (reallocating when it is too small).
-static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n, hipStream_t stream)
+// Make pb hold a workspace for m rows and n columns (reallocating when it is too small).
+static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int m, int n, hipStream_t stream)
 {
     if (!pb.d_work) {
         HIPCHK(ctx, hipMalloc(&pb.d_work, sizeof(Control)));
         pb.d_prm = &reinterpret_cast<Control*>(pb.d_work)->prm;
     }
-    if (n <= pb.cap_n && pb.ws) return ensure_scratch(ctx, n);
-    const size_t need = workspace_bytes(n);
+    const size_t need = workspace_bytes(m, n);
+    if (pb.ws && need <= pb.ws_bytes) return ensure_scratch(ctx, m, n);
     if (pb.ws) {
         (void)hipFree(pb.ws);
         pb.ws = nullptr;
+        pb.ws_bytes = 0;
         pb.cap_n = 0;
     }
     if (ctx->graph) {  // the captured graph may reference the old sizes
         (void)hipGraphExecDestroy(ctx->graph);
         ctx->graph = nullptr;
-        ctx->graph_n = 0;
+        ctx->graph_m = ctx->graph_n = 0;
     }
     hipError_t e = hipMalloc(&pb.ws, need);
     if (e != hipSuccess) {
@@ -242,9 +246,9 @@ static int ensure_workspace(mdot_ctx* ctx, ProblemBufs& pb, int n, hipStream_t s
         return fail(ctx, MDOT_E_NOMEM, "hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
     }
     pb.ws_bytes = need;
-    pb.cap_n = n;
+    pb.cap_n = std::max(m, n);
     HIPCHK(ctx, hipMemsetAsync(pb.ws, 0, need, stream));
-    return ensure_scratch(ctx, n);
+    return ensure_scratch(ctx, m, n);
 }
 
 // Names of the base cost codes in the tuning file (the order of CostCode in the kernels).
@@ -321,30 +325,32 @@ static void pick_variant(const mdot_ctx* ctx, int code, int n, int* occ2, int* s
     *stage_min_tiles = st;
 }
 
-// Lay the Work struct out over pb's workspace for size n (n <= cap_n) and upload it.
-static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int n, const mdot_cost_desc* cost, double scale,
+// Lay the Work struct out over pb's workspace for m rows and n columns (the workspace holds at
+// least workspace_bytes(m, n)) and upload it.
+static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int m, int n, const mdot_cost_desc* cost, double scale,
                      const double* r, const double* c, hipStream_t stream)
 {
     size_t off[32];
-    workspace_bytes(n, off);
+    workspace_bytes(m, n, off);
     char* b = (char*)pb.ws;
     Work& w = pb.host_work;
     memset(&w, 0, sizeof w);
+    w.m = m;
     w.n = n;
-    w.nrt = tiles_r(n);
+    w.nrt = tiles_r(m);
     w.nct = tiles_c(n);
-    w.fin_L = fin_lanes(n);
-    w.fin_per = fin_per(n);
+    w.fin_L = fin_lanes(m, n);
+    w.fin_per = fin_per(m, n);
     w.fin_lgL = 0;
     while ((1 << w.fin_lgL) < w.fin_L) ++w.fin_lgL;
-    w.fin_nvb = fin_vblocks(n);
-    w.fin_nblk = fin_grid(n);
+    w.fin_nvb = fin_vblocks(m, n);
+    w.fin_nblk = fin_grid(m, n);
     w.cost_kind = cost ? cost->kind : MDOT_COST_DENSE;
     w.dtype = cost ? cost->dtype : MDOT_DT_F32;
     w.d = cost ? cost->d : 0;
     {
         const int cc = cost_code_of(w.cost_kind, w.dtype);
-        pick_variant(ctx, cost_code_dim(cc, w.d), n, &w.occ2, &w.stage_min_tiles);
+        pick_variant(ctx, cost_code_dim(cc, w.d), std::max(m, n), &w.occ2, &w.stage_min_tiles);
     }
     w.cost = cost ? cost->data : nullptr;
     w.scale = scale;
@@ -393,6 +399,8 @@ static int check_cost_desc(mdot_ctx* ctx, const mdot_cost_desc* cost)
 {
     if (!cost || !cost->data) return fail(ctx, MDOT_E_ARG, "cost descriptor or its data is NULL");
     if (cost->n < 1 || cost->n > kMaxN) return fail(ctx, MDOT_E_ARG, "n=%d outside [1, %d]", cost->n, kMaxN);
+    if (cost->m < 0 || cost->m > kMaxN) return fail(ctx, MDOT_E_ARG, "m=%d outside [0, %d]", cost->m, kMaxN);
+    if (cost->reserved != 0) return fail(ctx, MDOT_E_ARG, "reserved field of the cost descriptor is not 0");
     if (cost->kind != MDOT_COST_DENSE && cost->kind != MDOT_COST_POINTS_SQEUCLID && cost->kind != MDOT_COST_POINTS_L1)
         return fail(ctx, MDOT_E_ARG, "unknown cost kind %d", (int)cost->kind);
     if (cost->kind == MDOT_COST_DENSE && (cost->dtype < MDOT_DT_F64 || cost->dtype > MDOT_DT_BF16))
@@ -429,8 +437,7 @@ static int check_params(mdot_ctx* ctx, const mdot_params& prm, double target_gap
 static int resolve_scale(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, double* scale_out,
                          hipStream_t stream, double* dpart = nullptr)
 {
-    const int n = cost->n;
-    const int tiles = tiles_r(n) * tiles_c(n);
+    const int tiles = tiles_r(rows_of(cost)) * tiles_c(cost->n);
     if (!dpart) dpart = ctx->d_scratch;
     if (launch_cost_range(pb.host_work, pb.d_work, dpart, stream))
         return fail(ctx, MDOT_E_DEVICE, "cost range kernel launch failed");
@@ -454,14 +461,14 @@ static int resolve_scale(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
     return MDOT_OK;
 }
 
-static int intake_marginals(mdot_ctx* ctx, ProblemBufs& pb, int n, double* hmin, hipStream_t stream)
+static int intake_marginals(mdot_ctx* ctx, ProblemBufs& pb, int m, int n, double* hmin, hipStream_t stream)
 {
     if (launch_intake(pb.d_work, ctx->d_scratch, stream))
         return fail(ctx, MDOT_E_DEVICE, "intake kernel launch failed");
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_scratch, ctx->d_scratch, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHK(ctx, hipStreamSynchronize(stream));
     const double* s = ctx->h_scratch;
-    const double tol = 1e-9 * n;
+    const double tol = 1e-9 * std::max(m, n);
     if (s[6] > 0) return fail(ctx, MDOT_E_MARGINAL, "marginals contain non-finite values");
     if (s[2] < 0 || s[3] < 0) return fail(ctx, MDOT_E_MARGINAL, "marginals contain negative values");
     if (std::fabs(s[0] - 1.0) > tol || std::fabs(s[1] - 1.0) > tol)
@@ -476,20 +483,20 @@ static int intake_marginals(mdot_ctx* ctx, ProblemBufs& pb, int n, double* hmin,
 static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* cost, const double* r,
                          const double* c, double target_gap, const mdot_params& prm, hipStream_t stream)
 {
-    const int n = cost->n;
-    int rc = ensure_workspace(ctx, pb, n, stream);
+    const int m = rows_of(cost), n = cost->n;
+    int rc = ensure_workspace(ctx, pb, m, n, stream);
     if (rc) return rc;
-    rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c, stream);
+    rc = bind_work(ctx, pb, m, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c, stream);
     if (rc) return rc;
     double scale;
     rc = resolve_scale(ctx, pb, cost, &scale, stream);
     if (rc) return rc;
     if (scale != pb.host_work.scale) {
-        rc = bind_work(ctx, pb, n, cost, scale, r, c, stream);
+        rc = bind_work(ctx, pb, m, n, cost, scale, r, c, stream);
         if (rc) return rc;
     }
     double hmin;
-    rc = intake_marginals(ctx, pb, n, &hmin, stream);
+    rc = intake_marginals(ctx, pb, m, n, &hmin, stream);
     if (rc) return rc;
     const bool adaptive = !(prm.gamma_f > 0.0);
     DevParams& P = *ctx->h_prm;
@@ -504,7 +511,8 @@ static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
     P.c1 = prm.ls_c1;
     P.c2 = prm.ls_c2;
     P.hmin = hmin;
-    P.hterm = prm.tol_log_n ? std::log((double)n) : hmin;  // App. C variant: log n in eps_d
+    // App. C variant: log n in eps_d (log min(m, n), the upper bound of H_min, when m != n)
+    P.hterm = prm.tol_log_n ? std::log((double)std::min(m, n)) : hmin;
     P.smooth_fixed = prm.smoothing == 1;
     P.w_fixed = std::min(P.hterm / std::pow(P.gamma_f, prm.p) / 4.0, 0.5);  // App. D: the final stage's weight
     P.projector = prm.projector;
@@ -521,7 +529,7 @@ static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
         // FP16 copy of the cost and its largest rounding error delta; stages with
         // gamma * scale * delta <= mixed_switch run on the copy, and at least the last stage
         // before gamma_f runs on the exact cost
-        const size_t count = (size_t)n * n;
+        const size_t count = (size_t)m * n;
         if (pb.proxy_bytes < count * 2) {
             if (pb.proxy) (void)hipFree(pb.proxy);
             pb.proxy = nullptr;
@@ -548,7 +556,7 @@ static int setup_problem(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc* c
         proxy.dtype = MDOT_DT_F16;
         proxy.data = pb.proxy;
         const double scale = pb.host_work.scale;
-        rc = bind_work(ctx, pb, n, &proxy, scale, r, c, stream);
+        rc = bind_work(ctx, pb, m, n, &proxy, scale, r, c, stream);
         if (rc) return rc;
     }
     // the pinned parameter block is reused by the next intake: let this copy land first
@@ -580,11 +588,11 @@ static void fill_result(const State& S, double seconds, mdot_result* res)
     res->tilde_iters = S.tilde_iters;
 }
 
-static int ensure_graph(mdot_ctx* ctx, int n)
+static int ensure_graph(mdot_ctx* ctx)
 {
     const Work& hw = ctx->main.host_work;
     const int code = cost_code(hw);
-    if (ctx->graph && ctx->graph_n == n && ctx->graph_code == code) return MDOT_OK;
+    if (ctx->graph && ctx->graph_m == hw.m && ctx->graph_n == hw.n && ctx->graph_code == code) return MDOT_OK;
     if (ctx->graph) {
         (void)hipGraphExecDestroy(ctx->graph);
         ctx->graph = nullptr;
@@ -605,15 +613,16 @@ static int ensure_graph(mdot_ctx* ctx, int n)
         ctx->graph = nullptr;
         return fail(ctx, MDOT_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
     }
-    ctx->graph_n = n;
+    ctx->graph_m = hw.m;
+    ctx->graph_n = hw.n;
     ctx->graph_code = code;
     return MDOT_OK;
 }
 
 // Run solver steps of `main` until the device sets done (or max_chunks chunks have run).
-static int run_steps(mdot_ctx* ctx, int n, int max_chunks)
+static int run_steps(mdot_ctx* ctx, int max_chunks)
 {
-    int rc = ensure_graph(ctx, n);
+    int rc = ensure_graph(ctx);
     if (rc) return rc;
     // slot 0 holds the newest state after an even chunk; the graph's last kernel copies its
     // done flag to h_done[chunk number & 1]
@@ -660,7 +669,7 @@ static int rebuild_batch(mdot_ctx* ctx)
         hw[m] = &sl.pb.host_work;
         B.items[m] = sl.pb.d_work;
         B.fin_prefix[m] = nf;
-        nf += fin_grid(sl.pb.host_work.n);
+        nf += sl.pb.host_work.fin_nblk;
         ++m;
     }
     B.nitems = m;
@@ -677,7 +686,8 @@ static int rebuild_batch(mdot_ctx* ctx)
         for (int b = a; b < m; ++b) {
             const Work& x = *hw[a];
             const Work& y = *hw[b];
-            if (y.cost == x.cost && y.n == x.n && y.d == x.d && y.cost_kind == x.cost_kind && y.dtype == x.dtype)
+            if (y.cost == x.cost && y.m == x.m && y.n == x.n && y.d == x.d && y.cost_kind == x.cost_kind &&
+                y.dtype == x.dtype)
                 taken[b] = true;
         }
         const int code = cost_code(*hw[a]);  // includes the tuned occupancy variant
@@ -704,7 +714,8 @@ static int rebuild_batch(mdot_ctx* ctx)
             int K = 0;
             for (int b = gfirst[q]; b < m; ++b) {
                 const Work& y = *hw[b];
-                if (y.cost != x.cost || y.n != x.n || y.d != x.d || y.cost_kind != x.cost_kind || y.dtype != x.dtype)
+                if (y.cost != x.cost || y.m != x.m || y.n != x.n || y.d != x.d || y.cost_kind != x.cost_kind ||
+                    y.dtype != x.dtype)
                     continue;
                 B.grp_items[ne++] = b;
                 ++K;
@@ -791,7 +802,7 @@ static void pool_put(mdot_ctx* ctx, const ProblemBufs& pb)
     // keep the pool bounded: free the smallest buffers beyond kMaxBatch entries
     while (ctx->pool.size() > (size_t)kMaxBatch) {
         auto it = std::min_element(ctx->pool.begin(), ctx->pool.end(),
-                                   [](const ProblemBufs& a, const ProblemBufs& b) { return a.cap_n < b.cap_n; });
+                                   [](const ProblemBufs& a, const ProblemBufs& b) { return a.ws_bytes < b.ws_bytes; });
         free_bufs(*it);
         ctx->pool.erase(it);
     }
@@ -883,7 +894,7 @@ int mdot_tune_variant(mdot_ctx* ctx, const mdot_cost_desc* cost, int* occ, int* 
     if (rc) return rc;
     const int cc = cost_code_of(cost->kind, cost->dtype);
     int o2 = 0;
-    pick_variant(ctx, cost->kind != MDOT_COST_DENSE ? cost_code_dim(cc, cost->d) : cc, cost->n, &o2,
+    pick_variant(ctx, cost->kind != MDOT_COST_DENSE ? cost_code_dim(cc, cost->d) : cc, std::max(rows_of(cost), cost->n), &o2,
                  stage_min_tiles);
     *occ = o2 ? 2 : 4;
     return MDOT_OK;
@@ -929,7 +940,7 @@ int mdot_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, mdot_
     void* fixed = nullptr;
     if (ok) ok = noalloc_scratch(device, &fixed) == 0 && fixed != nullptr;
     if (ok) ctx->d_fixed = static_cast<unsigned char*>(fixed);
-    if (ok) ok = ensure_scratch(ctx, kNoAllocMaxN) == MDOT_OK;
+    if (ok) ok = ensure_scratch(ctx, kNoAllocMaxN, kNoAllocMaxN) == MDOT_OK;
     if (!ok) {
         mdot_ctx_destroy(ctx);
         return MDOT_E_DEVICE;
@@ -992,16 +1003,16 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
     rc = check_params(ctx, prm, target_gap);
     if (rc) return rc;
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    const int n = cost->n;
+    const int m = rows_of(cost), n = cost->n;
     // the single-problem buffers plus MIXED's FP16 copy, beside what the serving engine holds
-    const size_t need = problem_footprint(n) + (prm.precision == MDOT_PREC_MIXED ? (size_t)n * n * 2 : 0);
+    const size_t need = problem_footprint(m, n) + (prm.precision == MDOT_PREC_MIXED ? (size_t)m * n * 2 : 0);
     if (ctx->budget && need + ctx->bytes_in_use > ctx->budget) {
         for (auto& pb : ctx->pool) free_bufs(pb);  // idle engine buffers go first
         ctx->pool.clear();
     }
     if (ctx->budget && need + ctx->bytes_in_use > ctx->budget)
-        return fail(ctx, MDOT_E_NOMEM, "n=%d needs %zu bytes, budget %zu has %zu in use", n, need, ctx->budget,
-                    ctx->bytes_in_use);
+        return fail(ctx, MDOT_E_NOMEM, "m=%d n=%d needs %zu bytes, budget %zu has %zu in use", m, n, need,
+                    ctx->budget, ctx->bytes_in_use);
     if (prm.precision == MDOT_PREC_MIXED &&
         (cost->kind != MDOT_COST_DENSE || (cost->dtype != MDOT_DT_F32 && cost->dtype != MDOT_DT_F64)))
         return fail(ctx, MDOT_E_ARG, "MIXED needs a dense FP32 or FP64 cost");
@@ -1011,18 +1022,18 @@ int mdot_solve(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, const
     // hard cap on steps: every LSE sweep is one step, each stage adds at most a few more
     const int64_t max_steps = prm.max_sweeps > 0 ? 4 * prm.max_sweeps + 4096 : (int64_t)1 << 22;
     const int max_chunks = (int)std::min<int64_t>(max_steps / kChunk + 1, 1 << 30);
-    rc = run_steps(ctx, n, max_chunks);
+    rc = run_steps(ctx, max_chunks);
     if (rc) return rc;
     if (ctx->main.host_work.dtype != cost->dtype) {  // MIXED: paused at the switch to the exact cost
         rc = read_state(ctx, ctx->main);
         if (rc) return rc;
         if (ctx->h_state->done == 2) {
-            rc = bind_work(ctx, ctx->main, n, cost, ctx->main.host_work.scale, r, c, ctx->stream);
+            rc = bind_work(ctx, ctx->main, m, n, cost, ctx->main.host_work.scale, r, c, ctx->stream);
             if (rc) return rc;
             static const int32_t kResume = 0;
             HIPCHK(ctx, hipMemcpyAsync(&ctx->main.host_work.st[0].done, &kResume, sizeof kResume,
                                        hipMemcpyHostToDevice, ctx->stream));
-            rc = run_steps(ctx, n, max_chunks);
+            rc = run_steps(ctx, max_chunks);
             if (rc) return rc;
         }
     }
@@ -1047,34 +1058,34 @@ static int standalone_setup(mdot_ctx* ctx, ProblemBufs& pb, const mdot_cost_desc
                             const double* u_prev, const double* v_prev, double gamma_prev, const double* r,
                             const double* c, double* dpart = nullptr)
 {
-    const int n = cost->n;
+    const int m = rows_of(cost), n = cost->n;
     if (!pb.borrowed) {
-        int rc = ensure_workspace(ctx, pb, n, ctx->stream);
+        int rc = ensure_workspace(ctx, pb, m, n, ctx->stream);
         if (rc) return rc;
     }
-    int rc = bind_work(ctx, pb, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c, ctx->stream);
+    int rc = bind_work(ctx, pb, m, n, cost, cost->scale > 0 ? cost->scale : 1.0, r, c, ctx->stream);
     if (rc) return rc;
     double scale;
     rc = resolve_scale(ctx, pb, cost, &scale, ctx->stream, dpart);
     if (rc) return rc;
     if (scale != pb.host_work.scale) {
-        rc = bind_work(ctx, pb, n, cost, scale, r, c, ctx->stream);
+        rc = bind_work(ctx, pb, m, n, cost, scale, r, c, ctx->stream);
         if (rc) return rc;
     }
     const Work& w = pb.host_work;
     // rt .. lzt and the n-vectors xr, yc, errc (the vectors these sweeps read besides z and lz)
     // start at zero: a fill kernel, since the static array keeps the previous call's contents
     size_t off[kWsBuffers + 1];
-    workspace_bytes(n, off);
+    workspace_bytes(m, n, off);
     if (launch_fill(w.rt, off[12] / sizeof(double), 0.0, ctx->stream))
         return fail(ctx, MDOT_E_DEVICE, "fill launch failed");
-    HIPCHK(ctx, hipMemcpyAsync(w.z, u, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(w.z + n, v, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    if (shift) HIPCHK(ctx, hipMemcpyAsync(w.lz, shift, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(w.z, u, m * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(w.z + m, v, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    if (shift) HIPCHK(ctx, hipMemcpyAsync(w.lz, shift, m * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     const bool ext = u_prev && v_prev && gamma > gamma_prev;
     if (ext) {
-        HIPCHK(ctx, hipMemcpyAsync(w.zprev, u_prev, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-        HIPCHK(ctx, hipMemcpyAsync(w.zprev + n, v_prev, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(w.zprev, u_prev, m * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(w.zprev + m, v_prev, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     }
     DevParams& P = *ctx->h_prm;
     memset(&P, 0, sizeof P);
@@ -1111,15 +1122,15 @@ int mdot_lse2(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u, const 
     rc = standalone_setup(ctx, ctx->main, cost, u, v, gamma, shift, precision == MDOT_PREC_F64, 1, nullptr, nullptr, 0.0, nullptr,
                           nullptr);
     if (rc) return rc;
-    rc = run_steps(ctx, cost->n, 1);
+    rc = run_steps(ctx, 1);
     if (rc) return rc;
     rc = read_state(ctx, ctx->main);
     if (rc) return rc;
     if (!ctx->h_state->done) return fail(ctx, MDOT_E_DEVICE, "standalone sweep did not finish");
     const Work& w = ctx->main.host_work;
-    const int n = cost->n;
-    HIPCHK(ctx, hipMemcpyAsync(lr_out, w.lzt, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(lc_out, w.lzt + n, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    const int m = rows_of(cost), n = cost->n;
+    HIPCHK(ctx, hipMemcpyAsync(lr_out, w.lzt, m * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(lc_out, w.lzt + m, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return ctx->h_state->status;
 }
@@ -1130,9 +1141,9 @@ int mdot_lse2_noalloc(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u
     if (!ctx) return MDOT_E_ARG;
     int rc = check_cost_desc(ctx, cost);
     if (rc) return rc;
-    if (cost->n > kNoAllocMaxN)
-        return fail(ctx, MDOT_E_ARG, "mdot_lse2_noalloc: n=%d exceeds its maximum n=%d (MDOT_NOALLOC_MAX_N)", cost->n,
-                    kNoAllocMaxN);
+    if (cost->n > kNoAllocMaxN || rows_of(cost) > kNoAllocMaxN)
+        return fail(ctx, MDOT_E_ARG, "mdot_lse2_noalloc: m=%d n=%d exceeds its maximum %d (MDOT_NOALLOC_MAX_N)",
+                    rows_of(cost), cost->n, kNoAllocMaxN);
     if (!u || !v || !lr_out || !lc_out) return fail(ctx, MDOT_E_ARG, "NULL vector pointer");
     if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(ctx, MDOT_E_ARG, "bad gamma %g", gamma);
     if (precision != MDOT_PREC_F32 && precision != MDOT_PREC_F64) return fail(ctx, MDOT_E_ARG, "bad precision");
@@ -1143,9 +1154,10 @@ int mdot_lse2_noalloc(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u
     pb.d_work = reinterpret_cast<Work*>(ctx->d_fixed);
     pb.d_prm = &reinterpret_cast<Control*>(ctx->d_fixed)->prm;
     pb.ws = ctx->d_fixed + kNoAllocCtl;
-    pb.ws_bytes = workspace_bytes(cost->n);
+    pb.ws_bytes = workspace_bytes(rows_of(cost), cost->n);
     pb.cap_n = kNoAllocMaxN;
-    double* dpart = reinterpret_cast<double*>(ctx->d_fixed + kNoAllocCtl + ws_offset(kWsBuffers, kNoAllocMaxN));
+    double* dpart =
+        reinterpret_cast<double*>(ctx->d_fixed + kNoAllocCtl + ws_offset(kWsBuffers, kNoAllocMaxN, kNoAllocMaxN));
     rc = standalone_setup(ctx, pb, cost, u, v, gamma, shift, precision == MDOT_PREC_F64, 1, nullptr, nullptr, 0.0,
                           nullptr, nullptr, dpart);
     if (rc) return rc;
@@ -1157,9 +1169,9 @@ int mdot_lse2_noalloc(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u
     rc = read_state(ctx, pb);
     if (rc) return rc;
     if (!ctx->h_state->done) return fail(ctx, MDOT_E_DEVICE, "standalone sweep did not finish");
-    const int n = cost->n;
-    HIPCHK(ctx, hipMemcpyAsync(lr_out, w.lzt, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(lc_out, w.lzt + n, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    const int m = rows_of(cost), n = cost->n;
+    HIPCHK(ctx, hipMemcpyAsync(lr_out, w.lzt, m * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(lc_out, w.lzt + m, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return ctx->h_state->status;
 }
@@ -1176,7 +1188,7 @@ int mdot_round_certify(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* 
     HIPCHK(ctx, hipSetDevice(ctx->device));
     rc = standalone_setup(ctx, ctx->main, cost, u, v, gamma, nullptr, 1, 2, u_prev, v_prev, gamma_prev, r, c);
     if (rc) return rc;
-    rc = run_steps(ctx, cost->n, 1);
+    rc = run_steps(ctx, 1);
     if (rc) return rc;
     rc = read_state(ctx, ctx->main);
     if (rc) return rc;
@@ -1200,11 +1212,11 @@ int mdot_bench_sweep(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* u,
     // exact log-sums first (max pass + LSE pass) so the timed sweeps run with converged shifts
     rc = standalone_setup(ctx, ctx->main, cost, u, v, gamma, nullptr, exp64, 1, nullptr, nullptr, 0.0, nullptr, nullptr);
     if (rc) return rc;
-    rc = run_steps(ctx, cost->n, 1);
+    rc = run_steps(ctx, 1);
     if (rc) return rc;
     const Work& w = ctx->main.host_work;
-    const int n = cost->n;
-    HIPCHK(ctx, hipMemcpyAsync(w.lz, w.lzt, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    const int mn = rows_of(cost) + cost->n;
+    HIPCHK(ctx, hipMemcpyAsync(w.lz, w.lzt, mn * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     State& S = *ctx->h_state;
     HIPCHK(ctx, hipMemcpyAsync(&S, w.st, sizeof S, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1243,11 +1255,11 @@ int mdot_bench_sweep_flushed(mdot_ctx* ctx, const mdot_cost_desc* cost, const do
     const int exp64 = precision == MDOT_PREC_F64;
     rc = standalone_setup(ctx, ctx->main, cost, u, v, gamma, nullptr, exp64, 1, nullptr, nullptr, 0.0, nullptr, nullptr);
     if (rc) return rc;
-    rc = run_steps(ctx, cost->n, 1);
+    rc = run_steps(ctx, 1);
     if (rc) return rc;
     const Work& w = ctx->main.host_work;
-    const int n = cost->n;
-    HIPCHK(ctx, hipMemcpyAsync(w.lz, w.lzt, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    const int mn = rows_of(cost) + cost->n;
+    HIPCHK(ctx, hipMemcpyAsync(w.lz, w.lzt, mn * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     State& S = *ctx->h_state;
     HIPCHK(ctx, hipMemcpyAsync(&S, w.st, sizeof S, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1316,12 +1328,13 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
         (cost->kind != MDOT_COST_DENSE || (cost->dtype != MDOT_DT_F32 && cost->dtype != MDOT_DT_F64)))
         return fail(ctx, MDOT_E_ARG, "MIXED needs a dense FP32 or FP64 cost");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    const int n = cost->n;
+    const int m = rows_of(cost), n = cost->n;
     const bool mixed = prm.precision == MDOT_PREC_MIXED;
-    const size_t proxy_need = mixed ? (size_t)n * n * 2 : 0;  // MIXED also holds an FP16 copy of the cost
-    const size_t fp = problem_footprint(n) + proxy_need;
+    const size_t proxy_need = mixed ? (size_t)m * n * 2 : 0;  // MIXED also holds an FP16 copy of the cost
+    const size_t ws_need = workspace_bytes(m, n);
+    const size_t fp = problem_footprint(m, n) + proxy_need;
     if (ctx->budget && fp > ctx->budget)
-        return fail(ctx, MDOT_E_NOMEM, "n=%d needs %zu bytes > budget %zu", n, fp, ctx->budget);
+        return fail(ctx, MDOT_E_NOMEM, "m=%d n=%d needs %zu bytes > budget %zu", m, n, fp, ctx->budget);
     rc = collect_retired(ctx, false, nullptr);  // finished retirements return their buffers first
     if (rc) return rc;
     int active = 0;
@@ -1332,7 +1345,8 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
     auto pick = [&]() {
         int best = -1;
         for (int k = 0; k < (int)ctx->pool.size(); ++k)
-            if (ctx->pool[k].cap_n >= n && (best < 0 || ctx->pool[k].cap_n < ctx->pool[best].cap_n)) best = k;
+            if (ctx->pool[k].ws_bytes >= ws_need && (best < 0 || ctx->pool[k].ws_bytes < ctx->pool[best].ws_bytes))
+                best = k;
         return best;
     };
     auto held_after = [&](int cand) {
@@ -1356,8 +1370,8 @@ int mdot_submit(mdot_ctx* ctx, const mdot_cost_desc* cost, const double* r, cons
             best = -1;
         }
         if (held_after(best) > ctx->budget)
-            return fail(ctx, MDOT_E_BUSY, "HBM budget: %zu of %zu bytes in use, n=%d needs %zu", ctx->bytes_in_use,
-                        ctx->budget, n, fp);
+            return fail(ctx, MDOT_E_BUSY, "HBM budget: %zu of %zu bytes in use, m=%d n=%d needs %zu",
+                        ctx->bytes_in_use, ctx->budget, m, n, fp);
     }
     int s = 0;
     while (ctx->slots[s].used) ++s;
@@ -1402,7 +1416,8 @@ static int process_chunk(mdot_ctx* ctx, int buf)
         if (done[m] == 2) {  // MIXED: paused at the switch to the exact cost
             // the chunk launched before the resume below still reports the pause: skip it
             if (ctx->chunk_seq[buf] <= sl.resumed_at) continue;
-            int rc = bind_work(ctx, sl.pb, sl.exact.n, &sl.exact, sl.pb.host_work.scale, sl.r, sl.c, ctx->stream);
+            int rc = bind_work(ctx, sl.pb, rows_of(&sl.exact), sl.exact.n, &sl.exact, sl.pb.host_work.scale, sl.r, sl.c,
+                               ctx->stream);
             if (rc) return rc;
             // chunks have an even number of steps, so the next step reads state slot 0
             static const int32_t kResume = 0;

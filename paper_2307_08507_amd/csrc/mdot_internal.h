@@ -15,24 +15,25 @@ constexpr int kRPW = 16;
 constexpr int kBR = 4 * kRPW;
 constexpr int kVecWG = 256;
 
-// Finalize kernel geometry: the tile partials of each 2n-vector entry are combined by a group of
-// L lanes (a power of two, at most 64) that each fold up to fin_per(n) of them; the groups fill
-// fin_vblocks(n) virtual workgroups, run on fin_grid(n) workgroups. Depends on n only, so the
-// summation order of every entry is fixed by n. Past n = 8192 each lane takes 32 partials, so
-// that the groups fit in kFinMaxGrid workgroups without a second round (n = 16384: L = 8,
-// 1024 workgroups; with 8 per lane it would be L = 32 and four rounds).
+// Finalize kernel geometry: the tile partials of each entry of the (m + n)-vectors (rows, then
+// columns) are combined by a group of L lanes (a power of two, at most 64) that each fold up to
+// fin_per(m, n) of them; the groups fill fin_vblocks(m, n) virtual workgroups, run on
+// fin_grid(m, n) workgroups. Depends on the sizes only, so the summation order of every entry is
+// fixed by them. Past 8192 rows or columns each lane takes 32 partials, so that the groups fit in
+// kFinMaxGrid workgroups without a second round (n = 16384: L = 8, 1024 workgroups; with 8 per
+// lane it would be L = 32 and four rounds).
 constexpr int kFinMaxGrid = 1024;
-constexpr int fin_per(int n) { return n > 8192 ? 32 : 8; }
-constexpr int fin_lanes(int n)
+constexpr int fin_per(int m, int n) { return (m > n ? m : n) > 8192 ? 32 : 8; }
+constexpr int fin_lanes(int m, int n)
 {
-    const int nrt = (n + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
-    const int m = nrt > nct ? nrt : nct;
+    const int nrt = (m + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
+    const int q = nrt > nct ? nrt : nct;
     int L = 1;
-    while (L < 64 && L * fin_per(n) < m) L <<= 1;
+    while (L < 64 && L * fin_per(m, n) < q) L <<= 1;
     return L;
 }
-constexpr int fin_vblocks(int n) { return (2 * n * fin_lanes(n) + kVecWG - 1) / kVecWG; }
-constexpr int fin_grid(int n) { return fin_vblocks(n) < kFinMaxGrid ? fin_vblocks(n) : kFinMaxGrid; }
+constexpr int fin_vblocks(int m, int n) { return ((m + n) * fin_lanes(m, n) + kVecWG - 1) / kVecWG; }
+constexpr int fin_grid(int m, int n) { return fin_vblocks(m, n) < kFinMaxGrid ? fin_vblocks(m, n) : kFinMaxGrid; }
 
 // What the next sweep does.
 enum SweepMode : int32_t { SM_NONE = 0, SM_LSE = 1, SM_R1 = 2, SM_R2 = 3, SM_MAX = 4 };
@@ -114,11 +115,12 @@ struct State {
     int64_t stall_k, prec_switches, proxy_stages, tilde_iters;
 };
 
-// Device buffers of one problem (all FP64 unless noted). 2n-vectors hold rows then columns.
+// Device buffers of one problem (all FP64 unless noted). (m + n)-vectors hold the m rows, then
+// the n columns: entry k < m is row k, entry m + j is column j.
 struct Work {
-    int32_t n, nrt, nct;     // size, row tiles, column tiles
-    int32_t cost_kind, dtype, d, fin_per;  // cost kind and dtype, point dimension, fin_per(n)
-    int32_t fin_L, fin_lgL, fin_nvb, fin_nblk;  // fin_lanes(n), log2 of it, fin_vblocks(n), fin_grid(n)
+    int32_t m, n, nrt, nct;  // rows (sources, r), columns (targets, c), row tiles, column tiles
+    int32_t cost_kind, dtype, d, fin_per;  // cost kind and dtype, point dimension, fin_per(m, n)
+    int32_t fin_L, fin_lgL, fin_nvb, fin_nblk;  // fin_lanes(m, n), log2 of it, fin_vblocks(m, n), fin_grid(m, n)
     // launch variant from the tuning table (neither changes any arithmetic): occ2 = 1 runs the
     // sweep instance capped at 2 waves per SIMD (256 VGPRs) instead of 4 (128 VGPRs); FP32 sweeps
     // of more than stage_min_tiles tiles stage their second row batch in LDS
@@ -127,29 +129,29 @@ struct Work {
     double scale;            // C = scale * raw
     const double* r;         // original marginals
     const double* c;
-    double* rt;        // [2n] smoothed marginals r~, c~
-    double* logt;      // [2n] log r~, log c~
-    double* z;         // [2n] u, v
-    double* zprev;     // [2n] previous-stage solution
-    double* zbest;     // [2n] potentials of the best UB stage
-    double* p;         // [2n] search direction
-    double* g;         // [2n] gradient at z
-    double* lz;        // [2n] log r(P), log c(P) at z (or a prediction)
-    double* lzt;       // [2n] at the current trial
-    double* xr;        // [n]  Round row factors x
+    double* rt;        // [m+n] smoothed marginals r~, c~
+    double* logt;      // [m+n] log r~, log c~
+    double* z;         // [m+n] u, v
+    double* zprev;     // [m+n] previous-stage solution
+    double* zbest;     // [m+n] potentials of the best UB stage
+    double* p;         // [m+n] search direction
+    double* g;         // [m+n] gradient at z
+    double* lz;        // [m+n] log r(P), log c(P) at z (or a prediction)
+    double* lzt;       // [m+n] at the current trial
+    double* xr;        // [m]  Round row factors x
     double* yc;        // [n]  Round column factors y
     double* errc;      // [n]  err_c
-    double* gp;        // [2n] g' (two variants) from R1
-    double* fpp;       // [2n] f'' (two variants) from R1
-    double* rowpart;   // [nct * n]    per-tile row partials
-    double* colpart;   // [nrt * n]    per-tile column partials
-    double* rowpart2;  // [nct * n]    second row partial (R2)
-    double* rowpart3;  // [nct * n]    third row partial (R2)
-    double* rowmin;    // [2 * nct * n] per-tile row minima (two variants)
+    double* gp;        // [2n] g' (two variants, n apart) from R1
+    double* fpp;       // [2m] f'' (two variants, m apart) from R1
+    double* rowpart;   // [nct * m]    per-tile row partials (column tile J, row i at J m + i)
+    double* colpart;   // [nrt * n]    per-tile column partials (row tile I, column j at I n + j)
+    double* rowpart2;  // [nct * m]    second row partial (R2)
+    double* rowpart3;  // [nct * m]    third row partial (R2)
+    double* rowmin;    // [2 * nct * m] per-tile row minima (two variants)
     double* colmin;    // [2 * nrt * n] per-tile column minima
     double* tshift;    // [nrt] per-row-tile column shift S_I
-    double* sdt;       // [2n] diagonal-Hessian direction s~ at the current trial (precond variant)
-    double* bdots;     // [fin_grid(n) * kNDot] per-workgroup dot products (in the control block)
+    double* sdt;       // [m+n] diagonal-Hessian direction s~ at the current trial (precond variant)
+    double* bdots;     // [fin_grid(m, n) * kNDot] per-workgroup dot products (in the control block)
     State* st;         // [2] state slots: step k reads slot k % 2, its decide kernel writes the other
     DevParams* prm;
 };
@@ -196,38 +198,41 @@ struct BatchDesc {
 };
 
 // Workspace layout of one problem (the vectors of Work, in the order bind_work assigns them):
-// FP64 counts per buffer, each buffer rounded up to 256 bytes.
+// FP64 counts per buffer for m rows and n columns, each buffer rounded up to 256 bytes.
 constexpr int kWsBuffers = 22;
-constexpr size_t ws_count(int b, size_t n)
+constexpr size_t ws_count(int b, size_t m, size_t n)
 {
-    const size_t nrt = (n + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
-    return b < 9 ? 2 * n                      // rt logt z zprev zbest p g lz lzt
-         : b < 12 ? n                         // xr yc errc
-         : b < 14 ? 2 * n                     // gp fpp
-         : b == 14 || b == 16 || b == 17 ? nct * n  // rowpart rowpart2 rowpart3
+    const size_t nrt = (m + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
+    return b < 9 ? m + n                      // rt logt z zprev zbest p g lz lzt
+         : b == 9 ? m                         // xr
+         : b < 12 ? n                         // yc errc
+         : b == 12 ? 2 * n                    // gp
+         : b == 13 ? 2 * m                    // fpp
+         : b == 14 || b == 16 || b == 17 ? nct * m  // rowpart rowpart2 rowpart3
          : b == 15 ? nrt * n                  // colpart
-         : b == 18 ? 2 * nct * n              // rowmin
+         : b == 18 ? 2 * nct * m              // rowmin
          : b == 19 ? 2 * nrt * n              // colmin
          : b == 20 ? nrt                      // tshift
-         : 2 * n;                             // sdt
+         : m + n;                             // sdt
 }
 constexpr size_t ws_round(size_t bytes) { return (bytes + 255) / 256 * 256; }
 // Byte offset of buffer b (b = kWsBuffers gives the total).
-constexpr size_t ws_offset(int b, size_t n)
+constexpr size_t ws_offset(int b, size_t m, size_t n)
 {
     size_t off = 0;
-    for (int i = 0; i < b; ++i) off += ws_round(ws_count(i, n) * sizeof(double));
+    for (int i = 0; i < b; ++i) off += ws_round(ws_count(i, m, n) * sizeof(double));
     return off;
 }
 
 // The allocation-free LSE entry point keeps its control block, workspace and cost-range
 // partials in one static device array of kNoAllocBytes per device: the control block first,
-// then the workspace of n = kNoAllocMaxN, then 2 partials per tile of that n.
+// then the workspace of m = n = kNoAllocMaxN (which holds that of any m, n <= kNoAllocMaxN), then
+// 2 partials per tile of that size.
 constexpr int kNoAllocMaxN = MDOT_NOALLOC_MAX_N;
 constexpr size_t kNoAllocCtl = ws_round(sizeof(Control));
 constexpr size_t kNoAllocRange =
     ws_round(2 * sizeof(double) * ((kNoAllocMaxN + kBR - 1) / kBR) * ((kNoAllocMaxN + kBC - 1) / kBC));
-constexpr size_t kNoAllocBytes = kNoAllocCtl + ws_offset(kWsBuffers, kNoAllocMaxN) + kNoAllocRange;
+constexpr size_t kNoAllocBytes = kNoAllocCtl + ws_offset(kWsBuffers, kNoAllocMaxN, kNoAllocMaxN) + kNoAllocRange;
 // Device address of that array on the current device (hipGetSymbolAddress, taken once per
 // device and cached). Returns 0 or a hipError_t code.
 int noalloc_scratch(int device, void** out);
@@ -258,7 +263,7 @@ int cost_code_dim(int cost_code, int d);
 // The sweep kernel instance a launch of hw takes (its cost code, planar for d <= 2, plus kOccHi
 // for the 2-waves-per-SIMD variant).
 int cost_code(const Work& hw);
-// big: some problem in flight has n > 8192 (the finalize instance for fin_per(n) = 32)
+// big: some problem in flight has m or n > 8192 (the finalize instance for fin_per = 32)
 int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, bool big, void* stream);
 // End-of-chunk done flags into host-visible memory: chunk number *seq (a device counter, advanced
 // here) writes out[(seq & 1) * kMaxBatch + item] (batch) or out[seq & 1] (single problem).

@@ -148,7 +148,7 @@ struct DenseCost {
     __device__ __forceinline__ DenseCost(const Work& w, int i0) : n(w.n), vec((w.n & 3) == 0)
     {
         const char* base = (const char*)w.cost + (size_t)i0 * w.n * kBytes;
-        const size_t rem = ((size_t)w.n - i0) * w.n * kBytes;
+        const size_t rem = ((size_t)w.m - i0) * w.n * kBytes;
         rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(rem > 0x7fffffffu ? 0x7fffffffu : rem),
                                                kBufDword3);
     }
@@ -249,12 +249,12 @@ struct PointCost {
     using Raw = int;
     const float* X;
     const float* Y;
-    int n, d, i0;
+    int m, n, d, i0;
     double y[4][D];
     const float4* sX;   // row coordinates 0..3 of the tile's rows (LDS)
     const float4* sX2;  // coordinates 4..7 (D = 8)
     __device__ __forceinline__ PointCost(const Work& w, int i0_)
-        : X((const float*)w.cost), Y((const float*)w.cost + (size_t)w.n * w.d), n(w.n), d(w.d), i0(i0_) {}
+        : X((const float*)w.cost), Y((const float*)w.cost + (size_t)w.m * w.d), m(w.m), n(w.n), d(w.d), i0(i0_) {}
     __device__ __forceinline__ void cols(int j0)
     {
 #pragma unroll
@@ -270,7 +270,7 @@ struct PointCost {
         const int i = i0 + r;
         RowX x;
 #pragma unroll
-        for (int e = 0; e < kRowF; ++e) x.v[e] = (e < D && i < n && e < d) ? X[(size_t)i * d + e] : 0.f;
+        for (int e = 0; e < kRowF; ++e) x.v[e] = (e < D && i < m && e < d) ? X[(size_t)i * d + e] : 0.f;
         return x;
     }
     __device__ __forceinline__ void decode(const RowX& x, double c[4]) const
@@ -300,7 +300,7 @@ struct PointCost {
         const RowX v = xrow(r);
         ((float4*)sX)[r] = make_float4(v.v[0], v.v[1], v.v[2], v.v[3]);
         if constexpr (kRowF == 8) ((float4*)sX2)[r] = make_float4(v.v[4], v.v[5], v.v[6], v.v[7]);
-        if (KIND == 1 && i < n) {
+        if (KIND == 1 && i < m) {
             double ss;
             if constexpr (D > 2) {
                 ss = (double)v.v[D - 1] * (double)v.v[D - 1];
@@ -429,13 +429,13 @@ __device__ __forceinline__ Entry entry_after(const Work& w, const SweepArgs& a, 
         e.z = fma(a.alpha_acc, e.p, e.z);
         e.lz = w.lzt[k];
         const double sdt = (a.reset & RS_TILDE) ? w.sdt[k] : 0.0;
-        e.p = next_dir(a, e.p, e.logt, e.lz, sdt, k < w.n);
+        e.p = next_dir(a, e.p, e.logt, e.lz, sdt, k < w.m);
     }
     e.zacc = e.z;
     if (a.va & VA_STAGE_INIT) {
-        const int n = w.n;
-        const double m = (k < n) ? w.r[k] : w.c[k - n];
-        e.rt = fma(1.0 - a.w, m, a.w / n);
+        const bool row = k < w.m;
+        const double mk = row ? w.r[k] : w.c[k - w.m];
+        e.rt = fma(1.0 - a.w, mk, a.w / (row ? w.m : w.n));  // smoothed toward the uniform law of the side
         e.logt = log(e.rt);
         if (a.stage == 1) {
             e.z = e.logt;
@@ -636,10 +636,10 @@ __device__ void tile_max(const Work& w, const SweepArgs& S, const TileCtx& t, do
 {
     double* sA = sm;
     double* sCol = sm + 5 * kBR;
-    const int n = w.n;
+    const int m = w.m, n = w.n;
     if (t.tid < kBR) {
         const int i = t.i0 + t.tid;
-        sA[t.tid] = (i < n) ? (w.z[i] + S.alpha * w.p[i]) * LOG2E_D : 0.0;
+        sA[t.tid] = (i < m) ? (w.z[i] + S.alpha * w.p[i]) * LOG2E_D : 0.0;
     }
     __syncthreads();
     const double g2 = S.gamma * w.scale * LOG2E_D;
@@ -651,24 +651,24 @@ __device__ void tile_max(const Work& w, const SweepArgs& S, const TileCtx& t, do
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         ok[k] = j0 + k < n;
-        V[k] = ok[k] ? (w.z[n + j0 + k] + S.alpha * w.p[n + j0 + k]) * LOG2E_D : 0.0;
+        V[k] = ok[k] ? (w.z[m + j0 + k] + S.alpha * w.p[m + j0 + k]) * LOG2E_D : 0.0;
         colmx[k] = -INFINITY;
     }
     for (int rr = 0; rr < kRPW; ++rr) {
         const int r = t.wave * kRPW + rr;
         const int i = t.i0 + r;
-        if (i >= n) break;
+        if (i >= m) break;
         double c[4];
         cost.row(r, j0, c);
-        double m = -INFINITY;
+        double mx = -INFINITY;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const double x = ok[k] ? fma(-g2, c[k], V[k]) + sA[r] : -INFINITY;
-            m = fmax(m, x);
+            mx = fmax(mx, x);
             colmx[k] = fmax(colmx[k], x);
         }
-        m = wave_max(m);
-        if (t.lane == 0) w.rowmin[(size_t)t.J * n + i] = m * LN2_D;
+        mx = wave_max(mx);
+        if (t.lane == 0) w.rowmin[(size_t)t.J * m + i] = mx * LN2_D;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) colmx[k] *= LN2_D;
@@ -690,14 +690,14 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     double* myRegion = region + t.wave * kWaveRegion;
     float* sRow = (float*)myRegion;                         // after the staged rows are read
     double* sColSlices = region + kRowBufD;                 // wave w's slice at + w kWaveRegion
-    const int n = w.n;
+    const int m = w.m, n = w.n;
     const double alpha = S.alpha;
     const double g2 = S.gamma * w.scale * LOG2E_D;
     const int j0 = t.j0lane;
     Cost cost(w, t.i0);
     cost.cols(j0);
     const int rbase = t.wave * kRPW;
-    const int nrows = min(kRPW, n - (t.i0 + rbase));  // rows of this wave (may be <= 0)
+    const int nrows = min(kRPW, m - (t.i0 + rbase));  // rows of this wave (may be <= 0)
     // loads of a batch of rows are issued before any compute on them (all 16 rows of the wave
     // for <= 8 B per lane-row, 8 rows for 16 B, 4 for 32 B); the first batch does not depend on the
     // solver state and is issued before the per-row and per-column set-up, which it overlaps
@@ -733,7 +733,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
     if (t.tid < kBR) {
         const int i = t.i0 + t.tid;
         double sh = -INFINITY, aa = -INFINITY;
-        if (i < n) {
+        if (i < m) {
             const Entry e = entry_after(w, S, i);
             sh = fma(alpha, e.p, e.lz);
             aa = (e.z - e.lz) * LOG2E_D;
@@ -746,7 +746,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
         const int j = t.J * kBC + t.tid;
         double vv = 0.0;
         if (j < n) {
-            const Entry e = entry_after(w, S, n + j);
+            const Entry e = entry_after(w, S, m + j);
             vv = fma(alpha, e.p, e.z) * LOG2E_D;
         }
         sColV[t.tid] = vv;
@@ -812,7 +812,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
         }
         const double rs = rows_reduce_f32(rp, sRow, t.lane);
         const int rr = t.lane >> 2;
-        if ((t.lane & 3) == 0 && rr < nrows) w.rowpart[(size_t)t.J * n + t.i0 + rbase + rr] = rs;
+        if ((t.lane & 3) == 0 && rr < nrows) w.rowpart[(size_t)t.J * m + t.i0 + rbase + rr] = rs;
     } else {
         double rp[kRPW];
         double c9 = kExp2C9;
@@ -863,7 +863,7 @@ __device__ void tile_lse(const Work& w, const SweepArgs& S, const TileCtx& t, do
         for (int r = kRPW - RB; r < kRPW; ++r) myRegion[r * 64 + t.lane] = rp[r];
         const double rs = rows_reduce_f64(myRegion, t.lane);
         const int rr = t.lane >> 2;
-        if ((t.lane & 3) == 0 && rr < nrows) w.rowpart[(size_t)t.J * n + t.i0 + rbase + rr] = rs;
+        if ((t.lane & 3) == 0 && rr < nrows) w.rowpart[(size_t)t.J * m + t.i0 + rbase + rr] = rs;
     }
     col_combine_store_strided(sColSlices, kWaveRegion, col64, t, w.colpart + (size_t)t.I * n, n, t.J * kBC);
     // every tile of row block I writes the same S_I, so the finalizer of any column block
@@ -883,7 +883,7 @@ __device__ void tile_r1(const Work& w, const SweepArgs& S, const TileCtx& t, dou
     double* sF1 = sm + 3 * kBR;
     double* sF2 = sm + 4 * kBR;
     double* sCol = sm + 5 * kBR;
-    const int n = w.n;
+    const int m = w.m, n = w.n;
     const double g2 = S.gamma * w.scale * LOG2E_D;
     const double inv_g = 1.0 / S.gamma;
     const double dg = S.gamma - S.gamma_prev;
@@ -893,7 +893,7 @@ __device__ void tile_r1(const Work& w, const SweepArgs& S, const TileCtx& t, dou
     if (t.tid < kBR) {
         int i = t.i0 + t.tid;
         double sh = -INFINITY, aa = 0.0, f1 = INFINITY, f2 = INFINITY, x = 0.0;
-        if (i < n) {
+        if (i < m) {
             const Entry e = entry_after(w, S, i);
             sh = e.lz;
             aa = (e.z - e.lz) * LOG2E_D;
@@ -907,7 +907,7 @@ __device__ void tile_r1(const Work& w, const SweepArgs& S, const TileCtx& t, dou
         const int j = t.J * kBC + t.tid;
         double vv = 0.0, g1 = INFINITY, g2v = INFINITY;
         if (j < n) {
-            const Entry e = entry_after(w, S, n + j);
+            const Entry e = entry_after(w, S, m + j);
             vv = e.z * LOG2E_D;
             g1 = e.z * inv_g;
             g2v = ext ? (e.z - e.zprev) * inv_dg : g1;
@@ -940,7 +940,7 @@ __device__ void tile_r1(const Work& w, const SweepArgs& S, const TileCtx& t, dou
     for (int rr = 0; rr < kRPW; ++rr) {
         const int ir = rbase + rr;
         const int i = t.i0 + ir;
-        if (i >= n) break;
+        if (i >= m) break;
         double c[4];
         cost.row(ir, j0, c);
         const double A = sA[ir], wt = sWt[ir], f1 = sF1[ir], f2 = sF2[ir];
@@ -959,8 +959,8 @@ __device__ void tile_r1(const Work& w, const SweepArgs& S, const TileCtx& t, dou
         rm1 = wave_min(rm1);
         rm2 = wave_min(rm2);
         if (t.lane == 0) {
-            w.rowmin[(size_t)t.J * n + i] = rm1;
-            w.rowmin[(size_t)(w.nct + t.J) * n + i] = rm2;
+            w.rowmin[(size_t)t.J * m + i] = rm1;
+            w.rowmin[(size_t)(w.nct + t.J) * m + i] = rm2;
         }
     }
     col_combine_store(sCol, col64, t, 0, w.colpart + (size_t)t.I * n, n, t.J * kBC);
@@ -981,23 +981,23 @@ __device__ void tile_r2(const Work& w, const SweepArgs& S, const TileCtx& t, dou
     double* sF1 = sm + 3 * kBR;
     double* sF2 = sm + 4 * kBR;
     double* sCol = sm + 5 * kBR;
-    const int n = w.n;
+    const int m = w.m, n = w.n;
     const double g2 = S.gamma * w.scale * LOG2E_D;
     if (t.tid < kBR) {
         int i = t.i0 + t.tid;
         double aa = 0.0, f1 = INFINITY, f2 = INFINITY;
-        if (i < n) {
+        if (i < m) {
             const Entry e = entry_after(w, S, i);
             aa = (e.z - e.lz) * LOG2E_D;
             f1 = w.fpp[i];
-            f2 = w.fpp[n + i];
+            f2 = w.fpp[m + i];
         }
         sA[t.tid] = aa; sF1[t.tid] = f1; sF2[t.tid] = f2;
     }
     {
         const int j = t.J * kBC + t.tid;
         double vv = 0.0;
-        if (j < n) vv = entry_after(w, S, n + j).z * LOG2E_D;
+        if (j < n) vv = entry_after(w, S, m + j).z * LOG2E_D;
         sCol[t.tid] = vv;
     }
     __syncthreads();
@@ -1025,7 +1025,7 @@ __device__ void tile_r2(const Work& w, const SweepArgs& S, const TileCtx& t, dou
     for (int rr = 0; rr < kRPW; ++rr) {
         const int ir = rbase + rr;
         const int i = t.i0 + ir;
-        if (i >= n) break;
+        if (i >= m) break;
         double c[4];
         cost.row(ir, j0, c);
         const double A = sA[ir], f1 = sF1[ir], f2 = sF2[ir];
@@ -1049,12 +1049,12 @@ __device__ void tile_r2(const Work& w, const SweepArgs& S, const TileCtx& t, dou
         rm1 = wave_min(rm1);
         rm2 = wave_min(rm2);
         if (t.lane == 0) {
-            const size_t o = (size_t)t.J * n + i;
+            const size_t o = (size_t)t.J * m + i;
             w.rowpart[o] = s0;
             w.rowpart2[o] = s1;
             w.rowpart3[o] = s2;
             w.rowmin[o] = rm1;
-            w.rowmin[(size_t)(w.nct + t.J) * n + i] = rm2;
+            w.rowmin[(size_t)(w.nct + t.J) * m + i] = rm2;
         }
     }
     col_combine_store(sCol, cm1, t, 1, w.colmin + (size_t)t.I * n, n, t.J * kBC);
@@ -1145,25 +1145,28 @@ __device__ __forceinline__ double group_fold(double v, int L)
 // Called by every lane of the wave; `valid` is false past the end of the 2n-vector.
 __device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool valid, int l, int L, const double* fac)
 {
-    const int n = w.n;
-    const bool row = k < n;
-    const int m = row ? w.nct : w.nrt;
-    const size_t ix = row ? (size_t)k : (size_t)(k - n);
+    // row entries (k < m) combine the nct column-tile partials at stride m, column entries the nrt
+    // row-tile partials at stride n
+    const int m = w.m;
+    const bool row = k < m;
+    const int np = row ? w.nct : w.nrt;
+    const size_t st = row ? (size_t)m : (size_t)w.n;
+    const size_t ix = row ? (size_t)k : (size_t)(k - m);
     Comb cb{0.0, INFINITY, INFINITY, 0.0, 0.0};
     if (mode == SM_LSE) {
-        cb.a = group_fold<0>(lane_fold<0>((row ? w.rowpart : w.colpart) + ix, n, l, L, m, row ? nullptr : fac, valid), L);
+        cb.a = group_fold<0>(lane_fold<0>((row ? w.rowpart : w.colpart) + ix, st, l, L, np, row ? nullptr : fac, valid), L);
     } else if (mode == SM_MAX) {
-        cb.b = group_fold<2>(lane_fold<2>((row ? w.rowmin : w.colmin) + ix, n, l, L, m, nullptr, valid), L);
+        cb.b = group_fold<2>(lane_fold<2>((row ? w.rowmin : w.colmin) + ix, st, l, L, np, nullptr, valid), L);
     } else {
         const double* mn = (row ? w.rowmin : w.colmin) + ix;
-        cb.b = group_fold<1>(lane_fold<1>(mn, n, l, L, m, nullptr, valid), L);
-        cb.c = group_fold<1>(lane_fold<1>(mn + (size_t)m * n, n, l, L, m, nullptr, valid), L);
+        cb.b = group_fold<1>(lane_fold<1>(mn, st, l, L, np, nullptr, valid), L);
+        cb.c = group_fold<1>(lane_fold<1>(mn + (size_t)np * st, st, l, L, np, nullptr, valid), L);
         if (mode == SM_R1) {
-            cb.a = group_fold<0>(lane_fold<0>(w.colpart + ix, n, l, L, m, fac, valid && !row), L);
+            cb.a = group_fold<0>(lane_fold<0>(w.colpart + ix, st, l, L, np, fac, valid && !row), L);
         } else {
-            cb.a = group_fold<0>(lane_fold<0>(w.rowpart + ix, n, l, L, m, nullptr, valid && row), L);
-            cb.d = group_fold<0>(lane_fold<0>(w.rowpart2 + ix, n, l, L, m, nullptr, valid && row), L);
-            cb.e = group_fold<0>(lane_fold<0>(w.rowpart3 + ix, n, l, L, m, nullptr, valid && row), L);
+            cb.a = group_fold<0>(lane_fold<0>(w.rowpart + ix, st, l, L, np, nullptr, valid && row), L);
+            cb.d = group_fold<0>(lane_fold<0>(w.rowpart2 + ix, st, l, L, np, nullptr, valid && row), L);
+            cb.e = group_fold<0>(lane_fold<0>(w.rowpart3 + ix, st, l, L, np, nullptr, valid && row), L);
         }
     }
     return cb;
@@ -1204,8 +1207,8 @@ __device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a
                                                int mode, bool e64, bool pre, const Comb& cb, double M,
                                                double v[kNDot])
 {
-    const int n = w.n;
-    if (k < n) {  // row i = k
+    const int m = w.m, n = w.n;
+    if (k < m) {  // row i = k
         const int i = k;
         if (mode == SM_MAX) {
             w.lz[i] = cb.b;
@@ -1215,7 +1218,7 @@ __device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a
             lse_terms(w, e, g_cur, k, l, sum, e64, pre, true, v);
         } else if (mode == SM_R1) {
             w.fpp[i] = cb.b;
-            w.fpp[n + i] = cb.c;
+            w.fpp[m + i] = cb.c;
             v[D_RF1] += w.r[i] * cb.b;
             v[D_RF2] += w.r[i] * cb.c;
         } else {  // SM_R2
@@ -1229,9 +1232,9 @@ __device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a
         }
         return;
     }
-    const int j = k - n;  // column
+    const int j = k - m;  // column
     if (mode == SM_MAX) {
-        w.lz[n + j] = cb.b;
+        w.lz[m + j] = cb.b;
     } else if (mode == SM_LSE) {
         const double sum = cb.a;
         const double l = M + log(sum);
@@ -1657,7 +1660,7 @@ struct EntryIn {
 };
 __device__ __forceinline__ EntryIn entry_load(const Work& w, const SweepArgs& a, int k)
 {
-    const int n = w.n;
+    const int m = w.m;
     EntryIn in;
     in.z = w.z[k];
     in.p = w.p[k];
@@ -1666,13 +1669,13 @@ __device__ __forceinline__ EntryIn entry_load(const Work& w, const SweepArgs& a,
     in.rt = w.rt[k];
     in.zprev = w.zprev[k];
     in.lzt = w.lzt[k];
-    in.m = (a.va & VA_STAGE_INIT) ? *((k < n) ? w.r + k : w.c + (k - n)) : 0.0;
+    in.m = (a.va & VA_STAGE_INIT) ? *((k < m) ? w.r + k : w.c + (k - m)) : 0.0;
     in.g = w.g[k];
     in.sdt = ((a.va & VA_ACCEPT) && (a.reset & RS_TILDE)) ? w.sdt[k] : 0.0;
     return in;
 }
 // entry_after from loaded inputs (same arithmetic, so bit-identical to the sweeps' copy)
-__device__ __forceinline__ Entry entry_from(const EntryIn& in, const SweepArgs& a, int n, int k)
+__device__ __forceinline__ Entry entry_from(const EntryIn& in, const SweepArgs& a, int m, int n, int k)
 {
     Entry e;
     e.z = in.z;
@@ -1684,11 +1687,11 @@ __device__ __forceinline__ Entry entry_from(const EntryIn& in, const SweepArgs& 
     if (a.va & VA_ACCEPT) {
         e.z = fma(a.alpha_acc, e.p, e.z);
         e.lz = in.lzt;
-        e.p = next_dir(a, e.p, e.logt, e.lz, in.sdt, k < n);
+        e.p = next_dir(a, e.p, e.logt, e.lz, in.sdt, k < m);
     }
     e.zacc = e.z;
     if (a.va & VA_STAGE_INIT) {
-        e.rt = fma(1.0 - a.w, in.m, a.w / n);
+        e.rt = fma(1.0 - a.w, in.m, a.w / (k < m ? m : n));
         e.logt = log(e.rt);
         if (a.stage == 1) {
             e.z = e.logt;
@@ -1725,7 +1728,7 @@ __device__ __forceinline__ double store_update(const Work& w, const SweepArgs& a
         w.g[k] = g_cur;
     }
     if (va & VA_SAVE_BEST) w.zbest[k] = e.zacc;
-    if ((va & VA_ROUND_PREP) && k < w.n) w.xr[k] = round_x(w.r[k], e.lz);
+    if ((va & VA_ROUND_PREP) && k < w.m) w.xr[k] = round_x(w.r[k], e.lz);
     return g_cur;
 }
 
@@ -1736,19 +1739,20 @@ template <int PER>
 __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a, int k, bool valid, int l, int L,
                                               bool e64, bool pre, double v[kNDot], double* sfac, bool first)
 {
-    const int n = w.n, nrt = w.nrt;
+    const int m = w.m, n = w.n, nrt = w.nrt;
     const int kc = valid ? k : 0;
-    const bool row = kc < n;
-    const int m = row ? w.nct : nrt;
+    const bool row = kc < m;
+    const int np = row ? w.nct : nrt;               // partials of this entry
+    const size_t st = row ? (size_t)m : (size_t)n;  // their stride
     const int lane = threadIdx.x & 63;
-    const double* base = row ? w.rowpart + kc : w.colpart + (kc - n);
+    const double* base = row ? w.rowpart + kc : w.colpart + (kc - m);
     double ts[4], x[PER];
 #pragma unroll
     for (int q = 0; q < 4; ++q) ts[q] = w.tshift[min(lane + 64 * q, nrt - 1)];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int I = min(l + u * L, m - 1);
-        x[u] = base[(size_t)I * n];
+        const int I = min(l + u * L, np - 1);
+        x[u] = base[(size_t)I * st];
     }
     const EntryIn in = entry_load(w, a, kc);
     // M = max_I S_I, the same value in every lane
@@ -1764,11 +1768,11 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
     double acc = 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u)
-        if (l + u * L < m) acc = fma(x[u], row ? 1.0 : sfac[min(l + u * L, 255)], acc);
+        if (l + u * L < np) acc = fma(x[u], row ? 1.0 : sfac[min(l + u * L, 255)], acc);
     Comb cb{};
     cb.a = group_fold<0>(acc, L);
     if (!valid || l != 0) return;
-    const Entry e = entry_from(in, a, n, k);
+    const Entry e = entry_from(in, a, m, n, k);
     const double g_cur = store_update(w, a, e, in.g, k);
     finalize_entry(w, a, e, g_cur, k, SM_LSE, e64, pre, cb, M, v);
 }
@@ -1795,7 +1799,7 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     const bool pre = C->prm.precond != 0;
     asm volatile("" ::: "memory");
     const int tid = threadIdx.x;
-    const int n = wl.n;
+    const int m = wl.m, n = wl.n;
     const int L = wl.fin_L;
     const int lgL = wl.fin_lgL;
     const int l = tid & (L - 1);
@@ -1820,7 +1824,7 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     const int nvb = wl.fin_nvb;
     for (int vb = blk; vb < nvb; vb += nblk) {
         const int k = (vb * kVecWG + tid) >> lgL;
-        const bool valid = k < 2 * n;
+        const bool valid = k < m + n;
         if (fast) {
             if (!BIG || per == 8) fin_lse_entry<8>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
             else fin_lse_entry<32>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
@@ -1831,7 +1835,7 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         Comb cb{};
         if (active) cb = combine(wl, mode, k, valid, l, L, sh.fac);
         if (!valid || l != 0) continue;
-        const Entry e = entry_from(in, a, n, k);
+        const Entry e = entry_from(in, a, m, n, k);
         const double g_cur = store_update(wl, a, e, in.g, k);
         if (active) finalize_entry(wl, a, e, g_cur, k, mode, e64, pre, cb, M, v);
     }
@@ -1855,9 +1859,9 @@ constexpr int kDecideWG = 64;
 __device__ __forceinline__ void decide_body(const Work& w, int parity)
 {
     const int lane = threadIdx.x;
-    // Every read of this kernel is issued together: the state, the parameters, n and the first
-    // 4 x 64 workgroups' dots (the dots array has kFinMaxGrid entries, so these loads are in
-    // bounds for any n; entries past fin_grid(n) are masked). The control block is read through
+    // Every read of this kernel is issued together: the state, the parameters, the finalize
+    // workgroup count and the first 4 x 64 workgroups' dots (the dots array has kFinMaxGrid
+    // entries, so these loads are in bounds for any size; entries past fin_grid are masked). The control block is read through
     // a pointer held in a vector register, so the state is loaded into VGPRs (as scalar data it
     // would overflow the SGPRs and be reloaded piecemeal).
     uint64_t cb = reinterpret_cast<uint64_t>(&ctl_of(w));
@@ -1865,13 +1869,12 @@ __device__ __forceinline__ void decide_body(const Work& w, int parity)
     const Control* C = reinterpret_cast<const Control*>(cb);
     State S = C->st[parity];
     const DevParams P = C->prm;
-    const int n = C->w.n;
+    const int nblk = C->w.fin_nblk;
     double x[4][kNDot];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int d = 0; d < kNDot; ++d) x[q][d] = C->bdots[(lane + 64 * q) * kNDot + d];
-    const int nblk = fin_grid(n);
     double v[kNDot];
 #pragma unroll
     for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
@@ -2013,14 +2016,20 @@ __global__ void k_intake(const Work* __restrict__ wp, double* out8)
 {
     const Work w = *wp;
     __shared__ double sred[8][kWG];
-    const int n = w.n, t = threadIdx.x;
+    const int m = w.m, n = w.n, t = threadIdx.x;
     double sr = 0, sc = 0, mr = INFINITY, mc = INFINITY, hr = 0, hc = 0, bad = 0;
-    for (int i = t; i < n; i += kWG) {
-        double a = w.r[i], b = w.c[i];
-        if (!isfinite(a) || !isfinite(b)) bad += 1;
-        sr += a; sc += b;
-        mr = fmin(mr, a); mc = fmin(mc, b);
+    for (int i = t; i < m; i += kWG) {
+        const double a = w.r[i];
+        if (!isfinite(a)) bad += 1;
+        sr += a;
+        mr = fmin(mr, a);
         if (a > 0) hr -= a * log(a);
+    }
+    for (int j = t; j < n; j += kWG) {
+        const double b = w.c[j];
+        if (!isfinite(b)) bad += 1;
+        sc += b;
+        mc = fmin(mc, b);
         if (b > 0) hc -= b * log(b);
     }
     sred[0][t] = sr; sred[1][t] = sc; sred[2][t] = mr; sred[3][t] = mc;
@@ -2043,7 +2052,7 @@ __global__ void k_intake(const Work* __restrict__ wp, double* out8)
 template <class Cost>
 __device__ void cost_range_body(const Work& w, double* mn, double* mx)
 {
-    const int n = w.n;
+    const int m = w.m, n = w.n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int I = blockIdx.x / w.nct, J = blockIdx.x % w.nct;
     const int j0 = J * kBC + lane * 4;
@@ -2052,7 +2061,7 @@ __device__ void cost_range_body(const Work& w, double* mn, double* mx)
     double lo = INFINITY, hi = -INFINITY;
     for (int rr = 0; rr < kRPW; ++rr) {
         const int i = I * kBR + wave * kRPW + rr;
-        if (i >= n) break;
+        if (i >= m) break;
         double c[4];
         cost.row(wave * kRPW + rr, j0, c);
 #pragma unroll
@@ -2107,22 +2116,23 @@ __global__ void k_finish(const Work* __restrict__ wp, double* u_out, double* v_o
     __shared__ double sdelta;
     const Work& w = *wp;
     const SweepArgs a = args_of(w.st);
-    const int n = w.n, t = threadIdx.x;
+    const int m = w.m, n = w.n, t = threadIdx.x;
+    const int mx = m > n ? m : n;
     double s = 0.0;
-    for (int i = t; i < n; i += kWG) s += best_entry(w, a, n + i) - best_entry(w, a, i);
+    for (int i = t; i < mx; i += kWG) s += (i < n ? best_entry(w, a, m + i) : 0.0) - (i < m ? best_entry(w, a, i) : 0.0);
     sred[t] = s;
     __syncthreads();
     for (int h = kWG / 2; h > 0; h >>= 1) {
         if (t < h) sred[t] += sred[t + h];
         __syncthreads();
     }
-    if (t == 0) sdelta = sred[0] / (2.0 * n);
+    if (t == 0) sdelta = sred[0] / (double)(m + n);
     __syncthreads();
     const double dl = sdelta;
-    for (int i = t; i < n; i += kWG) {
+    for (int i = t; i < m; i += kWG)
         if (u_out) u_out[i] = best_entry(w, a, i) + dl;
-        if (v_out) v_out[i] = best_entry(w, a, n + i) - dl;
-    }
+    for (int j = t; j < n; j += kWG)
+        if (v_out) v_out[j] = best_entry(w, a, m + j) - dl;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -2197,8 +2207,8 @@ int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
 #define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity)
     MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
-    if (hw.fin_per > 8) hipLaunchKernelGGL(k_fin<true>, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
-    else hipLaunchKernelGGL(k_fin<false>, dim3(fin_grid(hw.n)), dim3(kVecWG), 0, s, wd, parity);
+    if (hw.fin_per > 8) hipLaunchKernelGGL(k_fin<true>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity);
+    else hipLaunchKernelGGL(k_fin<false>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideWG), 0, s, wd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -26,7 +26,7 @@ PREC_F64, PREC_F32, PREC_MIXED = 0, 1, 2
 
 class CostDesc(ct.Structure):
     _fields_ = [("n", ct.c_int32), ("d", ct.c_int32), ("kind", ct.c_int), ("dtype", ct.c_int),
-                ("data", ct.c_void_p), ("scale", ct.c_double)]
+                ("data", ct.c_void_p), ("scale", ct.c_double), ("m", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class Params(ct.Structure):
@@ -124,21 +124,25 @@ def _dtype_code(t) -> int:
 
 
 def dense_cost(C, scale: float = 1.0) -> CostDesc:
-    """Descriptor of a dense n x n cost tensor (device, contiguous, f64/f32/f16/bf16)."""
-    assert C.is_cuda and C.dim() == 2 and C.shape[0] == C.shape[1] and C.is_contiguous()
-    desc = CostDesc(n=C.shape[0], d=0, kind=COST_DENSE, dtype=_dtype_code(C), data=C.data_ptr(), scale=scale)
+    """Descriptor of a dense m x n cost tensor (device, contiguous, f64/f32/f16/bf16): row i is
+    source i (marginal r), column j target j (marginal c)."""
+    assert C.is_cuda and C.dim() == 2 and C.is_contiguous()
+    desc = CostDesc(n=C.shape[1], m=C.shape[0], d=0, kind=COST_DENSE, dtype=_dtype_code(C), data=C.data_ptr(),
+                    scale=scale)
     desc._tensor = C  # the descriptor holds a raw pointer: keep the tensor alive with it
     return desc
 
 
-def point_cost(XY, n: int, d: int, kind: str = "sqeuclid", scale: float = 0.0) -> CostDesc:
-    """Descriptor of a point-cloud cost: XY is a contiguous FP32 device tensor holding X (n x d)
-    followed by Y (n x d). scale 0 lets the library normalise by the largest pairwise value."""
+def point_cost(XY, n: int, d: int, kind: str = "sqeuclid", scale: float = 0.0, m: int | None = None) -> CostDesc:
+    """Descriptor of a point-cloud cost: XY is a contiguous FP32 device tensor holding X (m x d,
+    the sources; m = n unless given) followed by Y (n x d, the targets). scale 0 lets the library
+    normalise by the largest pairwise value."""
     import torch
 
-    assert XY.is_cuda and XY.dtype == torch.float32 and XY.is_contiguous() and XY.numel() == 2 * n * d
+    m = n if m is None else m
+    assert XY.is_cuda and XY.dtype == torch.float32 and XY.is_contiguous() and XY.numel() == (m + n) * d
     k = COST_POINTS_SQEUCLID if kind == "sqeuclid" else COST_POINTS_L1
-    desc = CostDesc(n=n, d=d, kind=k, dtype=DT_F32, data=XY.data_ptr(), scale=scale)
+    desc = CostDesc(n=n, m=m, d=d, kind=k, dtype=DT_F32, data=XY.data_ptr(), scale=scale)
     desc._tensor = XY  # the descriptor holds a raw pointer: keep the tensor alive with it
     return desc
 

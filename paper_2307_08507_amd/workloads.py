@@ -150,6 +150,26 @@ def grid_problem(k: int, family: str, cost: str, seed: int, dtype=np.float64):
     return grid_cost(k, cost, dtype), r, c
 
 
+def grid_pair_problem(k1: int, k2: int, family: str, cost: str, seed: int, dtype=np.float64):
+    """A rectangular OT problem between images of two resolutions: r on a k1 x k1 grid, c on a
+    k2 x k2 grid (both from `family`, seeds seed and seed + 1), pixel centres placed in the unit
+    square ((i + 1/2) / k), cost = squared-Euclidean or L1 distance between centres divided by its
+    maximum. Returns (C of shape (k1^2, k2^2), r, c)."""
+    gen = FAMILIES[family]
+    r = gen(k1, seed)
+    c = gen(k2, seed + 1)
+    x = (grid_coords(k1).astype(np.float64) + 0.5) / k1
+    y = (grid_coords(k2).astype(np.float64) + 0.5) / k2
+    d = x[:, None, :] - y[None, :, :]
+    if cost == "sqeuclid":
+        num = (d * d).sum(-1)
+    elif cost == "l1":
+        num = np.abs(d).sum(-1)
+    else:
+        raise ValueError(f"unknown grid cost kind {cost!r}")
+    return (num / num.max()).astype(dtype), r, c
+
+
 def grid_problem_marginals(k: int, family: str, seed: int) -> np.ndarray:
     """The marginal `grid_problem` draws from `family` with `seed` (the cost is formed apart)."""
     return FAMILIES[family](k, seed)
