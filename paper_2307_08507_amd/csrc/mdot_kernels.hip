@@ -1842,11 +1842,18 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     if (active) block_dots(v, bdots_of(w) + (size_t)blk * kNDot, tid, sh.red);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2. With `xcd`,
+// physical workgroup b takes the place of workgroup (b % 8) (G / 8) + b / 8 (8 divides the grid
+// G): runs of consecutive virtual workgroups then run on one XCD at about the same time. With 16
+// or more lanes per entry, a virtual workgroup holds 16 or fewer entries, and the partials of
+// consecutive entries share cache lines, which each XCD then fetches once instead of once per
+// workgroup. Everything a workgroup computes and stores depends on its virtual index alone.
 template <bool BIG>
-__global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int parity)
+__global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int parity, int xcd)
 {
     __shared__ FinShared sh;
-    fin_body<BIG>(*wp, parity, blockIdx.x, gridDim.x, sh);
+    const int G = gridDim.x, b = blockIdx.x;
+    fin_body<BIG>(*wp, parity, xcd ? (b & 7) * (G >> 3) + (b >> 3) : b, G, sh);
 }
 
 // ------------------------------------------------------------------ the decide kernel
@@ -2207,8 +2214,9 @@ int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
 #define L_(CC) hipLaunchKernelGGL(k_sweep<CC>, dim3(tiles), dim3(kWG), 0, s, wd, parity)
     MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
-    if (hw.fin_per > 8) hipLaunchKernelGGL(k_fin<true>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity);
-    else hipLaunchKernelGGL(k_fin<false>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity);
+    const int xcd = hw.fin_L >= 16 && hw.fin_nblk % 8 == 0;
+    if (hw.fin_per > 8) hipLaunchKernelGGL(k_fin<true>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity, xcd);
+    else hipLaunchKernelGGL(k_fin<false>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity, xcd);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideWG), 0, s, wd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -320,6 +320,49 @@ def test_solve_large_n_points_recertified_by_oracle(ctx):
     assert me_o <= 1e-12
 
 
+def test_engine_past_256_row_tiles_bitwise_equals_solve(ctx):
+    # Past 256 row tiles (m > 16384) the finalize folds each entry's partials in its general
+    # path; in the engine the batched finalize serves that problem beside one whose entries take
+    # the 32-partial fast path. The engine must return each problem's solve-alone result bit for
+    # bit. n = 20000 (313 row tiles) beside n = 9000 (141 row tiles).
+    prm = M.default_params(precision="f32")
+    probs = []
+    for n, seed in [(20000, 83), (9000, 84)]:
+        X, Y, r, c = _points_problem(n, seed)
+        probs.append((n, dev(np.concatenate([X, Y]).ravel(), torch.float32), dev(r), dev(c)))
+    alone = []
+    for n, XY, r, c in probs:
+        u = torch.empty(n, dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+        res = ctx.solve(M.point_cost(XY, n, 2, "sqeuclid", scale=0.5), r, c, 1e-4, prm, u, v)
+        print(f"alone n={n}: status={res.status} gap={res.gap:.3e} sweeps={res.sweeps}", flush=True)
+        assert res.status == 0 and res.gap <= 1e-4
+        alone.append((res, u.cpu(), v.cpu()))
+    eng = M.Context(0)
+    try:
+        tickets, outs = [], []
+        for n, XY, r, c in probs:
+            u = torch.empty(n, dtype=torch.float64, device="cuda")
+            v = torch.empty_like(u)
+            t = eng.submit(M.point_cost(XY, n, 2, "sqeuclid", scale=0.5), r, c, 1e-4, prm, u, v)
+            assert t is not None
+            tickets.append(t)
+            outs.append((u, v))
+        for _ in range(100000):
+            if eng.inflight()[0] == 0:
+                break
+            eng.run(64)
+        assert eng.inflight() == (0, 0)
+        for t, (u, v), (ra, ua, va) in zip(tickets, outs, alone):
+            rb = eng.poll(t)
+            assert rb is not None
+            assert torch.equal(u.cpu(), ua) and torch.equal(v.cpu(), va)
+            for f in ("status", "primal_cost", "dual_bound", "gap", "gamma_final", "stages", "pncg_iters", "sweeps"):
+                assert getattr(rb, f) == getattr(ra, f), f
+    finally:
+        eng.close()
+
+
 def test_single_point(ctx):
     C = dev(np.array([[0.375]]), torch.float64)
     one = dev(np.array([1.0]))
