@@ -21,12 +21,17 @@ constexpr int kVecWG = 256;
 // fin_grid(m, n) workgroups. Depends on the sizes only, so the summation order of every entry is
 // fixed by them. Past 8192 rows or columns each lane takes 32 partials, so that the groups fit in
 // kFinMaxGrid workgroups without a second round (n = 16384: L = 8, 1024 workgroups; with 8 per
-// lane it would be L = 32 and four rounds).
+// lane it would be L = 32 and four rounds). Past 256 row tiles (more than 16384 rows) the
+// groups have kFinLanesLarge lanes, each folding its share of the partials in batches of 32
+// loads: the 8 entries of a wave then read 8 consecutive partials of each row tile, so a load
+// instruction touches 8 cache lines instead of one line per lane (L = 64 at 1561 row tiles).
 constexpr int kFinMaxGrid = 1024;
+constexpr int kFinLanesLarge = 8;
 constexpr int fin_per(int m, int n) { return (m > n ? m : n) > 8192 ? 32 : 8; }
 constexpr int fin_lanes(int m, int n)
 {
     const int nrt = (m + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
+    if (nrt > 256) return kFinLanesLarge;
     const int q = nrt > nct ? nrt : nct;
     int L = 1;
     while (L < 64 && L * fin_per(m, n) < q) L <<= 1;

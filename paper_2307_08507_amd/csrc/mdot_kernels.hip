@@ -1099,24 +1099,24 @@ __device__ __forceinline__ double fold_op(double acc, double x, double f)
 }
 
 // Lane l of an entry's L-lane group folds partials l, l + L, l + 2L, ... of the m partials at
-// base[I * stride], in that order, 8 loads in flight at a time. With `fac` (column LSE
+// base[I * stride], in that order, B loads in flight at a time. With `fac` (column LSE
 // partials) partial I is scaled by fac[I] = exp(S_I - M), a table the workgroup forms once.
-template <int OP>
+template <int OP, int B = 8>
 __device__ __forceinline__ double lane_fold(const double* __restrict__ base, size_t stride, int l, int L, int m,
                                             const double* __restrict__ fac, bool use)
 {
     double acc = (OP == 0) ? 0.0 : (OP == 1 ? INFINITY : -INFINITY);
     if (!use) return acc;
-    for (int q0 = l; q0 < m; q0 += 8 * L) {
-        double x[8], f[8];
+    for (int q0 = l; q0 < m; q0 += B * L) {
+        double x[B], f[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < B; ++u) {
             const int I = q0 + u * L;
             x[u] = (I < m) ? base[(size_t)I * stride] : 0.0;
             f[u] = (fac && I < m) ? fac[I] : 1.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < B; ++u) {
             const int I = q0 + u * L;
             if (I < m) acc = fold_op<OP>(acc, x[u], f[u]);
         }
@@ -1141,8 +1141,10 @@ __device__ __forceinline__ double group_fold(double v, int L)
     return v;
 }
 
-// Combine the tile partials of entry k (row k < n, column k - n otherwise) for `mode`.
-// Called by every lane of the wave; `valid` is false past the end of the 2n-vector.
+// Combine the tile partials of entry k (row k < n, column k - n otherwise) for `mode`. The LSE
+// fold keeps BL loads in flight per lane (the other modes 8). Called by every lane of the wave;
+// `valid` is false past the end of the 2n-vector.
+template <int BL = 8>
 __device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool valid, int l, int L, const double* fac)
 {
     // row entries (k < m) combine the nct column-tile partials at stride m, column entries the nrt
@@ -1154,7 +1156,7 @@ __device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool val
     const size_t ix = row ? (size_t)k : (size_t)(k - m);
     Comb cb{0.0, INFINITY, INFINITY, 0.0, 0.0};
     if (mode == SM_LSE) {
-        cb.a = group_fold<0>(lane_fold<0>((row ? w.rowpart : w.colpart) + ix, st, l, L, np, row ? nullptr : fac, valid), L);
+        cb.a = group_fold<0>(lane_fold<0, BL>((row ? w.rowpart : w.colpart) + ix, st, l, L, np, row ? nullptr : fac, valid), L);
     } else if (mode == SM_MAX) {
         cb.b = group_fold<2>(lane_fold<2>((row ? w.rowmin : w.colmin) + ix, st, l, L, np, nullptr, valid), L);
     } else {
@@ -1833,7 +1835,9 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         const int kc = valid ? k : 0;
         const EntryIn in = entry_load(wl, a, kc);
         Comb cb{};
-        if (active) cb = combine(wl, mode, k, valid, l, L, sh.fac);
+        // past 256 row tiles (the BIG instance only) an LSE entry folds its partials in batches of
+        // 32 loads: 8 lanes share some hundreds of partials there
+        if (active) cb = combine<BIG ? 32 : 8>(wl, mode, k, valid, l, L, sh.fac);
         if (!valid || l != 0) continue;
         const Entry e = entry_from(in, a, m, n, k);
         const double g_cur = store_update(wl, a, e, in.g, k);
