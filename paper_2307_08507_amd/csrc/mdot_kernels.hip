@@ -245,14 +245,19 @@ struct DenseCost {
 template <int KIND, int D = 3>
 struct PointCost {
     static_assert(D == 2 || D == 3 || D == 8, "point instances carry 2, 3 or 8 coordinates");
-    static constexpr int kRowF = D <= 4 ? 4 : 8;  // floats per row in LDS (one or two float4)
+    static constexpr int kRowF = D <= 4 ? 4 : 8;  // coordinates per row held for the loop
+    // Up to 3 coordinates the tile's rows are kept in LDS as FP64 (the FP32 values converted
+    // once per row at set-up, exactly), so the loop reads them without a conversion per row and
+    // lane; 8-coordinate rows stay FP32 (two float4), as FP64 they would not fit the LDS.
+    static constexpr bool kRowF64 = D <= 3;
+    using RowT = typename std::conditional<kRowF64, double, float>::type;
     using Raw = int;
     const float* X;
     const float* Y;
     int m, n, d, i0;
     double y[4][D];
-    const float4* sX;   // row coordinates 0..3 of the tile's rows (LDS)
-    const float4* sX2;  // coordinates 4..7 (D = 8)
+    const void* sX;   // row coordinates 0..3 (float4), or 0..1 (double2) (LDS)
+    const void* sX2;  // coordinates 4..7 (float4, D = 8), or 2 (double, D = 3)
     __device__ __forceinline__ PointCost(const Work& w, int i0_)
         : X((const float*)w.cost), Y((const float*)w.cost + (size_t)w.m * w.d), m(w.m), n(w.n), d(w.d), i0(i0_) {}
     __device__ __forceinline__ void cols(int j0)
@@ -263,14 +268,14 @@ struct PointCost {
             for (int e = 0; e < D; ++e) y[k][e] = (j0 + k < n && e < d) ? (double)Y[(size_t)(j0 + k) * d + e] : 0.0;
     }
     struct RowX {
-        float v[kRowF];
+        RowT v[kRowF];
     };
     __device__ __forceinline__ RowX xrow(int r) const
     {
         const int i = i0 + r;
         RowX x;
 #pragma unroll
-        for (int e = 0; e < kRowF; ++e) x.v[e] = (e < D && i < m && e < d) ? X[(size_t)i * d + e] : 0.f;
+        for (int e = 0; e < kRowF; ++e) x.v[e] = (RowT)((e < D && i < m && e < d) ? X[(size_t)i * d + e] : 0.f);
         return x;
     }
     __device__ __forceinline__ void decode(const RowX& x, double c[4]) const
@@ -292,14 +297,19 @@ struct PointCost {
     // r's coordinates and, for squared distances, folds -g2 |x_r|^2 into the row term a.
     __device__ __forceinline__ void bind_rows(void* lds, void* lds_hi)
     {
-        sX = (const float4*)lds;
-        sX2 = (const float4*)lds_hi;
+        sX = lds;
+        sX2 = lds_hi;
     }
     __device__ __forceinline__ void row_setup(int r, int i, double g2, double& a)
     {
         const RowX v = xrow(r);
-        ((float4*)sX)[r] = make_float4(v.v[0], v.v[1], v.v[2], v.v[3]);
-        if constexpr (kRowF == 8) ((float4*)sX2)[r] = make_float4(v.v[4], v.v[5], v.v[6], v.v[7]);
+        if constexpr (kRowF64) {
+            ((double2*)sX)[r] = make_double2(v.v[0], v.v[1]);
+            if constexpr (D == 3) ((double*)sX2)[r] = v.v[2];
+        } else {
+            ((float4*)sX)[r] = make_float4(v.v[0], v.v[1], v.v[2], v.v[3]);
+            if constexpr (kRowF == 8) ((float4*)sX2)[r] = make_float4(v.v[4], v.v[5], v.v[6], v.v[7]);
+        }
         if (KIND == 1 && i < m) {
             double ss;
             if constexpr (D > 2) {
@@ -335,12 +345,17 @@ struct PointCost {
     }
     __device__ __forceinline__ RowX lds_row(int r) const
     {
-        RowX x;
-        const float4 a = sX[r];  // one address for the whole wave: an LDS broadcast
-        x.v[0] = a.x; x.v[1] = a.y; x.v[2] = a.z; x.v[3] = a.w;
-        if constexpr (kRowF == 8) {
-            const float4 b = sX2[r];
-            x.v[4] = b.x; x.v[5] = b.y; x.v[6] = b.z; x.v[7] = b.w;
+        RowX x;  // one address for the whole wave: LDS broadcasts
+        if constexpr (kRowF64) {
+            const double2 a = ((const double2*)sX)[r];
+            x.v[0] = a.x; x.v[1] = a.y; x.v[2] = D == 3 ? ((const double*)sX2)[r] : 0.0; x.v[3] = 0.0;
+        } else {
+            const float4 a = ((const float4*)sX)[r];
+            x.v[0] = a.x; x.v[1] = a.y; x.v[2] = a.z; x.v[3] = a.w;
+            if constexpr (kRowF == 8) {
+                const float4 b = ((const float4*)sX2)[r];
+                x.v[4] = b.x; x.v[5] = b.y; x.v[6] = b.z; x.v[7] = b.w;
+            }
         }
         return x;
     }
