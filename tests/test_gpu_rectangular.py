@@ -50,7 +50,8 @@ def _lse2(ctx, desc, u, v, gamma, prec, m, n, fn=None):
     return lr.cpu().numpy(), lc.cpu().numpy()
 
 
-@pytest.mark.parametrize("m,n", [(300, 1000), (1000, 300), (257, 65), (64, 4097), (1, 700), (700, 1)])
+@pytest.mark.parametrize("m,n", [(300, 1000), (1000, 300), (257, 65), (64, 4097), (1, 700), (700, 1),
+                                 (20000, 300), (300, 20000)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_lse2_rectangular(ctx, m, n, prec):
     print(f"rect lse2 {m}x{n} {prec}", flush=True)
@@ -89,6 +90,30 @@ def test_round_certify_rectangular(ctx, shape):
     assert ub == pytest.approx(ub_o, rel=1e-12, abs=1e-15)
     assert lb == pytest.approx(lb_o, rel=1e-12, abs=1e-15)
     assert me <= 1e-12
+
+
+@pytest.mark.parametrize("prec_dtype", [torch.float64, torch.float32])
+def test_round_certify_tall(ctx, prec_dtype):
+    # 20000 rows are 313 row tiles: past 256 the finalize folds each column's partials with 8
+    # lanes in its general path, in the LSE, Round and certificate sweeps alike
+    m, n, gamma = 20000, 300, 200.0
+    print(f"round/certify {m}x{n} {prec_dtype}", flush=True)
+    rng = np.random.default_rng(20000)
+    Cd = dev(rng.random((m, n)), prec_dtype)
+    C64 = Cd.double().cpu().numpy()
+    r = rng.dirichlet(np.ones(m))
+    c = rng.dirichlet(np.ones(n))
+    u, v = _potentials(C64, gamma, 3)
+    up, vp = _potentials(C64, gamma / 2, 4)
+    ub_o, lb_o, me_o, _ = O.round_certify(C64, u, v, gamma, r, c, u_prev=up, v_prev=vp, gamma_prev=gamma / 2)
+    ub, lb, me = ctx.round_certify(M.dense_cost(Cd), dev(u), dev(v), gamma, dev(r), dev(c),
+                                   u_prev=dev(up), v_prev=dev(vp), gamma_prev=gamma / 2)
+    print(f"UB {ub:.15e} vs {ub_o:.15e}  LB {lb:.15e} vs {lb_o:.15e}", flush=True)
+    # the Round sweeps take FP64 exponentials whatever the cost's storage
+    assert ub == pytest.approx(ub_o, rel=1e-11, abs=1e-14)
+    assert lb == pytest.approx(lb_o, rel=1e-11, abs=1e-14)
+    assert lb <= ub
+    assert me <= 1e-11
 
 
 def _solve(ctx, desc, r, c, target=1e-4, **kw):
