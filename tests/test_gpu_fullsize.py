@@ -320,6 +320,40 @@ def test_solve_large_n_points_recertified_by_oracle(ctx):
     assert me_o <= 1e-12
 
 
+def test_engine_equals_solve_with_xcd_finalize_order(ctx):
+    # n = 5120: 16 lanes per finalize entry and 640 finalize workgroups, so a solve alone runs
+    # its finalize in the XCD-aware workgroup order; the batched finalize does not. Everything a
+    # workgroup computes depends on its virtual index only, so the two must agree bit for bit.
+    n = 5120
+    rng = np.random.default_rng(5120)
+    Cd = dev(rng.random((n, n)), torch.float32)
+    r = dev(W.dirichlet_marginal(n, 11))
+    c = dev(W.dirichlet_marginal(n, 12))
+    prm = M.default_params(precision="f32")
+    u_a = torch.empty(n, dtype=torch.float64, device="cuda")
+    v_a = torch.empty_like(u_a)
+    ra = ctx.solve(M.dense_cost(Cd), r, c, 1e-4, prm, u_a, v_a)
+    print(f"alone n={n}: status={ra.status} gap={ra.gap:.3e} sweeps={ra.sweeps}", flush=True)
+    assert ra.status == 0 and ra.gap <= 1e-4
+    eng = M.Context(0)
+    try:
+        u_b = torch.empty_like(u_a)
+        v_b = torch.empty_like(u_a)
+        t = eng.submit(M.dense_cost(Cd), r, c, 1e-4, prm, u_b, v_b)
+        assert t is not None
+        for _ in range(100000):
+            if eng.inflight()[0] == 0:
+                break
+            eng.run(64)
+        rb = eng.poll(t)
+        assert rb is not None
+        assert torch.equal(u_a, u_b) and torch.equal(v_a, v_b)
+        for f in ("status", "primal_cost", "dual_bound", "gap", "gamma_final", "stages", "pncg_iters", "sweeps"):
+            assert getattr(rb, f) == getattr(ra, f), f
+    finally:
+        eng.close()
+
+
 def test_engine_past_256_row_tiles_bitwise_equals_solve(ctx):
     # Past 256 row tiles (m > 16384) the finalize folds each entry's partials in its general
     # path; in the engine the batched finalize serves that problem beside one whose entries take
