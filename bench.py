@@ -24,7 +24,9 @@ The default run (no workload flags) adds, beside the headline, the rest of the m
   legs.projectors        PNCG against the Sinkhorn projector (Alg. 4) at fixed gamma_f on the
                          L1 problems: LSE sweeps per solve
   legs.serving           a short continuous-batching run (--leg-requests requests, Poisson
-                         arrivals at 0.7 x saturation, HBM admission budget --hbm-budget)
+                         arrivals at 0.7 x saturation, HBM admission budget --hbm-budget);
+                         tail_request: the slowest request, its latency against its own
+                         solve time alone
 --no-legs reports the headline alone.
 
 Other workloads (not the default line):
@@ -511,7 +513,7 @@ def run_legs(args, head: dict) -> dict:
     srv = bench_serving(a)
     legs["serving"] = {k: srv[k] for k in ("value", "unit", "saturation_rps", "latency_p50_s", "latency_p99_s",
                                            "latency_max_s", "all_certified", "sample_bitwise_equal_to_alone",
-                                           "hbm_budget_bytes", "peak_bytes_in_use")}
+                                           "hbm_budget_bytes", "peak_bytes_in_use", "tail_request")}
     legs["serving"]["workload"] = srv["config"]["workload"]
     print(f"legs: serving done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     fp32 = head["value"]
@@ -592,6 +594,19 @@ def bench_serving(args) -> dict:
         u, v = torch.empty_like(q.u), torch.empty_like(q.v)
         r1 = ctx.solve(M.point_cost(q.XY, q.n, 3, "sqeuclid"), q.rd, q.cd, q.target, prm, u, v)
         same &= bool(torch.equal(u, q.u) and torch.equal(v, q.v) and r1.primal_cost == res[i].primal_cost)
+    # the slowest request solved alone: its latency over its own solve time is the slowdown that
+    # sharing the GPU with the requests in flight cost it
+    i_max = max(range(len(reqs)), key=lambda i: lat[i])
+    q = reqs[i_max]
+    u, v = torch.empty_like(q.u), torch.empty_like(q.v)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r1 = ctx.solve(M.point_cost(q.XY, q.n, 3, "sqeuclid"), q.rd, q.cd, q.target, prm, u, v)
+    torch.cuda.synchronize()
+    alone_s = time.perf_counter() - t1
+    same &= bool(torch.equal(u, q.u) and torch.equal(v, q.v) and r1.primal_cost == res[i_max].primal_cost)
+    tail = {"n": q.n, "target_gap": q.target, "sweeps": int(r1.sweeps), "latency_s": round(lat[i_max], 4),
+            "alone_s": round(alone_s, 4), "slowdown": round(lat[i_max] / alone_s, 2)}
     ctx.close()
     lat_s = sorted(lat)
     return {
@@ -614,6 +629,7 @@ def bench_serving(args) -> dict:
         "latency_max_s": round(lat_s[-1], 4),
         "all_certified": all(r.status == 0 and r.gap <= reqs[i].target for i, r in enumerate(res)),
         "sample_bitwise_equal_to_alone": same,
+        "tail_request": tail,
     }
 
 
