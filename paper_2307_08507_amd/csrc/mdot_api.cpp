@@ -339,10 +339,12 @@ static int bind_work(mdot_ctx* ctx, ProblemBufs& pb, int m, int n, const mdot_co
     w.n = n;
     w.nrt = tiles_r(m);
     w.nct = tiles_c(n);
-    w.fin_L = fin_lanes(m, n);
+    w.fin_Lr = fin_lanes_r(m, n);
+    w.fin_L = fin_lanes_c(m, n);
     w.fin_per = fin_per(m, n);
-    w.fin_lgL = 0;
+    while ((1 << w.fin_lgLr) < w.fin_Lr) ++w.fin_lgLr;
     while ((1 << w.fin_lgL) < w.fin_L) ++w.fin_lgL;
+    w.fin_nvbr = fin_vblocks_r(m, n);
     w.fin_nvb = fin_vblocks(m, n);
     w.fin_nblk = fin_grid(m, n);
     w.cost_kind = cost ? cost->kind : MDOT_COST_DENSE;

@@ -17,27 +17,44 @@ constexpr int kVecWG = 256;
 
 // Finalize kernel geometry: the tile partials of each entry of the (m + n)-vectors (rows, then
 // columns) are combined by a group of L lanes (a power of two, at most 64) that each fold up to
-// fin_per(m, n) of them; the groups fill fin_vblocks(m, n) virtual workgroups, run on
-// fin_grid(m, n) workgroups. Depends on the sizes only, so the summation order of every entry is
-// fixed by them. Past 8192 rows or columns each lane takes 32 partials, so that the groups fit in
-// kFinMaxGrid workgroups without a second round (n = 16384: L = 8, 1024 workgroups; with 8 per
-// lane it would be L = 32 and four rounds). Past 256 row tiles (more than 16384 rows) the
-// groups have kFinLanesLarge lanes, each folding its share of the partials in batches of 32
-// loads: the 8 entries of a wave then read 8 consecutive partials of each row tile, so a load
-// instruction touches 8 cache lines instead of one line per lane (L = 64 at 1561 row tiles).
+// fin_per(m, n) of them. Rows and columns have their own L: a row combines one partial per column
+// tile, a column one per row tile (4 times as many on a square problem), so a row needs fewer
+// lanes. The row groups fill the first fin_vblocks_r(m, n) virtual workgroups, the column groups
+// the rest, fin_vblocks(m, n) in all, run on fin_grid(m, n) workgroups. Depends on the sizes
+// only, so the summation order of every entry is fixed by them. Past 8192 rows or columns each
+// lane takes 32 partials, so that the groups fit in kFinMaxGrid workgroups without a second round
+// (n = 16384: 2 lanes per row, 8 per column, 640 workgroups; with 8 per lane it would be 32 lanes
+// per column and several rounds). Past 256 row tiles (more than 16384 rows) the column groups
+// have kFinLanesLarge lanes, each folding its share of the partials in batches of 32 loads: the 8
+// entries of a wave then read 8 consecutive partials of each row tile, so a load instruction
+// touches 8 cache lines instead of one line per lane (L = 64 at 1561 row tiles); the row groups
+// there take as many lanes as 32 partials each need, at most kFinLanesLarge.
 constexpr int kFinMaxGrid = 1024;
 constexpr int kFinLanesLarge = 8;
 constexpr int fin_per(int m, int n) { return (m > n ? m : n) > 8192 ? 32 : 8; }
-constexpr int fin_lanes(int m, int n)
+// the fewest lanes (a power of two, at most 64) that fold q partials at `per` each
+constexpr int fin_lanes_for(int q, int per)
 {
-    const int nrt = (m + kBR - 1) / kBR, nct = (n + kBC - 1) / kBC;
-    if (nrt > 256) return kFinLanesLarge;
-    const int q = nrt > nct ? nrt : nct;
     int L = 1;
-    while (L < 64 && L * fin_per(m, n) < q) L <<= 1;
+    while (L < 64 && L * per < q) L <<= 1;
     return L;
 }
-constexpr int fin_vblocks(int m, int n) { return ((m + n) * fin_lanes(m, n) + kVecWG - 1) / kVecWG; }
+constexpr int fin_large(int m) { return (m + kBR - 1) / kBR > 256; }
+constexpr int fin_lanes_r(int m, int n)
+{
+    const int nct = (n + kBC - 1) / kBC;
+    if (fin_large(m)) {
+        const int L = fin_lanes_for(nct, 32);
+        return L < kFinLanesLarge ? L : kFinLanesLarge;
+    }
+    return fin_lanes_for(nct, fin_per(m, n));
+}
+constexpr int fin_lanes_c(int m, int n)
+{
+    return fin_large(m) ? kFinLanesLarge : fin_lanes_for((m + kBR - 1) / kBR, fin_per(m, n));
+}
+constexpr int fin_vblocks_r(int m, int n) { return (m * fin_lanes_r(m, n) + kVecWG - 1) / kVecWG; }
+constexpr int fin_vblocks(int m, int n) { return fin_vblocks_r(m, n) + (n * fin_lanes_c(m, n) + kVecWG - 1) / kVecWG; }
 constexpr int fin_grid(int m, int n) { return fin_vblocks(m, n) < kFinMaxGrid ? fin_vblocks(m, n) : kFinMaxGrid; }
 
 // What the next sweep does.
@@ -125,7 +142,8 @@ struct State {
 struct Work {
     int32_t m, n, nrt, nct;  // rows (sources, r), columns (targets, c), row tiles, column tiles
     int32_t cost_kind, dtype, d, fin_per;  // cost kind and dtype, point dimension, fin_per(m, n)
-    int32_t fin_L, fin_lgL, fin_nvb, fin_nblk;  // fin_lanes(m, n), log2 of it, fin_vblocks(m, n), fin_grid(m, n)
+    int32_t fin_Lr, fin_lgLr, fin_nvbr;  // fin_lanes_r(m, n), log2 of it, fin_vblocks_r(m, n)
+    int32_t fin_L, fin_lgL, fin_nvb, fin_nblk;  // fin_lanes_c(m, n), log2 of it, fin_vblocks(m, n), fin_grid(m, n)
     // launch variant from the tuning table (neither changes any arithmetic): occ2 = 1 runs the
     // sweep instance capped at 2 waves per SIMD (256 VGPRs) instead of 4 (128 VGPRs); FP32 sweeps
     // of more than stage_min_tiles tiles stage their second row batch in LDS

@@ -1817,13 +1817,13 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     asm volatile("" ::: "memory");
     const int tid = threadIdx.x;
     const int m = wl.m, n = wl.n;
-    const int L = wl.fin_L;
-    const int lgL = wl.fin_lgL;
-    const int l = tid & (L - 1);
     const bool active = (done == 0) & (mode != SM_NONE);
     const bool e64 = exp64 != 0;
     const int per = wl.fin_per;
-    const bool fast = active & (mode == SM_LSE) & (wl.nrt <= 256) & (wl.nrt <= per * L) & (wl.nct <= per * L);
+    // the fast path: LSE entries whose partials take one load per slot, with the factor table
+    // of at most 256 row tiles
+    const bool lse = active & (mode == SM_LSE) & (wl.nrt <= 256);
+    const bool fast_r = lse & (wl.nct <= per * wl.fin_Lr), fast_c = lse & (wl.nrt <= per * wl.fin_L);
     double v[kNDot];
 #pragma unroll
     for (int d = 0; d < kNDot; ++d) v[d] = 0.0;
@@ -1831,18 +1831,22 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
     // exp(S_I - M) of the column partials, formed once per workgroup (instead of once per entry
     // and partial: 2 x 10^8 FP64 exps per sweep at n = 10^5)
     double M = 0.0;
-    if (!fast && active && (mode == SM_LSE || mode == SM_R1)) {
+    if (!(fast_r && fast_c) && active && (mode == SM_LSE || mode == SM_R1)) {
         double mx = -INFINITY;
         for (int I = tid & 63; I < wl.nrt; I += 64) mx = fmax(mx, wl.tshift[I]);
         M = wave_max(mx);
         for (int I = tid; I < wl.nrt; I += kVecWG) sh.fac[I] = exp(wl.tshift[I] - M);
         __syncthreads();
     }
-    const int nvb = wl.fin_nvb;
+    const int nvb = wl.fin_nvb, nvbr = wl.fin_nvbr;
     for (int vb = blk; vb < nvb; vb += nblk) {
-        const int k = (vb * kVecWG + tid) >> lgL;
-        const bool valid = k < m + n;
-        if (fast) {
+        // virtual workgroups [0, nvbr) hold the row groups, the rest the column groups
+        const bool rseg = vb < nvbr;
+        const int L = rseg ? wl.fin_Lr : wl.fin_L;
+        const int l = tid & (L - 1);
+        const int k = rseg ? (vb * kVecWG + tid) >> wl.fin_lgLr : m + (((vb - nvbr) * kVecWG + tid) >> wl.fin_lgL);
+        const bool valid = k < (rseg ? m : m + n);
+        if (rseg ? fast_r : fast_c) {
             if (!BIG || per == 8) fin_lse_entry<8>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
             else fin_lse_entry<32>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
             continue;
@@ -1864,8 +1868,8 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2. With `xcd`,
 // physical workgroup b takes the place of workgroup (b % 8) (G / 8) + b / 8 (8 divides the grid
 // G): runs of consecutive virtual workgroups then run on one XCD at about the same time. With 16
-// or more lanes per entry, a virtual workgroup holds 16 or fewer entries, and the partials of
-// consecutive entries share cache lines, which each XCD then fetches once instead of once per
+// or more lanes per column entry, a virtual workgroup holds 16 or fewer columns, and the partials
+// of consecutive columns share cache lines, which each XCD then fetches once instead of once per
 // workgroup. Everything a workgroup computes and stores depends on its virtual index alone.
 template <bool BIG>
 __global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int parity, int xcd)

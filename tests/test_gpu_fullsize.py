@@ -321,7 +321,7 @@ def test_solve_large_n_points_recertified_by_oracle(ctx):
 
 
 def test_engine_equals_solve_with_xcd_finalize_order(ctx):
-    # n = 5120: 16 lanes per finalize entry and 640 finalize workgroups, so a solve alone runs
+    # n = 5120: 16 lanes per column entry and 400 finalize workgroups, so a solve alone runs
     # its finalize in the XCD-aware workgroup order; the batched finalize does not. Everything a
     # workgroup computes depends on its virtual index only, so the two must agree bit for bit.
     n = 5120
