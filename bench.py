@@ -30,6 +30,9 @@ The default run (no workload flags) adds, beside the headline, the rest of the m
 --no-legs reports the headline alone.
 
 Other workloads (not the default line):
+  --problems 64          the full grid problem set: 8 marginal pairs of each family and cost
+                         (reports mean, median, p90 and max time to gap over the problems)
+  --family F             draw marginals from family F only (repeatable)
   --grid 128             n = 16384 on a 128 x 128 grid (the cost is 1 GiB in FP32)
   --cost-storage S       f32 (default), f16, bf16 (stored dense cost) or points (the cost is
                          recomputed in registers from FP32 grid coordinates, in FP64)
@@ -74,18 +77,30 @@ COSTS = ("sqeuclid", "l1")
 BYTES = {"f32": 4, "f16": 2, "bf16": 2, "f64": 8}
 
 
-def build_problems(k: int, count: int):
+def build_problems(k: int, count: int, families=FAMILIES):
+    """Up to 8 marginal pairs per (family, cost): pair j of family fi and cost ci draws r and c with
+    seeds 1000 (fi + 1) + 10 ci + 100 j and that + 1. Pairs are taken j-major, so the first
+    len(families) x 2 problems are pair 0 of every (family, cost), and count = 64 over all four
+    families is the full grid problem set."""
     from paper_2307_08507_amd import workloads as W
 
     probs = []
-    for fi, fam in enumerate(FAMILIES):
-        for ci, cost in enumerate(COSTS):
-            if len(probs) < count:
-                seed = 1000 * (fi + 1) + 10 * ci
-                probs.append({"family": fam, "cost": cost, "seed": seed,
-                              "r": W.grid_problem_marginals(k, fam, seed),
-                              "c": W.grid_problem_marginals(k, fam, seed + 1)})
+    for j in range(8):
+        for fi, fam in enumerate(FAMILIES):
+            if fam not in families:
+                continue
+            for ci, cost in enumerate(COSTS):
+                if len(probs) < count:
+                    seed = 1000 * (fi + 1) + 10 * ci + 100 * j
+                    probs.append({"family": fam, "cost": cost, "seed": seed,
+                                  "name": f"{fam}/{cost}" + (f"#{j}" if j else ""),
+                                  "r": W.grid_problem_marginals(k, fam, seed),
+                                  "c": W.grid_problem_marginals(k, fam, seed + 1)})
     return probs
+
+
+def problem_set(args):
+    return build_problems(args.grid, args.problems, tuple(args.family) if args.family else FAMILIES)
 
 
 def grid_cost_device(k: int, kind: str, storage: str, dev):
@@ -210,7 +225,7 @@ def bench_grid(args) -> dict:
     del ref
     k = args.grid
     n = k * k
-    probs = build_problems(k, args.problems)
+    probs = problem_set(args)
     costs = {kind: grid_cost_device(k, kind, args.cost_storage, dev) for kind in {p["cost"] for p in probs}}
     for p in probs:
         p["rd"] = torch.tensor(p["r"], dtype=torch.float64, device=dev)
@@ -250,7 +265,7 @@ def bench_grid(args) -> dict:
             exact = grid_cost_device(k, kind, "f64", dev)["keep"]
             delta[kind] = float((cd["keep"].double() - exact).abs().max())
             del exact
-        error_vs_exact = [{"problem": f"{probs[i % len(probs)]['family']}/{probs[i % len(probs)]['cost']}",
+        error_vs_exact = [{"problem": probs[i % len(probs)]["name"],
                            "certified_gap_stored_cost": res.gap, "delta": delta[probs[i % len(probs)]["cost"]],
                            "error_bound_exact_cost": res.gap + 2.0 * delta[probs[i % len(probs)]["cost"]]}
                           for i, res in enumerate(results)]
@@ -294,10 +309,11 @@ def bench_grid(args) -> dict:
             "problems": len(probs),
             "cost_storage": args.cost_storage,
         },
-        "time_to_gap_per_problem_s": {f"{p['family']}/{p['cost']}": round(statistics.mean(t), 6)
+        "time_to_gap_per_problem_s": {p["name"]: round(statistics.mean(t), 6)
                                       for p, t in zip(probs, per_prob) if t},
-        "time_to_gap_median_s": round(statistics.median(step_times), 6),
-        "time_to_gap_max_s": round(max(step_times), 6),
+        "time_to_gap_median_s": round(statistics.median(prob_means), 6),
+        "time_to_gap_p90_s": round(sorted(prob_means)[min(len(prob_means) - 1, int(0.9 * len(prob_means)))], 6),
+        "time_to_gap_max_s": round(max(prob_means), 6),
         "certified_gap_max": max(r.gap for r in results),
         "all_certified": all(r.status == 0 and r.gap <= args.target for r in results),
         "sweeps_mean": statistics.mean(r.sweeps for r in results),
@@ -353,7 +369,7 @@ def bench_grid_batched(args) -> dict:
     dev = torch.device("cuda", 0)
     k = args.grid
     n = k * k
-    probs = build_problems(k, args.problems)
+    probs = problem_set(args)
     costs = {kind: grid_cost_device(k, kind, args.cost_storage, dev) for kind in {p["cost"] for p in probs}}
     for p in probs:
         p["rd"] = torch.tensor(p["r"], dtype=torch.float64, device=dev)
@@ -440,7 +456,7 @@ def leg_single(args, precision: str, problems=None, target=None, **kw) -> dict:
     dev = torch.device("cuda", 0)
     k = args.grid
     n = k * k
-    probs = build_problems(k, args.problems)
+    probs = problem_set(args)
     if problems is not None:
         probs = [probs[i] for i in problems]
     costs = {kind: grid_cost_device(k, kind, args.cost_storage, dev) for kind in {p["cost"] for p in probs}}
@@ -464,7 +480,7 @@ def leg_single(args, precision: str, problems=None, target=None, **kw) -> dict:
     return {"time_to_gap_s": round(statistics.mean(t for t, _ in out), 6),
             "all_certified": all(r.status == 0 and (kw.get("gamma_f") or r.gap <= tg) for _, r in out),
             "sweeps_mean": statistics.mean(r.sweeps for _, r in out),
-            "per_problem": [{"problem": f"{p['family']}/{p['cost']}", "s": round(t, 5), "sweeps": r.sweeps,
+            "per_problem": [{"problem": p["name"], "s": round(t, 5), "sweeps": r.sweeps,
                              "gap": r.gap, "status": r.status} for p, (t, r) in zip(probs, out)]}
 
 
@@ -475,7 +491,7 @@ def leg_projectors(args) -> dict:
     import argparse as _ap
 
     a = _ap.Namespace(**vars(args))
-    l1 = [i for i, p in enumerate(build_problems(args.grid, args.problems)) if p["cost"] == "l1"]
+    l1 = [i for i, p in enumerate(problem_set(args)) if p["cost"] == "l1"]
     out = {}
     for gf in (2.0**9, 2.0**12):
         pn = leg_single(a, "f32", problems=l1, gamma_f=gf)
@@ -640,7 +656,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--target", type=float, default=1e-6)
     ap.add_argument("--grid", type=int, default=64, help="grid side k (n = k*k)")
-    ap.add_argument("--problems", type=int, default=8, help="problems cycled through (at most 8)")
+    ap.add_argument("--problems", type=int, default=8,
+                    help="problems cycled through: pair 0 of every (family, cost) first; 64 = the full set")
+    ap.add_argument("--family", action="append", choices=FAMILIES,
+                    help="grid workload: marginal families to draw from (repeatable; default all four)")
     ap.add_argument("--precision", default="f32", choices=("f32", "f64", "mixed"))
     ap.add_argument("--cost-storage", default="f32", choices=("f32", "f16", "bf16", "f64", "points"))
     ap.add_argument("--workload", default="grid", choices=("grid", "serving"))
