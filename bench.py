@@ -33,6 +33,9 @@ Other workloads (not the default line):
   --problems 64          the full grid problem set: 8 marginal pairs of each family and cost
                          (reports mean, median, p90 and max time to gap over the problems)
   --family F             draw marginals from family F only (repeatable)
+  --workload precision   every grid problem in each precision mode (FP64 on the exact cost as the
+                         reference, FP32, FP16/BF16 storage, recomputed point cost, MIXED): per
+                         result the relative UB difference, gap, marginal error and gamma_final
   --grid 128             n = 16384 on a 128 x 128 grid (the cost is 1 GiB in FP32)
   --cost-storage S       f32 (default), f16, bf16 (stored dense cost) or points (the cost is
                          recomputed in registers from FP32 grid coordinates, in FP64)
@@ -649,6 +652,83 @@ def bench_serving(args) -> dict:
     }
 
 
+def bench_precision(args) -> dict:
+    """Per-result accuracy of every precision mode on the grid problems: each problem is solved
+    with FP64 exponentials on the exact FP64 cost (the reference: the paper's precision), then in
+    each other mode. Per result: |UB - UB_ref| / UB_ref, the certified gap, the marginal error and
+    gamma_final; for FP16/BF16 storage also delta = max |C_stored - C_exact| and the bound
+    gap + 2 delta on the exact problem (the gap there is certified on the stored cost)."""
+    import torch
+
+    from paper_2307_08507_amd import mdot as M
+
+    dev = torch.device("cuda", 0)
+    k = args.grid
+    n = k * k
+    probs = problem_set(args)
+    for p in probs:
+        p["rd"] = torch.tensor(p["r"], dtype=torch.float64, device=dev)
+        p["cd"] = torch.tensor(p["c"], dtype=torch.float64, device=dev)
+    ctx = M.Context(0)
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+    v = torch.empty_like(u)
+    modes = [("f64_exact_cost", "f64", "f64"), ("f32", "f32", "f32"), ("f16_storage", "f32", "f16"),
+             ("bf16_storage", "f32", "bf16"), ("recompute_points", "f32", "points"), ("mixed", "mixed", "f32")]
+    exact = {kind: grid_cost_device(k, kind, "f64", dev)["keep"] for kind in COSTS}
+    ref, ref_gap, out = {}, {}, {}
+    for name, prec, storage in modes:
+        costs = {kind: grid_cost_device(k, kind, storage, dev) for kind in COSTS}
+        delta = {kind: (float((costs[kind]["keep"].double() - exact[kind]).abs().max())
+                        if storage in ("f16", "bf16") else 0.0) for kind in COSTS}
+        prm = M.default_params(precision=prec)
+        rows = []
+        for p in probs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.solve(costs[p["cost"]]["desc"](), p["rd"], p["cd"], args.target, prm, u, v)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if name == "f64_exact_cost":
+                ref[p["name"]], ref_gap[p["name"]] = res.primal_cost, res.gap
+            row = {"problem": p["name"], "s": round(dt, 5), "status": res.status, "ub": res.primal_cost,
+                   "rel_ub_vs_ref": abs(res.primal_cost - ref[p["name"]]) / ref[p["name"]], "gap": res.gap,
+                   "marg_err_l1": res.marg_err_l1, "gamma_final": res.gamma_final, "sweeps": res.sweeps}
+            if storage in ("f16", "bf16"):
+                row["delta"] = delta[p["cost"]]
+                row["error_bound_exact_cost"] = res.gap + 2.0 * delta[p["cost"]]
+            # both UBs lie within their certified gaps of their own problems' optima, which differ
+            # by at most delta: |UB - UB_ref| <= gap + gap_ref + 2 delta
+            row["ub_diff_over_bound"] = abs(res.primal_cost - ref[p["name"]]) / max(
+                res.gap + ref_gap[p["name"]] + 2.0 * row.get("delta", 0.0), 1e-300)
+            rows.append(row)
+        out[name] = {
+            "precision": prec, "cost_storage": storage,
+            "all_certified": all(r["status"] == 0 and r["gap"] <= args.target for r in rows),
+            "max_rel_ub_vs_ref": max(r["rel_ub_vs_ref"] for r in rows),
+            "max_ub_diff_over_bound": max(r["ub_diff_over_bound"] for r in rows),
+            "max_gap": max(r["gap"] for r in rows),
+            "max_marg_err_l1": max(r["marg_err_l1"] for r in rows),
+            "gamma_final_range": [min(r["gamma_final"] for r in rows), max(r["gamma_final"] for r in rows)],
+            "time_to_gap_mean_s": round(statistics.mean(r["s"] for r in rows), 6),
+            "per_problem": rows,
+        }
+        if storage in ("f16", "bf16"):
+            out[name]["max_error_bound_exact_cost"] = max(r["error_bound_exact_cost"] for r in rows)
+        del costs
+        print(f"precision mode {name} done", file=sys.stderr, flush=True)
+    ctx.close()
+    return {
+        "metric": f"per-result accuracy of the precision modes at gap {args.target:g}, n={n}",
+        "value": out["f32"]["max_rel_ub_vs_ref"],
+        "unit": "relative UB difference against FP64 on the exact cost (FP32 mode, max over problems)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "data": "synthetic",
+        "config": {"workload": f"n={n} ({k}x{k} grid), {len(probs)} problems, certified gap {args.target:g}"},
+        "modes": out,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -662,7 +742,7 @@ def main() -> int:
                     help="grid workload: marginal families to draw from (repeatable; default all four)")
     ap.add_argument("--precision", default="f32", choices=("f32", "f64", "mixed"))
     ap.add_argument("--cost-storage", default="f32", choices=("f32", "f16", "bf16", "f64", "points"))
-    ap.add_argument("--workload", default="grid", choices=("grid", "serving"))
+    ap.add_argument("--workload", default="grid", choices=("grid", "serving", "precision"))
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--load", type=float, default=0.7, help="arrival rate as a fraction of saturation")
     ap.add_argument("--seed", type=int, default=7)
@@ -682,6 +762,8 @@ def main() -> int:
         return 2
     if args.workload == "serving":
         out = bench_serving(args)
+    elif args.workload == "precision":
+        out = bench_precision(args)
     elif args.batched:
         out = bench_grid_batched(args)
     else:
