@@ -8,12 +8,12 @@
 //             single read of C (row sums reduced across the wave64 through an LDS transpose,
 //             column sums across the four waves). It writes per-tile partials only.
 //             The same kernel runs the two Round / certificate passes of a stage.
-//   k_fin   : a group of lanes per entry of the 2n-vectors: stores the vector update decided
+//   k_fin   : a group of lanes per entry of the (m + n)-vectors: stores the vector update decided
 //             by the previous step (accept a line-search step, start a stage with smoothing
 //             and warm start, prepare Round), combines the tile partials of its row or column
 //             in FP64 in a fixed order and reduces the dot products of the line search and of
 //             PNCG per workgroup.
-//   k_decide: one workgroup: reduces those dots in a fixed order and runs the scalar logic of
+//   k_decide: one wave: reduces those dots in a fixed order and runs the scalar logic of
 //             the line search (App. B), PNCG (Alg. 2) and the annealing loop (Alg. 1), then
 //             stores the next state. Kernel boundaries order the three; no atomics or fences.
 // The sweeps evaluate the pending vector update on the fly for their own rows and columns
@@ -410,7 +410,7 @@ __device__ __forceinline__ SweepArgs args_of(const State* S)
     return a;
 }
 
-// Entry k of the 2n-vectors (rows then columns) after the pending vector update:
+// Entry k of the (m + n)-vectors (rows then columns) after the pending vector update:
 //   accept : (u, v) += alpha p, log r(P) <- trial log-sums, p <- d + beta p or d (Alg. 2), with
 //            d the Sinkhorn direction s or (precond variant) the stored s~, restricted to the
 //            rows or the columns for the Sinkhorn projector's half-steps (Alg. 4)
@@ -1158,7 +1158,7 @@ __device__ __forceinline__ double group_fold(double v, int L)
 
 // Combine the tile partials of entry k (row k < n, column k - n otherwise) for `mode`. The LSE
 // fold keeps BL loads in flight per lane (the other modes 8). Called by every lane of the wave;
-// `valid` is false past the end of the 2n-vector.
+// `valid` is false past the end of the (m + n)-vector.
 template <int BL = 8>
 __device__ __forceinline__ Comb combine(const Work& w, int mode, int k, bool valid, int l, int L, const double* fac)
 {
@@ -1218,7 +1218,7 @@ __device__ __forceinline__ void lse_terms(const Work& w, const Entry& e, double 
     }
 }
 
-// Finalize entry k of the 2n-vector after a sweep from its combined partials and add this
+// Finalize entry k of the (m + n)-vector after a sweep from its combined partials and add this
 // entry's terms to the dots. M = max_I S_I (column entries of LSE and R1 sweeps).
 __device__ __forceinline__ void finalize_entry(const Work& w, const SweepArgs& a, const Entry& e, double g_cur, int k,
                                                int mode, bool e64, bool pre, const Comb& cb, double M,
@@ -1660,7 +1660,7 @@ k_sweep(const Work* __restrict__ wp, int parity)
 
 // ------------------------------------------------------------------ the finalize kernel
 // Reads state slot `parity` (the one this step's sweep used): stores the pending vector
-// update, combines the tile partials of every entry of the 2n-vectors and writes per-workgroup
+// update, combines the tile partials of every entry of the (m + n)-vectors and writes per-workgroup
 // dot products. The decide kernel that follows reduces them and writes the other slot.
 constexpr int kFacMax = (MDOT_MAX_N + kBR - 1) / kBR;  // row tiles at the largest n
 struct FinShared {
@@ -1794,9 +1794,10 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
     finalize_entry(w, a, e, g_cur, k, SM_LSE, e64, pre, cb, M, v);
 }
 
-// Finalize workgroup `blk` of the problem's `nblk` (= fin_grid(n)) workgroups. Entry k is
-// handled by an L-lane group (L = fin_lanes(n)); the groups are laid out in virtual blocks of
-// kVecWG / L entries, which the workgroups take in a grid-stride loop.
+// Finalize workgroup `blk` of the problem's `nblk` (= fin_grid(m, n)) workgroups. A row entry is
+// handled by a group of fin_Lr lanes, a column entry by one of fin_L lanes; the row groups fill
+// virtual blocks [0, fin_nvbr) of kVecWG / fin_Lr rows each, the column groups the rest, and the
+// workgroups take the virtual blocks in a grid-stride loop.
 // BIG: the instance that also handles n > 8192 (32 partials per lane in the fast path); it needs
 // more registers, so the smaller sizes run the other instance.
 template <bool BIG>
