@@ -134,11 +134,11 @@ struct mdot_ctx {
     // replaced batch graphs, destroyed once the last chunk launched from them has been read back
     std::vector<std::pair<hipGraphExec_t, int64_t>> graveyard;
     // what the batch graph was captured with: its sweep instances and their tile ranges, the
-    // finalize grid, and whether a problem has n > 8192
+    // finalize grid and finalize instance
     int bgraph_ncodes = 0, bgraph_code[kMaxCodes] = {}, bgraph_begin[kMaxCodes + 1] = {};
     int bgraph_fin = -1;
-    bool bgraph_big = false;
-    bool batch_big = false;
+    int bgraph_fin_v = -1;
+    int batch_fin_v = kFinSmall;  // the finalize instance the batch needs (fin_instance)
     // engine chunks in flight: the next chunk is launched before the previous one's done flags
     // are read; each remembers the slots and tickets it advanced, in descriptor order
     hipEvent_t eng_ev[2] = {nullptr, nullptr};
@@ -677,8 +677,8 @@ static int rebuild_batch(mdot_ctx* ctx)
     B.nitems = m;
     B.fin_prefix[m] = nf;
     B.total_fin = nf;
-    ctx->batch_big = false;
-    for (int a = 0; a < m; ++a) ctx->batch_big |= hw[a]->fin_per > 8;
+    ctx->batch_fin_v = kFinSmall;
+    for (int a = 0; a < m; ++a) ctx->batch_fin_v = std::max(ctx->batch_fin_v, fin_instance(hw[a]->fin_per, hw[a]->nrt));
     // sweep groups: items with the same cost data, size, point dimension, kind and dtype, in
     // order of first appearance; each needs one sweep kernel instance (planar for d <= 2 clouds)
     bool taken[kMaxBatch] = {};
@@ -749,8 +749,8 @@ static int ensure_batch_graph(mdot_ctx* ctx)
 {
     const BatchDesc& hb = *ctx->h_batch[ctx->hb_cur];
     const int fin = std::max(1, hb.total_fin);
-    const bool big = ctx->batch_big;
-    bool same = ctx->bgraph && ctx->bgraph_ncodes == hb.ncodes && ctx->bgraph_fin == fin && ctx->bgraph_big == big;
+    const int fin_v = ctx->batch_fin_v;
+    bool same = ctx->bgraph && ctx->bgraph_ncodes == hb.ncodes && ctx->bgraph_fin == fin && ctx->bgraph_fin_v == fin_v;
     for (int c = 0; same && c < hb.ncodes; ++c)
         same = ctx->bgraph_code[c] == hb.code[c] && ctx->bgraph_begin[c + 1] == hb.code_begin[c + 1];
     if (same) return MDOT_OK;
@@ -763,7 +763,7 @@ static int ensure_batch_graph(mdot_ctx* ctx)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(hb, ctx->d_batch, k & 1, fin, big, cap);
+        for (int k = 0; k < kBatchChunk; ++k) launch_step_batch(hb, ctx->d_batch, k & 1, fin, fin_v, cap);
         launch_gather_done(ctx->d_batch, ctx->d_hdone + 2, ctx->d_seq + 1, cap);
         e = hipStreamEndCapture(cap, &g);
     }
@@ -780,7 +780,7 @@ static int ensure_batch_graph(mdot_ctx* ctx)
         ctx->bgraph_begin[c + 1] = hb.code_begin[c + 1];
     }
     ctx->bgraph_fin = fin;
-    ctx->bgraph_big = big;
+    ctx->bgraph_fin_v = fin_v;
     return MDOT_OK;
 }
 

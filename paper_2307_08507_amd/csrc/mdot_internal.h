@@ -56,6 +56,12 @@ constexpr int fin_lanes_c(int m, int n)
 constexpr int fin_vblocks_r(int m, int n) { return (m * fin_lanes_r(m, n) + kVecWG - 1) / kVecWG; }
 constexpr int fin_vblocks(int m, int n) { return fin_vblocks_r(m, n) + (n * fin_lanes_c(m, n) + kVecWG - 1) / kVecWG; }
 constexpr int fin_grid(int m, int n) { return fin_vblocks(m, n) < kFinMaxGrid ? fin_vblocks(m, n) : kFinMaxGrid; }
+// Finalize kernel instances, each with the registers its sizes need: kFinSmall for at most 8192
+// rows and columns (fin_per = 8), kFinMid for larger problems of at most 256 row tiles, kFinAll
+// for any size. A batch takes the largest instance one of its problems needs; every instance
+// computes the same bits for the sizes it takes.
+constexpr int kFinSmall = 0, kFinMid = 1, kFinAll = 2;
+constexpr int fin_instance(int fin_per, int nrt) { return fin_per == 8 ? kFinSmall : (nrt <= 256 ? kFinMid : kFinAll); }
 
 // What the next sweep does.
 enum SweepMode : int32_t { SM_NONE = 0, SM_LSE = 1, SM_R1 = 2, SM_R2 = 3, SM_MAX = 4 };
@@ -286,8 +292,8 @@ int cost_code_dim(int cost_code, int d);
 // The sweep kernel instance a launch of hw takes (its cost code, planar for d <= 2, plus kOccHi
 // for the 2-waves-per-SIMD variant).
 int cost_code(const Work& hw);
-// big: some problem in flight has m or n > 8192 (the finalize instance for fin_per = 32)
-int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, bool big, void* stream);
+// fin_v: the finalize instance (fin_instance) the largest problem in flight needs
+int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, int fin_v, void* stream);
 // End-of-chunk done flags into host-visible memory: chunk number *seq (a device counter, advanced
 // here) writes out[(seq & 1) * kMaxBatch + item] (batch) or out[seq & 1] (single problem).
 int launch_gather_done(const BatchDesc* bd, int* out, int* seq, void* stream);

@@ -1749,10 +1749,11 @@ __device__ __forceinline__ double store_update(const Work& w, const SweepArgs& a
     return g_cur;
 }
 
-// LSE finalize of one entry group when every partial fits one load per slot (m <= 8 L) and
-// nrt <= 256: all loads of the group (tile shifts, partials, entry inputs) are issued before
-// any arithmetic.
-template <int PER>
+// LSE finalize of one entry group when every partial fits one load per slot (at most PER per
+// lane) and nrt <= 256: all loads of the group (tile shifts, partials, and unless LATE the entry
+// inputs) are issued before any arithmetic. LATE loads the entry inputs after the fold, in the
+// group's lane 0 only, which keeps them out of the registers the partials occupy.
+template <int PER, bool LATE = false>
 __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a, int k, bool valid, int l, int L,
                                               bool e64, bool pre, double v[kNDot], double* sfac, bool first)
 {
@@ -1771,7 +1772,8 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
         const int I = min(l + u * L, np - 1);
         x[u] = base[(size_t)I * st];
     }
-    const EntryIn in = entry_load(w, a, kc);
+    EntryIn in{};
+    if constexpr (!LATE) in = entry_load(w, a, kc);
     // M = max_I S_I, the same value in every lane
     const double M = wave_max(fmax(fmax(ts[0], ts[1]), fmax(ts[2], ts[3])));
     // the column partials' factors exp(S_I - M) depend on I alone: thread I of the workgroup
@@ -1789,6 +1791,7 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
     Comb cb{};
     cb.a = group_fold<0>(acc, L);
     if (!valid || l != 0) return;
+    if constexpr (LATE) in = entry_load(w, a, kc);
     const Entry e = entry_from(in, a, m, n, k);
     const double g_cur = store_update(w, a, e, in.g, k);
     finalize_entry(w, a, e, g_cur, k, SM_LSE, e64, pre, cb, M, v);
@@ -1798,9 +1801,12 @@ __device__ __forceinline__ void fin_lse_entry(const Work& w, const SweepArgs& a,
 // handled by a group of fin_Lr lanes, a column entry by one of fin_L lanes; the row groups fill
 // virtual blocks [0, fin_nvbr) of kVecWG / fin_Lr rows each, the column groups the rest, and the
 // workgroups take the virtual blocks in a grid-stride loop.
-// BIG: the instance that also handles n > 8192 (32 partials per lane in the fast path); it needs
-// more registers, so the smaller sizes run the other instance.
-template <bool BIG>
+// Instances (V, fin_instance):
+//   kFinSmall: at most 8192 rows and columns (8 partials per lane in the fast path);
+//   kFinMid:   more, with at most 256 row tiles (32 partials per lane in the fast path, the entry
+//              inputs loaded after the fold); capped at 256 VGPRs, two waves per SIMD;
+//   kFinAll:   any size (past 256 row tiles the general path folds in batches of 32 loads).
+template <int V>
 __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int nblk, FinShared& sh)
 {
     // Every control read (the Work fields and the state) is issued before the first branch,
@@ -1848,16 +1854,16 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
         const int k = rseg ? (vb * kVecWG + tid) >> wl.fin_lgLr : m + (((vb - nvbr) * kVecWG + tid) >> wl.fin_lgL);
         const bool valid = k < (rseg ? m : m + n);
         if (rseg ? fast_r : fast_c) {
-            if (!BIG || per == 8) fin_lse_entry<8>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
-            else fin_lse_entry<32>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
+            if (V == kFinSmall || per == 8) fin_lse_entry<8>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
+            else fin_lse_entry<32, V == kFinMid>(wl, a, k, valid, l, L, e64, pre, v, sh.fac, vb == blk);
             continue;
         }
         const int kc = valid ? k : 0;
         const EntryIn in = entry_load(wl, a, kc);
         Comb cb{};
-        // past 256 row tiles (the BIG instance only) an LSE entry folds its partials in batches of
-        // 32 loads: 8 lanes share some hundreds of partials there
-        if (active) cb = combine<BIG ? 32 : 8>(wl, mode, k, valid, l, L, sh.fac);
+        // past 256 row tiles (the kFinAll instance only) an LSE entry folds its partials in
+        // batches of 32 loads: 8 lanes share some hundreds of partials there
+        if (active) cb = combine<V == kFinAll ? 32 : 8>(wl, mode, k, valid, l, L, sh.fac);
         if (!valid || l != 0) continue;
         const Entry e = entry_from(in, a, m, n, k);
         const double g_cur = store_update(wl, a, e, in.g, k);
@@ -1872,12 +1878,12 @@ __device__ __forceinline__ void fin_body(const Work& w, int parity, int blk, int
 // or more lanes per column entry, a virtual workgroup holds 16 or fewer columns, and the partials
 // of consecutive columns share cache lines, which each XCD then fetches once instead of once per
 // workgroup. Everything a workgroup computes and stores depends on its virtual index alone.
-template <bool BIG>
-__global__ void __launch_bounds__(kVecWG) k_fin(const Work* __restrict__ wp, int parity, int xcd)
+template <int V>
+__global__ void __launch_bounds__(kVecWG, V == kFinMid ? 2 : 1) k_fin(const Work* __restrict__ wp, int parity, int xcd)
 {
     __shared__ FinShared sh;
     const int G = gridDim.x, b = blockIdx.x;
-    fin_body<BIG>(*wp, parity, xcd ? (b & 7) * (G >> 3) + (b >> 3) : b, G, sh);
+    fin_body<V>(*wp, parity, xcd ? (b & 7) * (G >> 3) + (b >> 3) : b, G, sh);
 }
 
 // ------------------------------------------------------------------ the decide kernel
@@ -1978,14 +1984,14 @@ k_sweep_batch(const BatchDesc* __restrict__ bd, int parity, int tile_begin, int 
 }
 
 // Batched finalize: one workgroup per finalize block of every problem in flight.
-template <bool BIG>
-__global__ void __launch_bounds__(kVecWG) k_fin_batch(const BatchDesc* __restrict__ bd, int parity)
+template <int V>
+__global__ void __launch_bounds__(kVecWG, V == kFinMid ? 2 : 1) k_fin_batch(const BatchDesc* __restrict__ bd, int parity)
 {
     __shared__ FinShared sh;
     const int g = blockIdx.x;
     if (g >= bd->total_fin) return;
     const int b = batch_item(bd->fin_prefix, bd->nitems, g);
-    fin_body<BIG>(*bd->items[b], parity, g - bd->fin_prefix[b], bd->fin_prefix[b + 1] - bd->fin_prefix[b], sh);
+    fin_body<V>(*bd->items[b], parity, g - bd->fin_prefix[b], bd->fin_prefix[b + 1] - bd->fin_prefix[b], sh);
 }
 
 __global__ void __launch_bounds__(kDecideWG) k_decide_batch(const BatchDesc* __restrict__ bd, int parity)
@@ -2239,8 +2245,10 @@ int launch_step(const Work& hw, const Work* wd, int parity, void* stream)
     MDOT_CC_SWITCH(cost_code(hw), L_)
 #undef L_
     const int xcd = hw.fin_L >= 16 && hw.fin_nblk % 8 == 0;
-    if (hw.fin_per > 8) hipLaunchKernelGGL(k_fin<true>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity, xcd);
-    else hipLaunchKernelGGL(k_fin<false>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity, xcd);
+    const int fv = fin_instance(hw.fin_per, hw.nrt);
+    if (fv == kFinSmall) hipLaunchKernelGGL(k_fin<kFinSmall>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity, xcd);
+    else if (fv == kFinMid) hipLaunchKernelGGL(k_fin<kFinMid>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity, xcd);
+    else hipLaunchKernelGGL(k_fin<kFinAll>, dim3(hw.fin_nblk), dim3(kVecWG), 0, s, wd, parity, xcd);
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideWG), 0, s, wd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -2254,7 +2262,7 @@ int launch_sweep(const Work& hw, const Work* wd, int parity, void* stream)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, bool big, void* stream)
+int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int fin_grid, int fin_v, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
     for (int c = 0; c < hb.ncodes; ++c) {
@@ -2264,8 +2272,9 @@ int launch_step_batch(const BatchDesc& hb, const BatchDesc* bd, int parity, int 
         MDOT_CC_SWITCH(hb.code[c], L_)
 #undef L_
     }
-    if (big) hipLaunchKernelGGL(k_fin_batch<true>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
-    else hipLaunchKernelGGL(k_fin_batch<false>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
+    if (fin_v == kFinSmall) hipLaunchKernelGGL(k_fin_batch<kFinSmall>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
+    else if (fin_v == kFinMid) hipLaunchKernelGGL(k_fin_batch<kFinMid>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
+    else hipLaunchKernelGGL(k_fin_batch<kFinAll>, dim3(fin_grid), dim3(kVecWG), 0, s, bd, parity);
     hipLaunchKernelGGL(k_decide_batch, dim3(kMaxBatch), dim3(kDecideWG), 0, s, bd, parity);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -354,14 +354,17 @@ def test_engine_equals_solve_with_xcd_finalize_order(ctx):
         eng.close()
 
 
-def test_engine_past_256_row_tiles_bitwise_equals_solve(ctx):
+@pytest.mark.parametrize("sizes", [((20000, 83), (9000, 84)), ((9000, 85), (12000, 86))])
+def test_engine_past_256_row_tiles_bitwise_equals_solve(ctx, sizes):
     # Past 256 row tiles (m > 16384) the finalize folds each entry's partials in its general
     # path; in the engine the batched finalize serves that problem beside one whose entries take
-    # the 32-partial fast path. The engine must return each problem's solve-alone result bit for
-    # bit. n = 20000 (313 row tiles) beside n = 9000 (141 row tiles).
+    # the 32-partial fast path. n = 20000 (313 row tiles) beside n = 9000 (141 row tiles): the
+    # batch runs the finalize instance for any size, while n = 9000 alone runs the one for at
+    # most 256 row tiles. n = 9000 beside n = 12000: the batch runs that instance too. The engine
+    # must return each problem's solve-alone result bit for bit.
     prm = M.default_params(precision="f32")
     probs = []
-    for n, seed in [(20000, 83), (9000, 84)]:
+    for n, seed in sizes:
         X, Y, r, c = _points_problem(n, seed)
         probs.append((n, dev(np.concatenate([X, Y]).ravel(), torch.float32), dev(r), dev(c)))
     alone = []
