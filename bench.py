@@ -27,6 +27,8 @@ The default run (no workload flags) adds, beside the headline, the rest of the m
                          arrivals at 0.7 x saturation, HBM admission budget --hbm-budget);
                          tail_request: the slowest request, its latency against its own
                          solve time alone
+  legs.precision_modes   the 8 problems in every precision mode against FP64 on the exact
+                         cost (as --workload precision, summarised per mode)
 --no-legs reports the headline alone.
 
 Other workloads (not the default line):
@@ -509,7 +511,8 @@ def leg_projectors(args) -> dict:
 
 def run_legs(args, head: dict) -> dict:
     """The rest of the metric beside the headline: FP64 and MIXED single solves, the batched
-    engine (FP32 and MIXED), PNCG against the Sinkhorn projector, and a short serving run."""
+    engine (FP32 and MIXED), PNCG against the Sinkhorn projector, a short serving run, and the
+    per-result accuracy of every precision mode."""
     import argparse as _ap
 
     legs = {}
@@ -535,6 +538,11 @@ def run_legs(args, head: dict) -> dict:
                                            "hbm_budget_bytes", "peak_bytes_in_use", "tail_request")}
     legs["serving"]["workload"] = srv["config"]["workload"]
     print(f"legs: serving done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    prec = bench_precision(_ap.Namespace(**vars(args)))
+    legs["precision_modes"] = {name: {k: m[k] for k in ("all_certified", "max_ub_diff_over_bound", "max_rel_ub_vs_ref",
+                                                         "max_gap", "max_marg_err_l1", "time_to_gap_mean_s")}
+                               for name, m in prec["modes"].items()}
+    print(f"legs: precision modes done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     fp32 = head["value"]
     legs["summary"] = {
         "fp32_single_s": fp32,
